@@ -1,0 +1,479 @@
+"""Plain CPU FP64 oracle for one block-eigensolver step of plane-wave DFT.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the bench may import this module.  It shares no code with
+the HIP library: it takes the seeded inputs (atom positions, perturbation
+modes, starting blocks) as plain arrays and computes everything else itself,
+in float64 / complex128, with numpy and scipy primitives.
+
+What it computes, and where the paper fixes it:
+
+* The problem is the eigenproblem H X = X Lambda of the plane-wave
+  Hamiltonian (Section II-A, Eq. 1); X are plane-wave coefficients and the
+  wanted output is the lowest part of the spectrum.
+* The cutoff E_cut selects the plane waves (Section II-A): a reciprocal
+  lattice vector G is kept iff |G|^2 / 2 <= E_cut (Gamma point).
+* The inner solver is an iterative block eigensolver (Section II-A) whose
+  subspace part forms S = Psi^* (H Psi) and solves a dense Hermitian
+  eigenproblem ("Syevd", Sections II-B and III-D).
+* The pseudopotential acts atom by atom on every wavefunction
+  (Section III-A); here as Kleinman-Bylander projectors B D B^H.
+
+Where the paper is silent the readings are: a Chebyshev-filtered subspace
+step (degree m; m = 0 is plain Rayleigh-Ritz), an alias-free FFT grid, a
+potential band-limited to the wavefunction sphere, real spherical harmonics,
+structure factors exp(-i G.tau), and the unnormalised inverse FFT
+psi(r) = sum_G c_G exp(+i G.r).
+
+Every function below is pinned by tests in tests/test_oracle_pins.py.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional, Sequence, Tuple
+
+import numpy as np
+import scipy.fft
+import scipy.linalg
+
+TWO_PI = 2.0 * math.pi
+
+
+# ----------------------------------------------------------------------------
+# Basis and grid (Section II-A: E_cut fixes the basis and the real-space grid)
+# ----------------------------------------------------------------------------
+
+def sphere_millers(L: Sequence[float], ecut: float) -> np.ndarray:
+    """All Miller triples n with |G|^2/2 <= ecut, G = 2 pi n / L, sorted n1, n2, n3."""
+    L = np.asarray(L, float)
+    nmax = [int(math.floor(math.sqrt(2.0 * ecut) * L[i] / TWO_PI)) for i in range(3)]
+    r = [np.arange(-nmax[i], nmax[i] + 1) for i in range(3)]
+    n1, n2, n3 = np.meshgrid(r[0], r[1], r[2], indexing="ij")
+    n = np.stack([n1.ravel(), n2.ravel(), n3.ravel()], axis=1)
+    g2 = ((TWO_PI * n / L) ** 2).sum(axis=1)
+    return n[0.5 * g2 <= ecut].astype(np.int64)
+
+
+def gvectors(miller: np.ndarray, L: Sequence[float]) -> np.ndarray:
+    """Cartesian G = 2 pi (n1/L1, n2/L2, n3/L3)."""
+    return TWO_PI * np.asarray(miller, float) / np.asarray(L, float)
+
+
+def paper_grid(L: Sequence[float], ecut: float) -> Tuple[int, ...]:
+    """The paper's grid rule (Section II-A): N_i = sqrt(2 E_cut) L_i / pi,
+
+    rounded up to the next size whose prime factors are all <= 7 (a common
+    FFT size set; the paper does not state its rounding).  Used only to check
+    Table I; the oracle itself uses the alias-free grid of fft_grid().
+    """
+    out = []
+    for Li in L:
+        x = math.sqrt(2.0 * ecut) * Li / math.pi
+        n = int(math.ceil(x - 1e-9))
+        while True:
+            m = n
+            for p in (2, 3, 5, 7):
+                while m % p == 0:
+                    m //= p
+            if m == 1:
+                break
+            n += 1
+        out.append(n)
+    return tuple(out)
+
+
+def fft_grid(L: Sequence[float], ecut: float) -> Tuple[int, int, int]:
+    """Alias-free grid: N_i = smallest 2^p 3^q >= 3 floor(n_max,i) + 1.
+
+    A product V(r) psi(r) with both factors band-limited to |n_i| <= n_max
+    has components up to 2 n_max; projecting back on the sphere is exact iff
+    N_i > 3 n_max.
+    """
+    out = []
+    for Li in L:
+        nmax = int(math.floor(math.sqrt(2.0 * ecut) * Li / TWO_PI))
+        need = 3 * nmax + 1
+        best = None
+        p2 = 1
+        while p2 < 4 * need:
+            p3 = p2
+            while p3 < 4 * need:
+                if p3 >= need and (best is None or p3 < best):
+                    best = p3
+                p3 *= 3
+            p2 *= 2
+        out.append(best)
+    return tuple(out)
+
+
+# ----------------------------------------------------------------------------
+# Potential and projectors (analytic synthetic pseudopotential)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Model:
+    """Everything H needs, built once from a cell description."""
+
+    L: np.ndarray
+    ecut: float
+    tau: np.ndarray
+    miller: np.ndarray  # (npw, 3)
+    G: np.ndarray  # (npw, 3)
+    kin: np.ndarray  # (npw,)   |G|^2/2
+    grid: Tuple[int, int, int]
+    vr: np.ndarray  # real-space local potential on the grid, indexed [j1, j2, j3]
+    B: np.ndarray  # (npw, 4*natoms) projector matrix
+    D: np.ndarray  # (4*natoms,) KB energies
+    zval: float
+    rc: float
+    gauss_c: float
+    mode_miller: np.ndarray
+    mode_amp: np.ndarray
+    mode_phase: np.ndarray
+    sf_sign: float = -1.0
+
+    @property
+    def npw(self) -> int:
+        return self.miller.shape[0]
+
+    @property
+    def omega(self) -> float:
+        return float(np.prod(self.L))
+
+
+def local_potential_g(miller: np.ndarray, L: np.ndarray, ecut: float, tau: np.ndarray,
+                      zval: float, rc: float, gauss_c: float, mode_miller: np.ndarray,
+                      mode_amp: np.ndarray, mode_phase: np.ndarray,
+                      sf_sign: float = -1.0) -> np.ndarray:
+    """V(G) for arbitrary Miller triples.
+
+    V(G) = S(G) v(|G|) + dV(G) for 0 < |G|^2/2 <= ecut, and 0 otherwise, with
+      v(G) = (1/Omega) (-4 pi Z exp(-G^2 rc^2/4) / G^2 + c exp(-G^2 rc^2/4)),
+      S(G) = sum_a exp(sf_sign * i G.tau_a),
+      dV(+-G_k) = (amp_k/2) exp(+-i phase_k)  (from amp cos(G_k.r + phase_k)).
+    """
+    miller = np.asarray(miller, np.int64)
+    G = gvectors(miller, L)
+    g2 = (G * G).sum(axis=1)
+    omega = float(np.prod(L))
+    inside = (g2 > 0) & (0.5 * g2 <= ecut)
+    out = np.zeros(miller.shape[0], complex)
+    if np.any(inside):
+        gi = G[inside]
+        g2i = g2[inside]
+        gauss = np.exp(-g2i * rc * rc / 4.0)
+        v = (-4.0 * math.pi * zval * gauss / g2i + gauss_c * gauss) / omega
+        phase = gi @ np.asarray(tau, float).T  # (n, natoms)
+        sf = np.exp(sf_sign * 1j * phase).sum(axis=1)
+        out[inside] = sf * v
+    for k in range(mode_miller.shape[0]):
+        mk = mode_miller[k]
+        plus = np.all(miller == mk, axis=1) & inside
+        minus = np.all(miller == -mk, axis=1) & inside
+        out[plus] += 0.5 * mode_amp[k] * np.exp(1j * mode_phase[k])
+        out[minus] += 0.5 * mode_amp[k] * np.exp(-1j * mode_phase[k])
+    return out
+
+
+def real_harmonics_l01(G: np.ndarray) -> np.ndarray:
+    """Real spherical harmonics Y_00, Y_1x, Y_1y, Y_1z of the direction of G.
+
+    Y_00 = 1/(2 sqrt(pi)); Y_1a = sqrt(3/(4 pi)) G_a/|G|; Y_1a(0) = 0.
+    """
+    g = np.sqrt((G * G).sum(axis=1))
+    out = np.zeros((G.shape[0], 4))
+    out[:, 0] = 0.5 / math.sqrt(math.pi)
+    nz = g > 0
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    for a in range(3):
+        out[nz, 1 + a] = c1 * G[nz, a] / g[nz]
+    return out
+
+
+def projector_matrix(miller: np.ndarray, L: np.ndarray, tau: np.ndarray, sigma: float,
+                     sf_sign: float = -1.0) -> np.ndarray:
+    """B[G, 4a+m] = (c/sqrt(Omega)) exp(-sigma^2 |G|^2/2) Y_m(G) exp(sf_sign i G.tau_a).
+
+    c = sqrt(32 pi^(5/2) sigma^3) gives unit norm in the continuum limit.
+    Projector order per atom: l=0, then l=1 x, y, z.
+    """
+    G = gvectors(miller, L)
+    g2 = (G * G).sum(axis=1)
+    omega = float(np.prod(L))
+    c = math.sqrt(32.0 * math.pi ** 2.5 * sigma ** 3)
+    radial = (c / math.sqrt(omega)) * np.exp(-0.5 * sigma * sigma * g2)
+    ylm = real_harmonics_l01(G)
+    natoms = tau.shape[0]
+    B = np.empty((G.shape[0], 4 * natoms), complex)
+    for a in range(natoms):
+        sf = np.exp(sf_sign * 1j * (G @ tau[a]))
+        for m in range(4):
+            B[:, 4 * a + m] = radial * ylm[:, m] * sf
+    return B
+
+
+def scatter_to_grid(x: np.ndarray, miller: np.ndarray, grid: Sequence[int]) -> np.ndarray:
+    """Place sphere coefficients on the FFT grid at n mod N (columns of x = bands)."""
+    N = tuple(grid)
+    idx = tuple(np.mod(miller[:, i], N[i]) for i in range(3))
+    if x.ndim == 1:
+        out = np.zeros(N, complex)
+        out[idx] = x
+        return out
+    out = np.zeros(N + (x.shape[1],), complex)
+    out[idx] = x
+    return out
+
+
+def gather_from_grid(f: np.ndarray, miller: np.ndarray) -> np.ndarray:
+    N = f.shape[:3]
+    idx = tuple(np.mod(miller[:, i], N[i]) for i in range(3))
+    return f[idx]
+
+
+def to_real_space(c: np.ndarray, miller: np.ndarray, grid: Sequence[int]) -> np.ndarray:
+    """psi(r_j) = sum_G c_G exp(+i G.r_j): unnormalised inverse DFT."""
+    f = scatter_to_grid(c, miller, grid)
+    return scipy.fft.ifftn(f, axes=(0, 1, 2), norm="forward")
+
+
+def to_g_space(f: np.ndarray, miller: np.ndarray) -> np.ndarray:
+    """c_G = (1/N_r) sum_j f(r_j) exp(-i G.r_j), gathered on the sphere."""
+    F = scipy.fft.fftn(f, axes=(0, 1, 2), norm="forward")
+    return gather_from_grid(F, miller)
+
+
+def build_model(L: Sequence[float], tau: np.ndarray, ecut: float, zval: float = 4.0,
+                rc: float = 1.0, gauss_c: float = 2.0, sigma: float = 0.8, d0: float = 1.5,
+                d1: float = -0.7, mode_miller: Optional[np.ndarray] = None,
+                mode_amp: Optional[np.ndarray] = None, mode_phase: Optional[np.ndarray] = None,
+                grid: Optional[Sequence[int]] = None, sf_sign: float = -1.0) -> Model:
+    L = np.asarray(L, float)
+    tau = np.asarray(tau, float)
+    mm = np.zeros((0, 3), np.int64) if mode_miller is None else np.asarray(mode_miller, np.int64)
+    ma = np.zeros(0) if mode_amp is None else np.asarray(mode_amp, float)
+    mp = np.zeros(0) if mode_phase is None else np.asarray(mode_phase, float)
+    miller = sphere_millers(L, ecut)
+    G = gvectors(miller, L)
+    kin = 0.5 * (G * G).sum(axis=1)
+    grid = tuple(fft_grid(L, ecut)) if grid is None else tuple(grid)
+    vg = local_potential_g(miller, L, ecut, tau, zval, rc, gauss_c, mm, ma, mp, sf_sign)
+    vr_c = to_real_space(vg, miller, grid)
+    scale = max(1.0, float(np.abs(vr_c).max()))
+    assert float(np.abs(vr_c.imag).max()) <= 1e-12 * scale, "V(r) must be real"
+    B = projector_matrix(miller, L, tau, sigma, sf_sign) if (d0 != 0 or d1 != 0) else \
+        np.zeros((miller.shape[0], 0), complex)
+    D = np.tile(np.array([d0, d1, d1, d1]), tau.shape[0]) if B.shape[1] else np.zeros(0)
+    return Model(L=L, ecut=ecut, tau=tau, miller=miller, G=G, kin=kin, grid=grid,
+                 vr=vr_c.real.copy(), B=B, D=D, zval=zval, rc=rc, gauss_c=gauss_c,
+                 mode_miller=mm, mode_amp=ma, mode_phase=mp, sf_sign=sf_sign)
+
+
+def model_from_cell(cell, **over) -> Model:
+    """Convenience: build from a synth.Cell-like object (duck-typed)."""
+    p = cell.pseudo
+    kw = dict(zval=p.zval, rc=p.rc, gauss_c=p.gauss_c, sigma=p.beta_sigma, d0=p.d0, d1=p.d1,
+              mode_miller=cell.modes.miller, mode_amp=cell.modes.amp,
+              mode_phase=cell.modes.phase)
+    kw.update(over)
+    return build_model(cell.L, cell.tau, cell.ecut, **kw)
+
+
+# ----------------------------------------------------------------------------
+# The Hamiltonian (Section II-A, Eq. 1)
+# ----------------------------------------------------------------------------
+
+def dense_h(model: Model) -> np.ndarray:
+    """H[G, G'] = delta ½|G|^2 + V(G - G') + sum_p B[G,p] D_p conj(B[G',p]).
+
+    V(G - G') is evaluated from the analytic formula (with the band limit),
+    not through an FFT.  Only for tiny cells (npw up to a few thousand).
+    """
+    m = model.miller
+    # Every difference n - n' lies in the box |d_i| <= 2 max|n_i|: tabulate V there.
+    span = 2 * np.abs(m).max(axis=0)
+    r = [np.arange(-span[i], span[i] + 1) for i in range(3)]
+    d1, d2, d3 = np.meshgrid(r[0], r[1], r[2], indexing="ij")
+    box = np.stack([d1.ravel(), d2.ravel(), d3.ravel()], axis=1)
+    vbox = local_potential_g(box, model.L, model.ecut, model.tau, model.zval, model.rc,
+                             model.gauss_c, model.mode_miller, model.mode_amp,
+                             model.mode_phase, model.sf_sign)
+    vbox = vbox.reshape(d1.shape)
+    i1 = m[:, None, 0] - m[None, :, 0] + span[0]
+    i2 = m[:, None, 1] - m[None, :, 1] + span[1]
+    i3 = m[:, None, 2] - m[None, :, 2] + span[2]
+    H = vbox[i1, i2, i3]
+    H = H + np.diag(model.kin)
+    if model.B.shape[1]:
+        H = H + (model.B * model.D) @ model.B.conj().T
+    return H
+
+
+def apply_h(model: Model, X: np.ndarray) -> np.ndarray:
+    """Matrix-free H X: kinetic + FFT local potential + B (D (B^H X))."""
+    X = np.asarray(X, complex)
+    one = X.ndim == 1
+    Xb = X[:, None] if one else X
+    out = model.kin[:, None] * Xb
+    psi = to_real_space(Xb, model.miller, model.grid)
+    out = out + to_g_space(model.vr[..., None] * psi, model.miller)
+    if model.B.shape[1]:
+        P = model.B.conj().T @ Xb
+        out = out + model.B @ (model.D[:, None] * P)
+    return out[:, 0] if one else out
+
+
+# ----------------------------------------------------------------------------
+# One step of the block eigensolver (Chebyshev-filtered subspace iteration)
+# ----------------------------------------------------------------------------
+
+def chebyshev_filter(hop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, m: int,
+                     a_lo: float, a: float, b: float) -> np.ndarray:
+    """Scaled degree-m Chebyshev filter that damps [a, b] and keeps values near a_lo.
+
+    With e = (b-a)/2, c = (b+a)/2, s_1 = e/(a_lo - c), tau = 2/s_1:
+      Y_1 = (s_1/e) (H - c) X,
+      s_{k+1} = 1/(tau - s_k),
+      Y_{k+1} = (2 s_{k+1}/e) (H - c) Y_k - s_k s_{k+1} Y_{k-1},  Y_0 = X.
+    Result: T_m((H - c)/e) X / T_m((a_lo - c)/e).
+    """
+    if m == 0:
+        return X.copy()
+    e = 0.5 * (b - a)
+    c = 0.5 * (b + a)
+    s1 = e / (a_lo - c)
+    tau = 2.0 / s1
+    y_prev = X
+    y = (hop(X) - c * X) * (s1 / e)
+    s = s1
+    for _ in range(1, m):
+        s_new = 1.0 / (tau - s)
+        y_new = (2.0 * s_new / e) * (hop(y) - c * y) - (s * s_new) * y_prev
+        y_prev, y = y, y_new
+        s = s_new
+    return y
+
+
+@dataclasses.dataclass
+class StepResult:
+    eig: np.ndarray
+    X: np.ndarray
+    HX: np.ndarray
+    resid: np.ndarray
+    a_lo: float
+    a: float
+
+
+def rayleigh_ritz(Y: np.ndarray, W: np.ndarray):
+    """Generalised Rayleigh-Ritz on span(Y) with W = H Y (Sections II-B, III-D).
+
+    S = Y^H Y, H_s = Y^H W (both symmetrised), S = L L^H, L^-1 H_s L^-H = Q diag(lam) Q^H,
+    C = L^-H Q.  Raises numpy.linalg.LinAlgError if S is not positive definite.
+    """
+    S = Y.conj().T @ Y
+    Hs = Y.conj().T @ W
+    S = 0.5 * (S + S.conj().T)
+    Hs = 0.5 * (Hs + Hs.conj().T)
+    Lc = np.linalg.cholesky(S)
+    T = scipy.linalg.solve_triangular(Lc, Hs, lower=True)
+    Hh = scipy.linalg.solve_triangular(Lc, T.conj().T, lower=True)
+    Hh = 0.5 * (Hh + Hh.conj().T)
+    lam, Q = np.linalg.eigh(Hh)
+    C = scipy.linalg.solve_triangular(Lc.conj().T, Q, lower=False)
+    return lam, C
+
+
+def eig_step(hop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, m: int, a_lo: float,
+             a: float, b: float) -> StepResult:
+    """One block-eigensolver step: filter, W = H Y, Rayleigh-Ritz, rotate, residuals."""
+    Y = chebyshev_filter(hop, X, m, a_lo, a, b)
+    W = hop(Y)
+    lam, C = rayleigh_ritz(Y, W)
+    Xn = Y @ C
+    Wn = W @ C
+    R = Wn - Xn * lam[None, :]
+    resid = np.sqrt((np.abs(R) ** 2).sum(axis=0))
+    return StepResult(eig=lam, X=Xn, HX=Wn, resid=resid, a_lo=float(lam[0]), a=float(lam[-1]))
+
+
+def lanczos_max(hop: Callable[[np.ndarray], np.ndarray], npw: int, steps: int = 20,
+                seed: int = 7) -> float:
+    """Largest Ritz value of a `steps`-step Lanczos run from a seeded random vector."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.standard_normal(npw) + 1j * rng.standard_normal(npw)
+    v /= np.linalg.norm(v)
+    v_prev = np.zeros_like(v)
+    alpha, beta = [], []
+    bprev = 0.0
+    for _ in range(min(steps, npw)):
+        w = hop(v) - bprev * v_prev
+        al = float(np.vdot(v, w).real)
+        w = w - al * v
+        bt = float(np.linalg.norm(w))
+        alpha.append(al)
+        beta.append(bt)
+        if bt < 1e-14:
+            break
+        v_prev, v, bprev = v, w / bt, bt
+    k = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[: k - 1], 1) + np.diag(beta[: k - 1], -1)
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[-1] + beta[k - 1])
+
+
+@dataclasses.dataclass
+class SolveResult:
+    eig: np.ndarray
+    X: np.ndarray
+    resid: np.ndarray
+    steps: int
+    converged: bool
+
+
+def solve(hop: Callable[[np.ndarray], np.ndarray], X0: np.ndarray, b: float, nocc: int,
+          tol: float = 1e-7, m: int = 10, max_steps: int = 200) -> SolveResult:
+    """Iterate steps: first m = 0 (bounds), then degree m until max resid over nocc <= tol."""
+    st = eig_step(hop, X0, 0, 0.0, 0.0, b)
+    steps = 1
+    while True:
+        if float(st.resid[:nocc].max()) <= tol:
+            return SolveResult(st.eig, st.X, st.resid, steps, True)
+        if steps >= max_steps:
+            return SolveResult(st.eig, st.X, st.resid, steps, False)
+        st = eig_step(hop, st.X, m, st.a_lo, st.a, b)
+        steps += 1
+
+
+# ----------------------------------------------------------------------------
+# Comparison helpers (degenerate clusters; several answers are correct)
+# ----------------------------------------------------------------------------
+
+def clusters(eig: np.ndarray, gap: float = 1e-3):
+    """Split sorted eigenvalues into runs whose consecutive gaps are < gap."""
+    out = []
+    start = 0
+    for i in range(1, len(eig) + 1):
+        if i == len(eig) or eig[i] - eig[i - 1] >= gap:
+            out.append((start, i))
+            start = i
+    return out
+
+
+def subspace_sin(Xref: np.ndarray, X: np.ndarray) -> float:
+    """sin of the largest principal angle between span(Xref) and span(X)."""
+    Qr, _ = np.linalg.qr(Xref)
+    Qx, _ = np.linalg.qr(X)
+    R = Qx - Qr @ (Qr.conj().T @ Qx)
+    return float(np.linalg.norm(R, 2))
+
+
+def chebyshev_t(m: int, x: np.ndarray) -> np.ndarray:
+    """T_m(x) by its trigonometric / hyperbolic closed form."""
+    x = np.asarray(x, float)
+    out = np.empty_like(x)
+    inside = np.abs(x) <= 1
+    out[inside] = np.cos(m * np.arccos(x[inside]))
+    xo = x[~inside]
+    out[~inside] = np.cosh(m * np.arccosh(np.abs(xo))) * np.sign(xo) ** m
+    return out
