@@ -1,0 +1,171 @@
+/*
+ * pw.h -- C ABI of the MI355X plane-wave block-eigensolver step.
+ *
+ * The library applies the plane-wave Kohn-Sham Hamiltonian H of a periodic
+ * cell to blocks of wavefunctions and performs one step of an iterative block
+ * eigensolver for the lowest eigenpairs of H X = X Lambda (paper Section II-A,
+ * Eq. 1), at a fixed effective potential.  One step is: a degree-m Chebyshev
+ * filter of the block (each degree is one H application), W = H Y, the Gram
+ * and projected matrices S = Y^H Y and H_s = Y^H W (Section II-B, S = Psi^*(H Psi)),
+ * the FP64 dense generalised eigensolve of (H_s, S) (Sections II-B and III-D,
+ * "Syevd"), the rotation X' = Y C and the residual norms ||H x_i - lambda_i x_i||.
+ *
+ * Units: Hartree atomic units (bohr, Ha).  Gamma point only; the basis is every
+ * reciprocal lattice vector G = 2 pi (n1/L1, n2/L2, n3/L3) with |G|^2/2 <= ecut
+ * (Section II-A: the cutoff energy selects the plane waves).
+ *
+ * Data layout.  Wavefunction blocks are column-major npw x nb complex arrays in
+ * device memory with leading dimension ld >= npw, one band per column, rows in
+ * the plane-wave order returned by pw_get_gvectors.  Element type: complex
+ * double (interleaved re, im) for PW_FP64, complex float for PW_MIXED.
+ *
+ * Ownership.  Host inputs are copied during the call.  All persistent device
+ * state lives in the caller's arena (pw_setup); the library never frees caller
+ * memory.  The dense eigensolver library used by pw_eig_step keeps its own
+ * small workspace.
+ *
+ * Streams.  Work is enqueued on the caller's HIP stream.  pw_apply_h returns
+ * without synchronising; pw_eig_step returns after its host outputs are written.
+ *
+ * Errors.  Every call returns a pw_status.  PW_EINVAL leaves no side effects.
+ * pw_last_error gives a text message for the last failing call on a handle.
+ * Handles are not thread safe; use one handle per host thread.
+ */
+#ifndef PW_H
+#define PW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PW_OK = 0,
+  PW_PENDING = 1,    /* serving: result not ready yet */
+  PW_EINVAL = -1,    /* invalid argument; nothing was done */
+  PW_ENOMEM = -2,    /* arena (or admission budget) too small */
+  PW_EDEVICE = -3,   /* HIP runtime / device error */
+  PW_ENOTPD = -4,    /* FP64 Cholesky of the Gram matrix failed (rank-deficient block) */
+  PW_ENUMERIC = -5,  /* non-finite value in the eigenvalues or residuals */
+  PW_ENOTCONV = -6,  /* serving: max_steps reached before tol */
+  PW_EBUSY = -7      /* serving: no free slot */
+} pw_status;
+
+/* Force the pencil form of the plane stage (three kernels through an HBM intermediate)
+   even when a whole FFT plane fits in LDS; for testing that path on small cells. */
+#define PW_FLAG_PENCIL_FFT 1u
+
+typedef enum {
+  PW_FP64 = 0,  /* every product and FFT in double precision */
+  PW_MIXED = 1  /* FP32 complex FFT / H application / GEMMs; FP64 Cholesky, eig, residuals */
+} pw_precision;
+
+/*
+ * Cell description (Section II-A; the synthetic analytic pseudopotential):
+ *   local part   V(G) = S(G) v(|G|) + dV(G) for 0 < |G|^2/2 <= ecut, V(0) = 0, with
+ *                v(G) = (1/Omega)(-4 pi zval e^{-G^2 rc^2/4}/G^2 + gauss_c e^{-G^2 rc^2/4}),
+ *                S(G) = sum_a e^{-i G.tau_a},
+ *                dV(r) = sum_k mode_amp[k] cos(G_k . r + mode_phase[k]), G_k from mode_miller;
+ *   nonlocal     V_NL = sum_a sum_m beta_{a,m} D_m beta_{a,m}^H (Section III-A: every
+ *                atom's pseudopotential acts on every wavefunction), 4 projectors per atom
+ *                (l = 0; l = 1 x, y, z), D = (d0, d1, d1, d1),
+ *                beta_{a,m}(G) = (c/sqrt(Omega)) e^{-beta_sigma^2 |G|^2/2} Y_m(G^) e^{-i G.tau_a},
+ *                c = sqrt(32 pi^{5/2} beta_sigma^3), real harmonics, Y_{1m}(0) = 0.
+ * Set d0 = d1 = 0 for a cell without projectors.
+ */
+typedef struct {
+  double L[3];               /* orthorhombic cell lengths (bohr) */
+  int natoms;                /* >= 0 */
+  const double *tau;         /* natoms * 3 Cartesian positions (bohr), host, copied */
+  double ecut;               /* plane-wave cutoff (Ha), > 0 */
+  int nbands;                /* largest block the handle will process (sizes the arena) */
+  double zval, rc, gauss_c;  /* local pseudopotential */
+  double beta_sigma, d0, d1; /* projectors */
+  int nmodes;                /* perturbation modes (0 for none) */
+  const int *mode_miller;    /* nmodes * 3, host, copied */
+  const double *mode_amp;    /* nmodes (Ha) */
+  const double *mode_phase;  /* nmodes (rad) */
+  int fft_n[3];              /* 0,0,0: alias-free rule N_i = min 2^p 3^q >= 3 floor(nmax_i) + 1;
+                                otherwise must satisfy that bound and be 2^p 3^q (else PW_EINVAL) */
+  int prec;                  /* pw_precision */
+  unsigned flags;            /* bitwise OR of PW_FLAG_* (0 = defaults) */
+} pw_cell_desc;
+
+typedef struct {
+  long long npw;              /* plane waves in the sphere */
+  long long nst;              /* sticks: distinct (n1, n2) columns of the sphere */
+  long long nr;               /* grid points N1 N2 N3 */
+  long long nproj;            /* 4 * natoms (0 without projectors) */
+  size_t footprint_bytes;     /* arena bytes pw_setup needs for this description */
+  int fft_n[3];
+  int nbands;
+  int prec;
+  int fused_planes;           /* 1 when each FFT plane is transformed inside LDS */
+} pw_info;
+
+typedef struct {
+  int degree;     /* Chebyshev degree m >= 0 (0 = plain Rayleigh-Ritz on the input block) */
+  double a_lo;    /* filter: value the filter normalises to 1 (lowest wanted eigenvalue estimate) */
+  double a, b;    /* filter: interval [a, b] to damp (b >= largest eigenvalue of H) */
+  int want_hx;    /* 1: write H X' to HX_dev */
+} pw_step_params;
+
+typedef struct pw_handle_s pw_handle;
+
+/* Sizes of a description, host only (no device needed).  PW_EINVAL for a bad description. */
+pw_status pw_plan(const pw_cell_desc *desc, pw_info *out);
+
+/* Miller indices of the basis of a description, host only: npw * 3 ints in stick order. */
+pw_status pw_plan_gvectors(const pw_cell_desc *desc, int *miller_host);
+
+/*
+ * Build a handle: plane-wave sphere (stick order: n1, then n2, then n3 ascending), grid,
+ * V(r) on the device (V(G) -> inverse FFT), projector table, work buffers.
+ * arena_dev: caller device memory of arena_bytes >= pw_plan(...).footprint_bytes
+ * (PW_ENOMEM otherwise).  hip_stream: a hipStream_t (NULL = default stream).
+ * Synchronises the stream before returning.
+ */
+pw_status pw_setup(const pw_cell_desc *desc, void *arena_dev, size_t arena_bytes, void *hip_stream,
+                   pw_handle **h);
+pw_status pw_query(const pw_handle *h, pw_info *out);
+/* Miller indices of the basis, npw * 3 ints in row order of every block (host buffer). */
+pw_status pw_get_gvectors(const pw_handle *h, int *miller_host);
+
+/*
+ * HX = H X for nb bands (1 <= nb <= nbands), device arrays with leading dimension ld >= npw
+ * (same ld for both).  X and HX must not overlap.  Asynchronous on the handle's stream.
+ */
+pw_status pw_apply_h(pw_handle *h, const void *X_dev, void *HX_dev, int nb, int ld);
+
+/*
+ * One block-eigensolver step on X (in/out, nb columns, ld >= npw):
+ *   Y = T_m((H - c)/e) X / T_m((a_lo - c)/e), e = (b - a)/2, c = (b + a)/2 (m = degree;
+ *       three-term recurrence, one H application per degree);
+ *   W = H Y; S = Y^H Y, H_s = Y^H W (Hermitian parts); S = L L^H (FP64 Cholesky);
+ *   L^-1 H_s L^-H = Q diag(lambda) Q^H (FP64, ascending); C = L^-H Q;
+ *   X <- Y C; resid_i = ||W C_i - lambda_i X_i||_2 (FP64 accumulation).
+ * eig_host, resid_host: nb doubles each (host).  bounds_out (may be NULL) receives
+ * {lambda_1, lambda_nb, b}: the a_lo and a of the next step, and the b used.
+ * HX_dev may be NULL unless want_hx.  PW_ENOTPD when the Cholesky fails (X unchanged
+ * content is not guaranteed), PW_ENUMERIC on a non-finite eigenvalue or residual.
+ * For degree > 0 the bounds must satisfy a_lo < a < b.
+ */
+pw_status pw_eig_step(pw_handle *h, void *X_dev, void *HX_dev, int nb, int ld, const pw_step_params *p,
+                      double *eig_host, double *resid_host, double bounds_out[3]);
+
+/*
+ * Upper bound estimate of the spectrum: 1.01 * (largest Ritz value + last off-diagonal) of a
+ * `steps`-step Lanczos run on H from a seeded random vector.  Host result.
+ */
+pw_status pw_spectrum_bound(pw_handle *h, int steps, unsigned long long seed, double *bmax);
+
+pw_status pw_destroy(pw_handle *h);
+const char *pw_last_error(const pw_handle *h);
+const char *pw_status_string(pw_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PW_H */

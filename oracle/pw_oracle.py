@@ -214,33 +214,39 @@ def projector_matrix(miller: np.ndarray, L: np.ndarray, tau: np.ndarray, sigma: 
 
 
 def scatter_to_grid(x: np.ndarray, miller: np.ndarray, grid: Sequence[int]) -> np.ndarray:
-    """Place sphere coefficients on the FFT grid at n mod N (columns of x = bands)."""
+    """Place sphere coefficients on the FFT grid at n mod N.
+
+    x of shape (npw,) gives a grid (N1, N2, N3); x of shape (npw, nb) gives (nb, N1, N2, N3).
+    """
     N = tuple(grid)
     idx = tuple(np.mod(miller[:, i], N[i]) for i in range(3))
     if x.ndim == 1:
         out = np.zeros(N, complex)
         out[idx] = x
         return out
-    out = np.zeros(N + (x.shape[1],), complex)
-    out[idx] = x
+    out = np.zeros((x.shape[1],) + N, complex)
+    out[(slice(None),) + idx] = x.T
     return out
 
 
 def gather_from_grid(f: np.ndarray, miller: np.ndarray) -> np.ndarray:
-    N = f.shape[:3]
+    """Inverse of scatter_to_grid: (N1, N2, N3) -> (npw,), (nb, N1, N2, N3) -> (npw, nb)."""
+    N = f.shape[-3:]
     idx = tuple(np.mod(miller[:, i], N[i]) for i in range(3))
-    return f[idx]
+    if f.ndim == 3:
+        return f[idx]
+    return f[(slice(None),) + idx].T
 
 
 def to_real_space(c: np.ndarray, miller: np.ndarray, grid: Sequence[int]) -> np.ndarray:
-    """psi(r_j) = sum_G c_G exp(+i G.r_j): unnormalised inverse DFT."""
+    """psi(r_j) = sum_G c_G exp(+i G.r_j): unnormalised inverse DFT (bands first for blocks)."""
     f = scatter_to_grid(c, miller, grid)
-    return scipy.fft.ifftn(f, axes=(0, 1, 2), norm="forward")
+    return scipy.fft.ifftn(f, axes=(-3, -2, -1), norm="forward", workers=-1)
 
 
 def to_g_space(f: np.ndarray, miller: np.ndarray) -> np.ndarray:
     """c_G = (1/N_r) sum_j f(r_j) exp(-i G.r_j), gathered on the sphere."""
-    F = scipy.fft.fftn(f, axes=(0, 1, 2), norm="forward")
+    F = scipy.fft.fftn(f, axes=(-3, -2, -1), norm="forward", workers=-1)
     return gather_from_grid(F, miller)
 
 
@@ -316,8 +322,10 @@ def apply_h(model: Model, X: np.ndarray) -> np.ndarray:
     one = X.ndim == 1
     Xb = X[:, None] if one else X
     out = model.kin[:, None] * Xb
-    psi = to_real_space(Xb, model.miller, model.grid)
-    out = out + to_g_space(model.vr[..., None] * psi, model.miller)
+    chunk = 16
+    for j in range(0, Xb.shape[1], chunk):
+        psi = to_real_space(Xb[:, j:j + chunk], model.miller, model.grid)
+        out[:, j:j + chunk] += to_g_space(model.vr[None] * psi, model.miller)
     if model.B.shape[1]:
         P = model.B.conj().T @ Xb
         out = out + model.B @ (model.D[:, None] * P)

@@ -1,0 +1,68 @@
+// Shared types and small device helpers for the plane-wave eigensolver library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pw {
+
+// Complex number types: interleaved (re, im) pairs.
+template <typename T> struct cvec;
+template <> struct cvec<float> { using type = float2; };
+template <> struct cvec<double> { using type = double2; };
+template <typename T> using cplx = typename cvec<T>::type;
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T x, T y) {
+  cplx<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// multiply by +i (s = +1) or -i (s = -1)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmuli(cplx<T> a, int s) {
+  return s > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+
+// One stick of the G sphere: all plane waves with Miller (n1, n2, n3), n3 in [-h, h],
+// stored contiguously from `off` (len = 2h + 1).
+struct Stick {
+  int off;
+  int len;
+  int n1;
+  int n2;
+};
+
+// Radix plan of one 1D FFT length (radices in order of application).
+struct FftPlan {
+  int n;
+  int nrad;
+  int rad[10];
+};
+
+// Geometry of the transform: the plane-wave sphere, its sticks and the grid.
+struct GridDesc {
+  int n1, n2, n3;     // grid
+  int nst;            // number of sticks
+  int npw;            // plane waves
+  int n1max;          // max |n1| over sticks; active x columns xa = n1 + n1max in [0, n1a)
+  int n1a;            // 2 * n1max + 1
+  FftPlan p1, p2, p3; // radix plans for the three axes
+};
+
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace pw

@@ -1,0 +1,597 @@
+// Handle, setup, H application, one block-eigensolver step and the C ABI.
+//
+// One step (pw_eig_step) follows the structure of the inner eigensolver of
+// Section II-A and the subspace products of Section II-B:
+//   filter:   Y = p_m(H) X with the scaled three-term Chebyshev recurrence,
+//             every degree one H application whose last GEMM writes the update
+//   project:  W = H Y; [S | H_s] = Y^H [Y | W] in one split-K GEMM
+//   solve:    FP64 Cholesky + generalised Hermitian eigensolve (rocSOLVER zhegvd),
+//             the one-device analogue of the ScaLAPACK Syevd of Section III-D
+//   rotate:   X' = Y C, W' = W C; residual norms ||W'_i - lambda_i X'_i||
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pw.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace pw;
+
+static thread_local std::string g_last_error;
+
+struct pw_handle_s {
+  Plan plan;
+  unsigned char* arena = nullptr;
+  size_t arena_bytes = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  int device = 0;
+  size_t max_lds = kDefaultMaxLds;
+  std::string err;
+  double bmax_cached = NAN;
+  template <typename X>
+  X* at(size_t off) const { return reinterpret_cast<X*>(arena + off); }
+};
+
+namespace {
+
+#define PW_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      h->err = std::string(#call) + ": " + hipGetErrorString(e_);                     \
+      return PW_EDEVICE;                                                              \
+    }                                                                                 \
+  } while (0)
+
+pw_status fail(pw_handle_s* h, pw_status s, const std::string& m) {
+  if (h) h->err = m;
+  g_last_error = m;
+  return s;
+}
+
+template <typename T>
+struct Engine {
+  pw_handle_s* h;
+  const Plan& P;
+  explicit Engine(pw_handle_s* hh) : h(hh), P(hh->plan) {}
+
+  cplx<T>* beta() const { return h->at<cplx<T>>(P.lay.beta); }
+  cplx<T>* u0() const { return h->at<cplx<T>>(P.lay.u0); }
+  cplx<T>* u1() const { return h->at<cplx<T>>(P.lay.u1); }
+  cplx<T>* zb() const { return h->at<cplx<T>>(P.lay.zb); }
+
+  // Local potential part: Z = P_sphere FFT_fwd[V FFT_inv[P_sphere^T Y]] for nb columns.
+  pw_status local_part(const cplx<T>* Y, long ldy, cplx<T>* Z, long ldz, int nb) {
+    const GridDesc& g = P.g;
+    const T scale = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
+    cplx<T>* SB = h->at<cplx<T>>(P.lay.sb);
+    cplx<T>* G1 = h->at<cplx<T>>(P.lay.g1);
+    const Stick* st = h->at<Stick>(P.lay.sticks);
+    const int* cs = h->at<int>(P.lay.colstart);
+    const T* V = h->at<T>(P.lay.vr);
+    const cplx<T>* tw1 = h->at<cplx<T>>(P.lay.tw1);
+    const cplx<T>* tw2 = h->at<cplx<T>>(P.lay.tw2);
+    const cplx<T>* tw3 = h->at<cplx<T>>(P.lay.tw3);
+    for (int b0 = 0; b0 < nb; b0 += P.fft_batch) {
+      const int nbt = std::min(P.fft_batch, nb - b0);
+      PW_HIP(launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, h->stream));
+      PW_HIP(launch_planes<T>(SB, G1, V, nbt, st, cs, g, tw1, tw2, scale, 0, nullptr, P.fl, h->stream));
+      PW_HIP(launch_sticks_fwd<T>(SB, Z + (long)b0 * ldz, ldz, nbt, st, g, tw3, P.fl, h->stream));
+    }
+    return PW_OK;
+  }
+
+  // out = alpha ((kin - c) Y + Zl + B D B^H Y) - beta Yp, where Zl is first filled with the
+  // local potential part.  Zl may equal out (apply_h); Yp may equal out (in-place update).
+  pw_status hop(const cplx<T>* Y, long ldy, int nb, cplx<T>* out, long ldo, cplx<T>* Zl, long ldz, double alpha,
+                double c, double beta_c, const cplx<T>* Yp, long ldp) {
+    pw_status s = local_part(Y, ldy, Zl, ldz, nb);
+    if (s != PW_OK) return s;
+    cplx<T>* PT = h->at<cplx<T>>(P.lay.pt);
+    if (P.nproj > 0) {
+      double2* parts = h->at<double2>(P.lay.parts);
+      PW_HIP(launch_gemm_cn<T>(beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw, P.nsplit_proj, parts,
+                               h->stream));
+      PW_HIP(launch_reduce_parts<T>(parts, P.nsplit_proj, P.nproj, nb, h->at<double>(P.lay.dscale), 4, nullptr, 0,
+                                    PT, P.nproj, h->stream));
+    }
+    EpiH e;
+    e.mode = 1;
+    e.alpha = alpha;
+    e.c = c;
+    e.beta = beta_c;
+    e.kin = h->at<T>(P.lay.kin);
+    e.Y = Y;
+    e.ldy = ldy;
+    e.Zl = Zl;
+    e.ldz = ldz;
+    e.Yp = Yp;
+    e.ldp = ldp;
+    PW_HIP(launch_gemm_nn<T>(beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e, h->stream));
+    return PW_OK;
+  }
+
+  pw_status apply_h(const cplx<T>* X, cplx<T>* HX, int nb, int ld) {
+    return hop(X, ld, nb, HX, ld, HX, ld, 1.0, 0.0, 0.0, nullptr, 0);
+  }
+
+  pw_status rotate(const cplx<T>* A, long lda, const cplx<T>* C, int nb, cplx<T>* out, long ldo) {
+    EpiH e;
+    std::memset(&e, 0, sizeof(e));
+    e.mode = 0;
+    PW_HIP(launch_gemm_nn<T>(A, lda, C, nb, P.npw, nb, nb, out, ldo, e, h->stream));
+    return PW_OK;
+  }
+
+  pw_status eig_step(cplx<T>* X, cplx<T>* HX, int nb, int ld, const pw_step_params& prm, double* eig_host,
+                     double* resid_host, double* bounds_out) {
+    const int m = prm.degree;
+    double bmax = prm.b;
+    const long ldw = P.ldw;
+    const cplx<T>* Y = X;
+    long ldy = ld;
+    cplx<T>* dead = u0();  // buffer free to receive W
+    pw_status s;
+    if (m >= 1) {
+      const double e = 0.5 * (prm.b - prm.a), c = 0.5 * (prm.b + prm.a);
+      const double s1 = e / (prm.a_lo - c), tau = 2.0 / s1;
+      s = hop(X, ld, nb, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0);
+      if (s != PW_OK) return s;
+      const cplx<T>* prev = X;
+      long ldprev = ld;
+      cplx<T>* cur = u1();
+      double sg = s1;
+      for (int k = 1; k < m; ++k) {
+        const double sn = 1.0 / (tau - sg);
+        cplx<T>* dst = (prev == X) ? u0() : const_cast<cplx<T>*>(prev);
+        s = hop(cur, ldw, nb, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev);
+        if (s != PW_OK) return s;
+        prev = cur;
+        ldprev = ldw;
+        cur = dst;
+        sg = sn;
+      }
+      Y = cur;
+      ldy = ldw;
+      dead = (prev == X) ? u0() : const_cast<cplx<T>*>(prev);
+    }
+    // W = H Y
+    cplx<T>* W = dead;
+    s = hop(Y, ldy, nb, W, ldw, zb(), ldw, 1.0, 0.0, 0.0, nullptr, 0);
+    if (s != PW_OK) return s;
+    // [S | H_s] = Y^H [Y | W]
+    double2* parts = h->at<double2>(P.lay.parts);
+    double2* SH = h->at<double2>(P.lay.sh);
+    PW_HIP(launch_gemm_cn<T>(Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram, parts, h->stream));
+    PW_HIP(launch_reduce_parts<T>(parts, P.nsplit_gram, nb, 2 * nb, nullptr, 0, SH, nb, (cplx<T>*)nullptr, 0,
+                                  h->stream));
+    double2* S = SH;
+    double2* Hs = SH + (size_t)nb * nb;
+    PW_HIP(launch_hermitize(S, nb, nb, h->stream));
+    PW_HIP(launch_hermitize(Hs, nb, nb, h->stream));
+    // FP64 generalised eigensolve: Hs C = S C diag(lambda), C^H S C = I
+    double* eig_d = h->at<double>(P.lay.eig);
+    int* info_d = h->at<int>(P.lay.info);
+    rocblas_status rs = rocsolver_zhegvd(h->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, nb,
+                                         reinterpret_cast<rocblas_double_complex*>(Hs), nb,
+                                         reinterpret_cast<rocblas_double_complex*>(S), nb, eig_d,
+                                         h->at<double>(P.lay.ework), info_d);
+    if (rs != rocblas_status_success)
+      return fail(h, PW_EDEVICE, std::string("rocsolver_zhegvd: ") + rocblas_status_to_string(rs));
+    int info = 0;
+    PW_HIP(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    PW_HIP(hipStreamSynchronize(h->stream));
+    if (info > nb) return fail(h, PW_ENOTPD, "Cholesky of the Gram matrix failed (rank-deficient block)");
+    if (info > 0) return fail(h, PW_ENUMERIC, "dense eigensolver did not converge");
+    // C in the compute precision
+    const cplx<T>* C;
+    if constexpr (sizeof(T) == 8) {
+      C = reinterpret_cast<const cplx<T>*>(Hs);
+    } else {
+      cplx<T>* ct = h->at<cplx<T>>(P.lay.ct);
+      PW_HIP(launch_convert_c64_to<T>(Hs, nb, ct, nb, nb, nb, h->stream));
+      C = ct;
+    }
+    // X' = Y C (never in place), W' = W C
+    cplx<T>* Wr = (prm.want_hx && HX) ? HX : zb();
+    const long ldwr = (prm.want_hx && HX) ? ld : ldw;
+    if (Y == X) {
+      s = rotate(Y, ldy, C, nb, u1(), ldw);
+      if (s != PW_OK) return s;
+      PW_HIP(launch_copy_cols<T>(u1(), ldw, X, ld, P.npw, nb, h->stream));
+    } else {
+      s = rotate(Y, ldy, C, nb, X, ld);
+      if (s != PW_OK) return s;
+    }
+    s = rotate(W, ldw, C, nb, Wr, ldwr);
+    if (s != PW_OK) return s;
+    double* resid_d = h->at<double>(P.lay.resid);
+    PW_HIP(launch_resid<T>(Wr, ldwr, X, ld, eig_d, P.npw, nb, resid_d, h->stream));
+    PW_HIP(hipMemcpyAsync(eig_host, eig_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
+    PW_HIP(hipMemcpyAsync(resid_host, resid_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
+    PW_HIP(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < nb; ++i)
+      if (!std::isfinite(eig_host[i]) || !std::isfinite(resid_host[i]))
+        return fail(h, PW_ENUMERIC, "non-finite eigenvalue or residual");
+    if (bounds_out) {
+      bounds_out[0] = eig_host[0];
+      bounds_out[1] = eig_host[nb - 1];
+      bounds_out[2] = bmax;
+    }
+    return PW_OK;
+  }
+
+  // Lanczos estimate of the top of the spectrum (filter bound b).
+  pw_status spectrum_bound(int steps, unsigned long long seed, double* out) {
+    const int n = P.npw;
+    cplx<T>* V0 = h->at<cplx<T>>(P.lay.lanc);
+    cplx<T>* V1 = V0 + P.ldw;
+    cplx<T>* Wv = V1 + P.ldw;
+    double* sc = h->at<double>(P.lay.scal);
+    // seeded start vector (splitmix64 + Box-Muller), normalised on the host
+    std::vector<cplx<T>> v(n);
+    uint64_t x = seed ? seed : 0x9e3779b97f4a7c15ull;
+    auto next = [&]() {
+      x += 0x9e3779b97f4a7c15ull;
+      uint64_t z = x;
+      z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+      z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+      z ^= z >> 31;
+      return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    double nrm = 0.0;
+    std::vector<double> tmp(2 * n);
+    for (int i = 0; i < n; ++i) {
+      const double u1 = next(), u2 = next();
+      const double r = std::sqrt(-2.0 * std::log(u1));
+      tmp[2 * i] = r * std::cos(6.283185307179586 * u2);
+      tmp[2 * i + 1] = r * std::sin(6.283185307179586 * u2);
+      nrm += tmp[2 * i] * tmp[2 * i] + tmp[2 * i + 1] * tmp[2 * i + 1];
+    }
+    nrm = 1.0 / std::sqrt(nrm);
+    for (int i = 0; i < n; ++i) v[i] = mk<T>((T)(tmp[2 * i] * nrm), (T)(tmp[2 * i + 1] * nrm));
+    PW_HIP(hipMemcpyAsync(V1, v.data(), sizeof(cplx<T>) * n, hipMemcpyHostToDevice, h->stream));
+    PW_HIP(launch_fill_zero<T>(V0, P.ldw, h->stream));
+    std::vector<double> al, be;
+    double bprev = 0.0;
+    for (int it = 0; it < steps && it < n; ++it) {
+      pw_status s = apply_h(V1, Wv, 1, (int)P.ldw);
+      if (s != PW_OK) return s;
+      PW_HIP(launch_lanczos_step<T>(Wv, V1, V0, bprev, n, sc, h->stream));
+      double hs[2];
+      PW_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
+      PW_HIP(hipStreamSynchronize(h->stream));
+      al.push_back(hs[0]);
+      be.push_back(hs[1]);
+      if (hs[1] < 1e-12) break;
+      // V0 <- V1, V1 <- W / beta
+      PW_HIP(launch_copy_cols<T>(V1, P.ldw, V0, P.ldw, n, 1, h->stream));
+      PW_HIP(launch_scale_copy<T>(Wv, V1, 1.0 / hs[1], n, h->stream));
+      bprev = hs[1];
+    }
+    // largest eigenvalue of the tridiagonal matrix by bisection (Sturm count)
+    const int k = (int)al.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < k; ++i) {
+      const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(be[i]) : 0.0);
+      lo = std::min(lo, al[i] - r);
+      hi = std::max(hi, al[i] + r);
+    }
+    auto count_below = [&](double xv) {
+      int cnt = 0;
+      double d = 1.0;
+      for (int i = 0; i < k; ++i) {
+        const double b2 = i > 0 ? be[i - 1] * be[i - 1] : 0.0;
+        d = al[i] - xv - (i > 0 ? b2 / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0) ++cnt;
+      }
+      return cnt;
+    };
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (count_below(mid) >= k) hi = mid; else lo = mid;
+    }
+    *out = 1.01 * (hi + std::fabs(be[k - 1]));
+    return PW_OK;
+  }
+
+  pw_status setup() {
+    const Plan& p = P;
+    const GridDesc& g = p.g;
+    hipStream_t st = h->stream;
+    // tables
+    PW_HIP(hipMemcpyAsync(h->at<int>(p.lay.miller), p.miller.data(), sizeof(int) * p.miller.size(),
+                          hipMemcpyHostToDevice, st));
+    PW_HIP(hipMemcpyAsync(h->at<Stick>(p.lay.sticks), p.sticks.data(), sizeof(Stick) * p.sticks.size(),
+                          hipMemcpyHostToDevice, st));
+    PW_HIP(hipMemcpyAsync(h->at<int>(p.lay.colstart), p.colstart.data(), sizeof(int) * p.colstart.size(),
+                          hipMemcpyHostToDevice, st));
+    std::vector<T> kin(p.npw);
+    for (int i = 0; i < p.npw; ++i) kin[i] = (T)p.kin[i];
+    PW_HIP(hipMemcpyAsync(h->at<T>(p.lay.kin), kin.data(), sizeof(T) * p.npw, hipMemcpyHostToDevice, st));
+    auto twid = [&](int n, size_t off) -> pw_status {
+      std::vector<cplx<T>> tw(n);
+      for (int m = 0; m < n; ++m) {
+        const long double a = -2.0L * 3.14159265358979323846264338327950288L * m / n;
+        tw[m] = mk<T>((T)std::cos(a), (T)std::sin(a));
+      }
+      PW_HIP(hipMemcpyAsync(h->at<cplx<T>>(off), tw.data(), sizeof(cplx<T>) * n, hipMemcpyHostToDevice, st));
+      PW_HIP(hipStreamSynchronize(st));
+      return PW_OK;
+    };
+    if (twid(g.n1, p.lay.tw1) != PW_OK || twid(g.n2, p.lay.tw2) != PW_OK || twid(g.n3, p.lay.tw3) != PW_OK)
+      return PW_EDEVICE;
+    const int nmodes = (int)p.mode_amp.size();
+    if (p.natoms)
+      PW_HIP(hipMemcpyAsync(h->at<double>(p.lay.frac), p.frac.data(), sizeof(double) * p.frac.size(),
+                            hipMemcpyHostToDevice, st));
+    if (nmodes) {
+      PW_HIP(hipMemcpyAsync(h->at<int>(p.lay.mmil), p.mode_miller.data(), sizeof(int) * 3 * nmodes,
+                            hipMemcpyHostToDevice, st));
+      PW_HIP(hipMemcpyAsync(h->at<double>(p.lay.mamp), p.mode_amp.data(), sizeof(double) * nmodes,
+                            hipMemcpyHostToDevice, st));
+      PW_HIP(hipMemcpyAsync(h->at<double>(p.lay.mpha), p.mode_phase.data(), sizeof(double) * nmodes,
+                            hipMemcpyHostToDevice, st));
+    }
+    const double ds[4] = {p.d0, p.d1, p.d1, p.d1};
+    PW_HIP(hipMemcpyAsync(h->at<double>(p.lay.dscale), ds, sizeof(ds), hipMemcpyHostToDevice, st));
+    // V(G) on the sphere -> V(r) on the grid (inverse FFT through the same stick/plane machinery)
+    PotParams pp;
+    for (int i = 0; i < 3; ++i) pp.L[i] = p.L[i];
+    pp.zval = p.natoms ? p.zval : 0.0;
+    pp.rc = p.rc;
+    pp.gauss_c = p.natoms ? p.gauss_c : 0.0;
+    pp.ecut = p.ecut;
+    pp.natoms = p.natoms;
+    pp.nmodes = nmodes;
+    double2* vg = h->at<double2>(p.lay.vg);
+    PW_HIP(launch_vg_sphere(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), h->at<int>(p.lay.mmil),
+                            h->at<double>(p.lay.mamp), h->at<double>(p.lay.mpha), pp, vg, st));
+    cplx<T>* vgT = u0();
+    PW_HIP(launch_convert_c64_to<T>(vg, p.npw, vgT, p.npw, p.npw, 1, st));
+    {
+      cplx<T>* SB = h->at<cplx<T>>(p.lay.sb);
+      cplx<T>* G1 = h->at<cplx<T>>(p.lay.g1);
+      const Stick* sti = h->at<Stick>(p.lay.sticks);
+      PW_HIP(launch_sticks_inv<T>(vgT, p.npw, SB, 1, sti, g, h->at<cplx<T>>(p.lay.tw3), p.fl, st));
+      PW_HIP(launch_planes<T>(SB, G1, (const T*)nullptr, 1, sti, h->at<int>(p.lay.colstart), g,
+                              h->at<cplx<T>>(p.lay.tw1), h->at<cplx<T>>(p.lay.tw2), (T)1, 1, h->at<T>(p.lay.vr),
+                              p.fl, st));
+    }
+    if (p.nproj)
+      PW_HIP(launch_beta_table<T>(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), p.natoms, p.L,
+                                  p.beta_sigma, beta(), p.ldw, st));
+    PW_HIP(hipStreamSynchronize(st));
+    return PW_OK;
+  }
+};
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* pw_status_string(pw_status s) {
+  switch (s) {
+    case PW_OK: return "ok";
+    case PW_PENDING: return "pending";
+    case PW_EINVAL: return "invalid argument";
+    case PW_ENOMEM: return "out of memory";
+    case PW_EDEVICE: return "device error";
+    case PW_ENOTPD: return "Gram matrix not positive definite";
+    case PW_ENUMERIC: return "non-finite result";
+    case PW_ENOTCONV: return "not converged";
+    case PW_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* pw_last_error(const pw_handle* h) {
+  if (h) return h->err.c_str();
+  return g_last_error.c_str();
+}
+
+// LDS per workgroup of the current device (gfx950: 160 KB); the default when no device is visible.
+static size_t device_max_lds() {
+  int dev = 0, n = 0, lds = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return kDefaultMaxLds;
+  }
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+    return std::min((size_t)lds, kDefaultMaxLds);
+  (void)hipGetLastError();
+  return kDefaultMaxLds;
+}
+
+static void fill_info(const Plan& p, pw_info* out) {
+  out->npw = p.npw;
+  out->nst = p.nst;
+  out->nr = (long long)p.n[0] * p.n[1] * p.n[2];
+  out->nproj = p.nproj;
+  out->footprint_bytes = p.lay.total;
+  for (int i = 0; i < 3; ++i) out->fft_n[i] = p.n[i];
+  out->nbands = p.nbands;
+  out->prec = p.prec;
+  out->fused_planes = p.fl.fused ? 1 : 0;
+}
+
+pw_status pw_plan(const pw_cell_desc* desc, pw_info* out) {
+  if (!out) return fail(nullptr, PW_EINVAL, "null output");
+  try {
+    Plan p;
+    std::string err;
+    pw_status s = make_plan(desc, device_max_lds(), &p, &err);
+    if (s != PW_OK) return fail(nullptr, s, err);
+    fill_info(p, out);
+    return PW_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, PW_ENOMEM, "host allocation failed");
+  }
+}
+
+pw_status pw_plan_gvectors(const pw_cell_desc* desc, int* miller) {
+  if (!miller) return fail(nullptr, PW_EINVAL, "null output");
+  try {
+    Plan p;
+    std::string err;
+    pw_status s = make_plan(desc, kDefaultMaxLds, &p, &err);
+    if (s != PW_OK) return fail(nullptr, s, err);
+    std::memcpy(miller, p.miller.data(), sizeof(int) * p.miller.size());
+    return PW_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, PW_ENOMEM, "host allocation failed");
+  }
+}
+
+pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes, void* hip_stream,
+                   pw_handle** out) {
+  if (!out) return fail(nullptr, PW_EINVAL, "null handle pointer");
+  *out = nullptr;
+  if (!arena_dev) return fail(nullptr, PW_EINVAL, "null arena");
+  if (reinterpret_cast<uintptr_t>(arena_dev) % kArenaAlign) return fail(nullptr, PW_EINVAL, "arena not 256-byte aligned");
+  pw_handle_s* h = nullptr;
+  try {
+    h = new pw_handle_s();
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, PW_ENOMEM, "host allocation failed");
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    delete h;
+    return fail(nullptr, PW_EDEVICE, "no HIP device");
+  }
+  h->device = dev;
+  h->max_lds = device_max_lds();
+  std::string err;
+  pw_status s;
+  try {
+    s = make_plan(desc, h->max_lds, &h->plan, &err);
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return fail(nullptr, PW_ENOMEM, "host allocation failed");
+  }
+  if (s != PW_OK) {
+    delete h;
+    return fail(nullptr, s, err);
+  }
+  if (arena_bytes < h->plan.lay.total) {
+    const std::string m = "arena too small: need " + std::to_string(h->plan.lay.total) + " bytes";
+    delete h;
+    return fail(nullptr, PW_ENOMEM, m);
+  }
+  h->arena = static_cast<unsigned char*>(arena_dev);
+  h->arena_bytes = arena_bytes;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  if (rocblas_create_handle(&h->blas) != rocblas_status_success) {
+    delete h;
+    return fail(nullptr, PW_EDEVICE, "rocblas_create_handle failed");
+  }
+  rocblas_set_stream(h->blas, h->stream);
+  if (h->plan.fl.fused) {
+    // allow large dynamic LDS for the fused plane kernel
+    pw_allow_large_lds();
+  }
+  s = h->plan.prec == PW_FP64 ? Engine<double>(h).setup() : Engine<float>(h).setup();
+  if (s != PW_OK) {
+    g_last_error = h->err;
+    rocblas_destroy_handle(h->blas);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return PW_OK;
+}
+
+pw_status pw_query(const pw_handle* h, pw_info* out) {
+  if (!h || !out) return fail(nullptr, PW_EINVAL, "null argument");
+  fill_info(h->plan, out);
+  return PW_OK;
+}
+
+pw_status pw_get_gvectors(const pw_handle* h, int* miller) {
+  if (!h || !miller) return fail(nullptr, PW_EINVAL, "null argument");
+  std::memcpy(miller, h->plan.miller.data(), sizeof(int) * h->plan.miller.size());
+  return PW_OK;
+}
+
+static pw_status check_block(pw_handle* h, const void* X, int nb, int ld) {
+  if (!X) return fail(h, PW_EINVAL, "null block");
+  if (nb < 1 || nb > h->plan.nbands) return fail(h, PW_EINVAL, "nb out of range [1, nbands]");
+  if (ld < h->plan.npw) return fail(h, PW_EINVAL, "ld < npw");
+  return PW_OK;
+}
+
+pw_status pw_apply_h(pw_handle* h, const void* X, void* HX, int nb, int ld) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  pw_status s = check_block(h, X, nb, ld);
+  if (s != PW_OK) return s;
+  if (!HX) return fail(h, PW_EINVAL, "null output");
+  const size_t cb = 2 * (size_t)h->plan.real_bytes;
+  const char* x0 = static_cast<const char*>(X);
+  const char* y0 = static_cast<const char*>(HX);
+  const size_t span = ((size_t)(nb - 1) * ld + h->plan.npw) * cb;
+  if (x0 < y0 + span && y0 < x0 + span) return fail(h, PW_EINVAL, "X and HX overlap");
+  if (h->plan.prec == PW_FP64)
+    return Engine<double>(h).apply_h(static_cast<const double2*>(X), static_cast<double2*>(HX), nb, ld);
+  return Engine<float>(h).apply_h(static_cast<const float2*>(X), static_cast<float2*>(HX), nb, ld);
+}
+
+pw_status pw_eig_step(pw_handle* h, void* X, void* HX, int nb, int ld, const pw_step_params* p, double* eig,
+                      double* resid, double bounds_out[3]) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  pw_status s = check_block(h, X, nb, ld);
+  if (s != PW_OK) return s;
+  if (!p || !eig || !resid) return fail(h, PW_EINVAL, "null argument");
+  if (p->degree < 0 || p->degree > 1000) return fail(h, PW_EINVAL, "degree out of range");
+  if (p->want_hx && !HX) return fail(h, PW_EINVAL, "want_hx without HX");
+  pw_step_params q = *p;
+  if (q.degree > 0) {
+    if (!std::isfinite(q.b)) {
+      if (!std::isfinite(h->bmax_cached)) {
+        double bb = 0.0;
+        s = pw_spectrum_bound(h, 20, 1, &bb);
+        if (s != PW_OK) return s;
+        h->bmax_cached = bb;
+      }
+      q.b = h->bmax_cached;
+    }
+    if (!(std::isfinite(q.a_lo) && std::isfinite(q.a) && q.a_lo < q.a && q.a < q.b))
+      return fail(h, PW_EINVAL, "filter bounds must satisfy a_lo < a < b");
+  }
+  if (h->plan.prec == PW_FP64)
+    return Engine<double>(h).eig_step(static_cast<double2*>(X), static_cast<double2*>(HX), nb, ld, q, eig, resid,
+                                      bounds_out);
+  return Engine<float>(h).eig_step(static_cast<float2*>(X), static_cast<float2*>(HX), nb, ld, q, eig, resid,
+                                   bounds_out);
+}
+
+pw_status pw_spectrum_bound(pw_handle* h, int steps, unsigned long long seed, double* bmax) {
+  if (!h || !bmax) return fail(nullptr, PW_EINVAL, "null argument");
+  if (steps < 2 || steps > 1000) return fail(h, PW_EINVAL, "steps out of range [2, 1000]");
+  if (h->plan.prec == PW_FP64) return Engine<double>(h).spectrum_bound(steps, seed, bmax);
+  return Engine<float>(h).spectrum_bound(steps, seed, bmax);
+}
+
+pw_status pw_destroy(pw_handle* h) {
+  if (!h) return PW_OK;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  if (h->blas) rocblas_destroy_handle(h->blas);
+  delete h;
+  return PW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Host-side launchers of the HIP kernels (all asynchronous on the given stream).
+#pragma once
+
+#include "common.hpp"
+
+namespace pw {
+
+// ---------------------------------------------------------------- FFT ------
+struct FftLaunch {
+  int spw;        // sticks per workgroup in the z pass
+  int stick_thr;  // threads per workgroup in the z pass
+  bool fused;     // whole plane in LDS
+  int plane_thr;
+  int cx, cy;     // columns / rows per workgroup in the pencil form
+  int col_thr, row_thr;
+};
+
+bool fft_plan_launch(const GridDesc& g, int real_bytes, size_t max_lds, FftLaunch* L);
+
+template <typename T>
+hipError_t launch_sticks_inv(const cplx<T>* X, long ldx, cplx<T>* SB, int nbatch, const Stick* st,
+                             const GridDesc& g, const cplx<T>* tw3, const FftLaunch& L, hipStream_t s);
+template <typename T>
+hipError_t launch_sticks_fwd(const cplx<T>* SB, cplx<T>* Z, long ldz, int nbatch, const Stick* st,
+                             const GridDesc& g, const cplx<T>* tw3, const FftLaunch& L, hipStream_t s);
+// mode 0: V multiply round trip (result scaled by `scale`); mode 1: inverse only, real part to vout
+template <typename T>
+hipError_t launch_planes(cplx<T>* SB, cplx<T>* G1, const T* V, int nbatch, const Stick* st, const int* colstart,
+                         const GridDesc& g, const cplx<T>* tw1, const cplx<T>* tw2, T scale, int mode, T* vout,
+                         const FftLaunch& L, hipStream_t s);
+
+// --------------------------------------------------------------- GEMM ------
+// C_part[s] = A^H B over the s-th K chunk.  A: K x M, B: K x N (column-major; columns of B
+// with index >= nsplit_col come from B2).  Partials are complex double, [s][N][M].
+template <typename T>
+hipError_t launch_gemm_cn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const cplx<T>* B2,
+                          long ldb2, int ncol1, int M, int N, int K, int nsplit, double2* part, hipStream_t s);
+
+// Sum the split partials: out[j*ldo + i] = scale_i * sum_s part[s][j][i]  (scale_i = dscale[i % dper]
+// when dscale != null), written as complex double to out64 (if non-null) and as T to outT (if non-null).
+template <typename T>
+hipError_t launch_reduce_parts(const double2* part, int nsplit, int M, int N, const double* dscale, int dper,
+                               double2* out64, long ldo64, cplx<T>* outT, long ldoT, hipStream_t s);
+
+// Epilogue parameters of the row-major-tile GEMM C = A B:
+//   out = alpha * ((kin_i - c) Y + Zl + acc) - beta * Yp      (EPI_H)
+//   out = acc                                                  (EPI_STORE)
+struct EpiH {
+  int mode;  // 0 = store, 1 = H / Chebyshev update
+  double alpha, c, beta;
+  const void* kin;  // T[M]
+  const void* Y;
+  long ldy;
+  const void* Zl;
+  long ldz;
+  const void* Yp;  // may be null when beta == 0
+  long ldp;
+};
+template <typename T>
+hipError_t launch_gemm_nn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb, int M, int N, int K,
+                          cplx<T>* out, long ldo, const EpiH& e, hipStream_t s);
+
+// --------------------------------------------------------------- misc ------
+template <typename T>
+hipError_t launch_fill_zero(cplx<T>* p, long n, hipStream_t s);
+
+// V(G) on the sphere (complex double) from the analytic pseudopotential and structure factors
+struct PotParams {
+  double L[3];
+  double zval, rc, gauss_c, ecut;
+  int natoms;
+  int nmodes;
+};
+hipError_t launch_vg_sphere(const int* miller, int npw, const double* frac, const int* mode_miller,
+                            const double* mode_amp, const double* mode_phase, PotParams p, double2* vg,
+                            hipStream_t s);
+// beta[g, 4a+m] table (column-major, ld)
+template <typename T>
+hipError_t launch_beta_table(const int* miller, int npw, const double* frac, int natoms, const double* L,
+                             double sigma, cplx<T>* beta, long ld, hipStream_t s);
+template <typename T>
+hipError_t launch_convert_c64_to(const double2* in, long ldi, cplx<T>* out, long ldo, int rows, int cols,
+                                 hipStream_t s);
+template <typename T>
+hipError_t launch_copy_cols(const cplx<T>* in, long ldi, cplx<T>* out, long ldo, int rows, int cols,
+                            hipStream_t s);
+// Hermitian part: A <- (A + A^H)/2, n x n complex double
+hipError_t launch_hermitize(double2* A, long lda, int n, hipStream_t s);
+// r_j = || W_j - lam_j X_j ||_2 with double accumulation; flag[0] |= non-finite seen
+template <typename T>
+hipError_t launch_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, const double* lam, int rows,
+                        int cols, double* resid, hipStream_t s);
+
+// Lanczos: alpha = Re<v, w>; w <- w - alpha v - beta_prev v_prev; beta = ||w||.  sc[0..1] = alpha, beta.
+template <typename T>
+hipError_t launch_lanczos_step(cplx<T>* w, const cplx<T>* v, const cplx<T>* vp, double beta_prev, int n, double* sc,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_scale_copy(const cplx<T>* in, cplx<T>* out, double scale, int n, hipStream_t s);
+// Opt the fused plane kernels in to the full LDS of a workgroup.
+void pw_allow_large_lds();
+
+}  // namespace pw

@@ -1,0 +1,294 @@
+// Setup kernels (local potential on the sphere, projector table) and the small
+// per-step kernels (conversions, Hermitian part, residual norms).
+
+#include <cmath>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pw {
+
+constexpr double kPi = 3.14159265358979323846;
+
+template <typename T>
+__global__ void k_fill_zero(cplx<T>* p, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = mk<T>(0, 0);
+}
+
+// exp(-2 pi i t) with t reduced to [-1/2, 1/2] first (exact phase from Miller indices)
+__device__ __forceinline__ double2 expm2pi(double t) {
+  t -= rint(t);
+  double s, c;
+  sincospi(2.0 * t, &s, &c);
+  return make_double2(c, -s);
+}
+
+// V(G) = S(G) v(|G|) + dV(G) on the sphere, with
+//   v(G) = (1/Omega)(-4 pi Z e^{-G^2 rc^2/4}/G^2 + c e^{-G^2 rc^2/4}),  S(G) = sum_a e^{-i G.tau_a},
+//   dV(+-G_k) = (amp_k / 2) e^{+-i phase_k};  V(0) = 0.
+__global__ void k_vg_sphere(const int* __restrict__ miller, int npw, const double* __restrict__ frac,
+                            const int* __restrict__ mm, const double* __restrict__ ma, const double* __restrict__ mp,
+                            PotParams p, double2* __restrict__ vg) {
+  __shared__ double sf[3 * 256];
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  int n1 = 0, n2 = 0, n3 = 0;
+  if (g < npw) {
+    n1 = miller[3 * g];
+    n2 = miller[3 * g + 1];
+    n3 = miller[3 * g + 2];
+  }
+  const double gx = 2.0 * kPi * n1 / p.L[0], gy = 2.0 * kPi * n2 / p.L[1], gz = 2.0 * kPi * n3 / p.L[2];
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  double sre = 0.0, sim = 0.0;
+  for (int a0 = 0; a0 < p.natoms; a0 += 256) {
+    const int na = min(256, p.natoms - a0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * na; i += blockDim.x) sf[i] = frac[3 * a0 + i];
+    __syncthreads();
+    for (int a = 0; a < na; ++a) {
+      const double2 e = expm2pi(n1 * sf[3 * a] + n2 * sf[3 * a + 1] + n3 * sf[3 * a + 2]);
+      sre += e.x;
+      sim += e.y;
+    }
+  }
+  if (g >= npw) return;
+  double2 out = make_double2(0.0, 0.0);
+  if (g2 > 0.0 && 0.5 * g2 <= p.ecut) {
+    const double omega = p.L[0] * p.L[1] * p.L[2];
+    const double gauss = exp(-g2 * p.rc * p.rc / 4.0);
+    const double v = (-4.0 * kPi * p.zval * gauss / g2 + p.gauss_c * gauss) / omega;
+    out.x = v * sre;
+    out.y = v * sim;
+    for (int k = 0; k < p.nmodes; ++k) {
+      const int m1 = mm[3 * k], m2 = mm[3 * k + 1], m3 = mm[3 * k + 2];
+      if (n1 == m1 && n2 == m2 && n3 == m3) {
+        out.x += 0.5 * ma[k] * cos(mp[k]);
+        out.y += 0.5 * ma[k] * sin(mp[k]);
+      } else if (n1 == -m1 && n2 == -m2 && n3 == -m3) {
+        out.x += 0.5 * ma[k] * cos(mp[k]);
+        out.y -= 0.5 * ma[k] * sin(mp[k]);
+      }
+    }
+  }
+  vg[g] = out;
+}
+
+// beta[g, 4a+m] = (c/sqrt(Omega)) e^{-sigma^2 |G|^2/2} Y_m(G) e^{-i G.tau_a},
+// c = sqrt(32 pi^{5/2} sigma^3); Y_0 = 1/(2 sqrt(pi)), Y_{1x,y,z} = sqrt(3/(4 pi)) G_{x,y,z}/|G| (0 at G=0).
+template <typename T>
+__global__ void k_beta_table(const int* __restrict__ miller, int npw, const double* __restrict__ frac, double L0,
+                             double L1, double L2, double sigma, cplx<T>* __restrict__ beta, long ld) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (g >= npw) return;
+  const int n1 = miller[3 * g], n2 = miller[3 * g + 1], n3 = miller[3 * g + 2];
+  const double gx = 2.0 * kPi * n1 / L0, gy = 2.0 * kPi * n2 / L1, gz = 2.0 * kPi * n3 / L2;
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  const double omega = L0 * L1 * L2;
+  const double c = sqrt(32.0 * pow(kPi, 2.5) * sigma * sigma * sigma);
+  const double radial = c / sqrt(omega) * exp(-0.5 * sigma * sigma * g2);
+  const double y0 = 0.5 / sqrt(kPi);
+  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  const double gn = sqrt(g2);
+  const double inv = gn > 0.0 ? c1 / gn : 0.0;
+  const double2 e = expm2pi(n1 * frac[3 * a] + n2 * frac[3 * a + 1] + n3 * frac[3 * a + 2]);
+  const double ym[4] = {y0, gx * inv, gy * inv, gz * inv};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const double s = radial * ym[m];
+    beta[(long)(4 * a + m) * ld + g] = mk<T>((T)(s * e.x), (T)(s * e.y));
+  }
+}
+
+template <typename T>
+__global__ void k_convert(const double2* __restrict__ in, long ldi, cplx<T>* __restrict__ out, long ldo, int rows,
+                          int cols) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  const int j = (int)(idx / rows), i = (int)(idx - (long)j * rows);
+  const double2 v = in[(long)j * ldi + i];
+  out[(long)j * ldo + i] = mk<T>((T)v.x, (T)v.y);
+}
+
+template <typename T>
+__global__ void k_copy_cols(const cplx<T>* __restrict__ in, long ldi, cplx<T>* __restrict__ out, long ldo, int rows,
+                            int cols) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  const int j = (int)(idx / rows), i = (int)(idx - (long)j * rows);
+  out[(long)j * ldo + i] = in[(long)j * ldi + i];
+}
+
+__global__ void k_hermitize(double2* A, long lda, int n) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * n) return;
+  const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
+  if (i < j) return;
+  double2 a = A[(long)j * lda + i];
+  if (i == j) {
+    a.y = 0.0;
+    A[(long)j * lda + i] = a;
+    return;
+  }
+  const double2 b = A[(long)i * lda + j];
+  const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  A[(long)j * lda + i] = m;
+  A[(long)i * lda + j] = make_double2(m.x, -m.y);
+}
+
+// One workgroup per column; fp64 accumulation, wavefront shuffles then LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid(const cplx<T>* __restrict__ W, long ldw, const cplx<T>* __restrict__ X,
+                                               long ldx, const double* __restrict__ lam, int rows,
+                                               double* __restrict__ resid) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  const double l = lam[j];
+  const cplx<T>* w = W + (long)j * ldw;
+  const cplx<T>* x = X + (long)j * ldx;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+    const cplx<T> a = w[i], b = x[i];
+    const double rx = (double)a.x - l * (double)b.x;
+    const double ry = (double)a.y - l * (double)b.y;
+    s += rx * rx + ry * ry;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) t += red[w2];
+    resid[j] = sqrt(t);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_lanczos(cplx<T>* __restrict__ w, const cplx<T>* __restrict__ v,
+                                                  const cplx<T>* __restrict__ vp, double bprev, int n,
+                                                  double* __restrict__ sc) {
+  __shared__ double red[16];
+  __shared__ double alpha_s;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += (double)v[i].x * w[i].x + (double)v[i].y * w[i].y;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+    alpha_s = t;
+  }
+  __syncthreads();
+  const double a = alpha_s;
+  double q = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    cplx<T> x = w[i];
+    const double rx = (double)x.x - a * v[i].x - bprev * vp[i].x;
+    const double ry = (double)x.y - a * v[i].y - bprev * vp[i].y;
+    w[i] = mk<T>((T)rx, (T)ry);
+    q += rx * rx + ry * ry;
+  }
+  __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_down(q, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+    sc[0] = a;
+    sc[1] = sqrt(t);
+  }
+}
+
+template <typename T>
+__global__ void k_scale_copy(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, double scale, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = mk<T>((T)(in[i].x * scale), (T)(in[i].y * scale));
+}
+
+template <typename T>
+hipError_t launch_lanczos_step(cplx<T>* w, const cplx<T>* v, const cplx<T>* vp, double beta_prev, int n, double* sc,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos<T>, dim3(1), dim3(1024), 0, s, w, v, vp, beta_prev, n, sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale_copy(const cplx<T>* in, cplx<T>* out, double scale, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, in, out, scale, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_zero(cplx<T>* p, long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_vg_sphere(const int* miller, int npw, const double* frac, const int* mode_miller,
+                            const double* mode_amp, const double* mode_phase, PotParams p, double2* vg,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_vg_sphere, dim3(ceil_div(npw, 256)), dim3(256), 0, s, miller, npw, frac, mode_miller, mode_amp,
+                     mode_phase, p, vg);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_beta_table(const int* miller, int npw, const double* frac, int natoms, const double* L,
+                             double sigma, cplx<T>* beta, long ld, hipStream_t s) {
+  if (natoms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_beta_table<T>, dim3(ceil_div(npw, 256), natoms), dim3(256), 0, s, miller, npw, frac, L[0], L[1],
+                     L[2], sigma, beta, ld);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_convert_c64_to(const double2* in, long ldi, cplx<T>* out, long ldo, int rows, int cols,
+                                 hipStream_t s) {
+  const long n = (long)rows * cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, in, ldi, out, ldo, rows, cols);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_cols(const cplx<T>* in, long ldi, cplx<T>* out, long ldo, int rows, int cols, hipStream_t s) {
+  const long n = (long)rows * cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_cols<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, in, ldi, out, ldo, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_hermitize(double2* A, long lda, int n, hipStream_t s) {
+  const long m = (long)n * n;
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hermitize, dim3(ceil_div(m, 256)), dim3(256), 0, s, A, lda, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, const double* lam, int rows, int cols,
+                        double* resid, hipStream_t s) {
+  if (cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resid<T>, dim3(cols), dim3(256), 0, s, W, ldw, X, ldx, lam, rows, resid);
+  return hipGetLastError();
+}
+
+#define PW_INST_MISC(T)                                                                                         \
+  template hipError_t launch_fill_zero<T>(cplx<T>*, long, hipStream_t);                                         \
+  template hipError_t launch_beta_table<T>(const int*, int, const double*, int, const double*, double, cplx<T>*, \
+                                           long, hipStream_t);                                                  \
+  template hipError_t launch_convert_c64_to<T>(const double2*, long, cplx<T>*, long, int, int, hipStream_t);    \
+  template hipError_t launch_copy_cols<T>(const cplx<T>*, long, cplx<T>*, long, int, int, hipStream_t);         \
+  template hipError_t launch_lanczos_step<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, double, int, double*, \
+                                             hipStream_t);                                                      \
+  template hipError_t launch_scale_copy<T>(const cplx<T>*, cplx<T>*, double, int, hipStream_t);                 \
+  template hipError_t launch_resid<T>(const cplx<T>*, long, const cplx<T>*, long, const double*, int, int,      \
+                                      double*, hipStream_t);
+PW_INST_MISC(float)
+PW_INST_MISC(double)
+
+}  // namespace pw

@@ -1,0 +1,237 @@
+// Host planner.  The basis is every G = 2 pi (n1/L1, n2/L2, n3/L3) with |G|^2/2 <= ecut
+// (Section II-A: the cutoff selects the plane waves and fixes the grid).  The grid
+// follows the alias-free reading N_i = min 2^p 3^q >= 3 floor(nmax_i) + 1, which is
+// the smallest grid on which the FFT application of a potential band-limited to the
+// same sphere equals the textbook matrix element V(G - G') exactly.
+#include "plan.hpp"
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+namespace pw {
+
+static const double kTwoPi = 6.283185307179586476925;
+
+bool is_23_smooth(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+FftPlan radix_plan(int n) {
+  FftPlan p;
+  p.n = n;
+  p.nrad = 0;
+  int m = n, c2 = 0, c3 = 0;
+  while (m % 2 == 0) { m /= 2; ++c2; }
+  while (m % 3 == 0) { m /= 3; ++c3; }
+  for (int i = 0; i < c2 / 2; ++i) p.rad[p.nrad++] = 4;
+  if (c2 % 2) p.rad[p.nrad++] = 2;
+  for (int i = 0; i < c3; ++i) p.rad[p.nrad++] = 3;
+  return p;
+}
+
+static int smallest_23_at_least(int need) {
+  int best = -1;
+  for (long p2 = 1; p2 < 8L * need + 8; p2 *= 2)
+    for (long p3 = p2; p3 < 8L * need + 8; p3 *= 3)
+      if (p3 >= need && (best < 0 || p3 < best)) best = (int)p3;
+  return best;
+}
+
+static size_t align_up(size_t x) { return (x + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+
+pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string* err) {
+  if (!d) { *err = "null description"; return PW_EINVAL; }
+  for (int i = 0; i < 3; ++i)
+    if (!(d->L[i] > 0.0) || !std::isfinite(d->L[i])) { *err = "cell lengths must be positive"; return PW_EINVAL; }
+  if (!(d->ecut > 0.0) || !std::isfinite(d->ecut)) { *err = "ecut must be positive"; return PW_EINVAL; }
+  if (d->natoms < 0 || (d->natoms > 0 && !d->tau)) { *err = "bad atoms"; return PW_EINVAL; }
+  if (d->nbands < 1) { *err = "nbands must be >= 1"; return PW_EINVAL; }
+  if (d->prec != PW_FP64 && d->prec != PW_MIXED) { *err = "unknown precision"; return PW_EINVAL; }
+  if (d->flags & ~PW_FLAG_PENCIL_FFT) { *err = "unknown flag bits"; return PW_EINVAL; }
+  if (d->nmodes < 0 || (d->nmodes > 0 && (!d->mode_miller || !d->mode_amp || !d->mode_phase))) {
+    *err = "bad perturbation modes";
+    return PW_EINVAL;
+  }
+  const bool have_proj = (d->d0 != 0.0 || d->d1 != 0.0) && d->natoms > 0;
+  if (have_proj && !(d->beta_sigma > 0.0)) { *err = "beta_sigma must be positive"; return PW_EINVAL; }
+  if (d->natoms > 0 && d->zval != 0.0 && !(d->rc > 0.0)) { *err = "rc must be positive"; return PW_EINVAL; }
+
+  Plan& P = *p;
+  for (int i = 0; i < 3; ++i) P.L[i] = d->L[i];
+  P.ecut = d->ecut;
+  P.natoms = d->natoms;
+  P.tau.assign(d->tau ? d->tau : nullptr, d->tau ? d->tau + 3 * d->natoms : nullptr);
+  P.frac.resize(3 * P.natoms);
+  for (int a = 0; a < P.natoms; ++a)
+    for (int i = 0; i < 3; ++i) {
+      const double t = P.tau[3 * a + i];
+      if (!std::isfinite(t)) { *err = "non-finite atom position"; return PW_EINVAL; }
+      P.frac[3 * a + i] = t / P.L[i];
+    }
+  P.nbands = d->nbands;
+  P.zval = d->zval;
+  P.rc = d->rc;
+  P.gauss_c = d->gauss_c;
+  P.beta_sigma = d->beta_sigma;
+  P.d0 = d->d0;
+  P.d1 = d->d1;
+  P.mode_miller.assign(d->mode_miller ? d->mode_miller : nullptr,
+                       d->mode_miller ? d->mode_miller + 3 * d->nmodes : nullptr);
+  P.mode_amp.assign(d->mode_amp ? d->mode_amp : nullptr, d->mode_amp ? d->mode_amp + d->nmodes : nullptr);
+  P.mode_phase.assign(d->mode_phase ? d->mode_phase : nullptr, d->mode_phase ? d->mode_phase + d->nmodes : nullptr);
+  P.prec = d->prec;
+  P.real_bytes = d->prec == PW_FP64 ? 8 : 4;
+
+  // --- sphere in stick order: n1, then n2, then n3 ascending -------------------
+  const double r2 = 2.0 * P.ecut;  // |G|^2 <= 2 ecut
+  for (int i = 0; i < 3; ++i) {
+    P.nmax[i] = (int)std::floor(std::sqrt(r2) * P.L[i] / kTwoPi);
+    if (P.nmax[i] > 4000) { *err = "cutoff too large for this cell"; return PW_EINVAL; }
+  }
+  P.miller.clear();
+  P.sticks.clear();
+  P.kin.clear();
+  const double b0 = kTwoPi / P.L[0], b1 = kTwoPi / P.L[1], b2 = kTwoPi / P.L[2];
+  for (int n1 = -P.nmax[0]; n1 <= P.nmax[0]; ++n1) {
+    for (int n2 = -P.nmax[1]; n2 <= P.nmax[1]; ++n2) {
+      const double g12 = (n1 * b0) * (n1 * b0) + (n2 * b1) * (n2 * b1);
+      if (g12 > r2) continue;
+      int h = (int)std::floor(std::sqrt(r2 - g12) / b2);
+      while (g12 + ((h + 1) * b2) * ((h + 1) * b2) <= r2) ++h;
+      while (h >= 0 && g12 + (h * b2) * (h * b2) > r2) --h;
+      if (h < 0) continue;
+      Stick s;
+      s.off = (int)(P.miller.size() / 3);
+      s.len = 2 * h + 1;
+      s.n1 = n1;
+      s.n2 = n2;
+      P.sticks.push_back(s);
+      for (int n3 = -h; n3 <= h; ++n3) {
+        P.miller.push_back(n1);
+        P.miller.push_back(n2);
+        P.miller.push_back(n3);
+        const double g2 = g12 + (n3 * b2) * (n3 * b2);
+        P.kin.push_back(0.5 * g2);
+      }
+    }
+  }
+  P.npw = (int)P.kin.size();
+  P.nst = (int)P.sticks.size();
+  if (P.nbands > P.npw) { *err = "nbands exceeds the number of plane waves"; return PW_EINVAL; }
+  P.nproj = have_proj ? 4 * P.natoms : 0;
+  P.ldw = (P.npw + 15) / 16 * 16;
+
+  // --- grid ----------------------------------------------------------------------
+  const bool user_grid = d->fft_n[0] || d->fft_n[1] || d->fft_n[2];
+  for (int i = 0; i < 3; ++i) {
+    const int need = 3 * P.nmax[i] + 1;
+    if (user_grid) {
+      const int ni = d->fft_n[i];
+      if (ni < need) { *err = "fft_n below the alias-free size 3*nmax+1"; return PW_EINVAL; }
+      if (!is_23_smooth(ni)) { *err = "fft_n must be of the form 2^p 3^q"; return PW_EINVAL; }
+      P.n[i] = ni;
+    } else {
+      P.n[i] = smallest_23_at_least(need);
+    }
+    if (P.n[i] > 512) { *err = "grid dimension above 512 is not supported"; return PW_EINVAL; }
+  }
+  int n1max = 0;
+  for (const Stick& s : P.sticks) n1max = std::max(n1max, std::abs(s.n1));
+  GridDesc& g = P.g;
+  g.n1 = P.n[0];
+  g.n2 = P.n[1];
+  g.n3 = P.n[2];
+  g.nst = P.nst;
+  g.npw = P.npw;
+  g.n1max = n1max;
+  g.n1a = 2 * n1max + 1;
+  g.p1 = radix_plan(g.n1);
+  g.p2 = radix_plan(g.n2);
+  g.p3 = radix_plan(g.n3);
+  P.colstart.assign(g.n1a + 1, 0);
+  {
+    int s = 0;
+    for (int xa = 0; xa < g.n1a; ++xa) {
+      P.colstart[xa] = s;
+      while (s < P.nst && P.sticks[s].n1 + n1max == xa) ++s;
+    }
+    P.colstart[g.n1a] = s;
+  }
+  if (!fft_plan_launch(g, P.real_bytes, (d->flags & PW_FLAG_PENCIL_FFT) ? 0 : max_lds, &P.fl)) {
+    *err = "no FFT launch shape fits this grid";
+    return PW_EINVAL;
+  }
+
+  // --- batching ------------------------------------------------------------------
+  const size_t cb = 2 * (size_t)P.real_bytes;
+  const size_t per_band_sb = (size_t)P.nst * g.n3 * cb;
+  const size_t per_band_g1 = P.fl.fused ? 0 : (size_t)g.n3 * g.n2 * g.n1a * cb;
+  size_t budget = 192ull << 20;  // keep the stick/pencil intermediates of one batch cache-sized
+  if (const char* e = std::getenv("PW_FFT_BATCH_MB")) budget = (size_t)std::atol(e) << 20;
+  int fb = (int)(budget / (per_band_sb + per_band_g1));
+  if (fb < 1) fb = 1;
+  if (fb > P.nbands) fb = P.nbands;
+  P.fft_batch = fb;
+  auto pick_split = [](int tiles, int K) {
+    int s = (2048 + tiles - 1) / tiles;
+    int kmax = K / 512;
+    if (s > kmax) s = kmax;
+    if (s > 64) s = 64;
+    if (s < 1) s = 1;
+    return s;
+  };
+  const int tb = (P.nbands + 63) / 64;
+  P.nsplit_proj = P.nproj ? pick_split(((P.nproj + 63) / 64) * tb, P.npw) : 1;
+  P.nsplit_gram = pick_split(tb * ((2 * P.nbands + 63) / 64), P.npw);
+
+  // --- arena layout --------------------------------------------------------------
+  ArenaLayout& L = P.lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const size_t rb = P.real_bytes;
+  const size_t nb = P.nbands;
+  const size_t nr = (size_t)g.n1 * g.n2 * g.n3;
+  L.miller = take(sizeof(int) * 3 * P.npw);
+  L.sticks = take(sizeof(Stick) * P.nst);
+  L.colstart = take(sizeof(int) * (g.n1a + 1));
+  L.kin = take(rb * P.npw);
+  L.tw1 = take(cb * g.n1);
+  L.tw2 = take(cb * g.n2);
+  L.tw3 = take(cb * g.n3);
+  L.vr = take(rb * nr);
+  L.frac = take(sizeof(double) * 3 * std::max(1, P.natoms));
+  L.mmil = take(sizeof(int) * 3 * std::max<size_t>(1, P.mode_amp.size()));
+  L.mamp = take(sizeof(double) * std::max<size_t>(1, P.mode_amp.size()));
+  L.mpha = take(sizeof(double) * std::max<size_t>(1, P.mode_amp.size()));
+  L.vg = take(sizeof(double) * 2 * P.npw);
+  L.dscale = take(sizeof(double) * 4);
+  L.beta = take(cb * P.ldw * P.nproj);
+  L.u0 = take(cb * P.ldw * nb);
+  L.u1 = take(cb * P.ldw * nb);
+  L.zb = take(cb * P.ldw * nb);
+  L.sb = take(per_band_sb * P.fft_batch);
+  L.g1 = take(per_band_g1 * P.fft_batch);
+  L.pt = take(cb * std::max(1, P.nproj) * nb);
+  const size_t parts = std::max((size_t)P.nsplit_proj * P.nproj * nb, (size_t)P.nsplit_gram * nb * 2 * nb);
+  L.parts = take(16 * parts);
+  L.sh = take(16 * nb * 2 * nb);
+  L.ct = take(cb * nb * nb);
+  L.eig = take(sizeof(double) * nb);
+  L.ework = take(sizeof(double) * nb);
+  L.resid = take(sizeof(double) * nb);
+  L.info = take(sizeof(int) * 4);
+  L.scal = take(sizeof(double) * 8);
+  L.lanc = take(cb * P.ldw * 3);
+  L.total = off;
+  return PW_OK;
+}
+
+}  // namespace pw

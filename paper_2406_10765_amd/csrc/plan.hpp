@@ -1,0 +1,58 @@
+// Host planner: plane-wave sphere, sticks, grid, radix plans and arena layout.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/pw.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pw {
+
+constexpr size_t kArenaAlign = 256;
+constexpr size_t kDefaultMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+
+struct ArenaLayout {
+  size_t miller, sticks, colstart, kin, tw1, tw2, tw3, vr, frac, mmil, mamp, mpha, vg, dscale;
+  size_t beta, u0, u1, zb, sb, g1, pt, parts, sh, ct, eig, ework, resid, info, scal, lanc;
+  size_t total;
+};
+
+struct Plan {
+  // copy of the description
+  double L[3];
+  double ecut;
+  int natoms;
+  std::vector<double> tau;  // 3 * natoms, Cartesian
+  std::vector<double> frac; // 3 * natoms, fractional (tau / L)
+  int nbands;
+  double zval, rc, gauss_c, beta_sigma, d0, d1;
+  std::vector<int> mode_miller;
+  std::vector<double> mode_amp, mode_phase;
+  int prec;
+  int real_bytes;  // 8 (FP64) or 4 (mixed)
+  // basis
+  int nmax[3];
+  int n[3];
+  int npw, nst, nproj;
+  long ldw;  // internal leading dimension (npw rounded up to 16)
+  std::vector<int> miller;     // 3 * npw, stick order
+  std::vector<Stick> sticks;   // nst
+  std::vector<int> colstart;   // n1a + 1: first stick of each active x column
+  std::vector<double> kin;     // npw: |G|^2 / 2
+  GridDesc g;
+  FftLaunch fl;
+  int fft_batch;               // bands per FFT launch group
+  int nsplit_proj, nsplit_gram;
+  ArenaLayout lay;
+};
+
+// Fills `p` from `d`; returns PW_OK or PW_EINVAL with a message.
+pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string* err);
+
+// 2^p 3^q test and radix plan
+bool is_23_smooth(int n);
+FftPlan radix_plan(int n);
+
+}  // namespace pw

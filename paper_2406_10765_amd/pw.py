@@ -1,0 +1,288 @@
+"""ctypes binding of libpw.so (argument marshalling only).
+
+Every computation runs inside the HIP library.  torch provides the device
+memory (the arena and the wavefunction blocks) and the stream.  If the
+library has not been built this module raises on first use; there is no
+fallback path.
+
+Block convention on the Python side: a torch tensor of shape (nb, ld) with
+contiguous rows is the column-major npw x nb block of the C ABI (row b is band
+b, first npw entries used).  complex128 for FP64 handles, complex64 for mixed.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpw.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pw.h")
+
+PW_OK, PW_PENDING, PW_EINVAL, PW_ENOMEM, PW_EDEVICE = 0, 1, -1, -2, -3
+PW_ENOTPD, PW_ENUMERIC, PW_ENOTCONV, PW_EBUSY = -4, -5, -6, -7
+PW_FP64, PW_MIXED = 0, 1
+
+
+class CellDesc(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_double * 3),
+        ("natoms", ctypes.c_int),
+        ("tau", ctypes.POINTER(ctypes.c_double)),
+        ("ecut", ctypes.c_double),
+        ("nbands", ctypes.c_int),
+        ("zval", ctypes.c_double),
+        ("rc", ctypes.c_double),
+        ("gauss_c", ctypes.c_double),
+        ("beta_sigma", ctypes.c_double),
+        ("d0", ctypes.c_double),
+        ("d1", ctypes.c_double),
+        ("nmodes", ctypes.c_int),
+        ("mode_miller", ctypes.POINTER(ctypes.c_int)),
+        ("mode_amp", ctypes.POINTER(ctypes.c_double)),
+        ("mode_phase", ctypes.POINTER(ctypes.c_double)),
+        ("fft_n", ctypes.c_int * 3),
+        ("prec", ctypes.c_int),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("npw", ctypes.c_longlong),
+        ("nst", ctypes.c_longlong),
+        ("nr", ctypes.c_longlong),
+        ("nproj", ctypes.c_longlong),
+        ("footprint_bytes", ctypes.c_size_t),
+        ("fft_n", ctypes.c_int * 3),
+        ("nbands", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("fused_planes", ctypes.c_int),
+    ]
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [
+        ("degree", ctypes.c_int),
+        ("a_lo", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("b", ctypes.c_double),
+        ("want_hx", ctypes.c_int),
+    ]
+
+
+class PWError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def declared_functions() -> List[str]:
+    """Names of every function include/pw.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pw_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2406_10765_amd/build.py (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    sig = {
+        "pw_plan": ([P(CellDesc), P(Info)]),
+        "pw_plan_gvectors": ([P(CellDesc), P(ctypes.c_int)]),
+        "pw_setup": ([P(CellDesc), vp, ctypes.c_size_t, vp, P(vp)]),
+        "pw_query": ([vp, P(Info)]),
+        "pw_get_gvectors": ([vp, P(ctypes.c_int)]),
+        "pw_apply_h": ([vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "pw_eig_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, P(StepParams), P(ctypes.c_double),
+                         P(ctypes.c_double), P(ctypes.c_double)]),
+        "pw_spectrum_bound": ([vp, ctypes.c_int, ctypes.c_ulonglong, P(ctypes.c_double)]),
+        "pw_destroy": ([vp]),
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.pw_last_error.argtypes = [vp]
+    L.pw_last_error.restype = ctypes.c_char_p
+    L.pw_status_string.argtypes = [ctypes.c_int]
+    L.pw_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, handle=None):
+    if status != PW_OK:
+        msg = lib().pw_last_error(handle)
+        raise PWError(status, (msg or b"").decode() or lib().pw_status_string(status).decode())
+
+
+PW_FLAG_PENCIL_FFT = 1
+
+
+def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,
+              fft_n: Sequence[int] = (0, 0, 0), flags: int = 0):
+    """CellDesc from a synth.Cell; returns (desc, keepalive)."""
+    p = cell.pseudo
+    tau = np.ascontiguousarray(np.asarray(cell.tau, np.float64).reshape(-1))
+    mm = np.ascontiguousarray(np.asarray(cell.modes.miller, np.int32).reshape(-1))
+    ma = np.ascontiguousarray(np.asarray(cell.modes.amp, np.float64))
+    mp = np.ascontiguousarray(np.asarray(cell.modes.phase, np.float64))
+    d = CellDesc()
+    d.L[:] = [float(x) for x in cell.L]
+    d.natoms = int(cell.natoms)
+    d.tau = tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if tau.size else None
+    d.ecut = float(cell.ecut)
+    d.nbands = int(cell.nbands if nbands is None else nbands)
+    d.zval, d.rc, d.gauss_c = p.zval, p.rc, p.gauss_c
+    d.beta_sigma, d.d0, d.d1 = p.beta_sigma, p.d0, p.d1
+    d.nmodes = int(ma.size)
+    d.mode_miller = mm.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if ma.size else None
+    d.mode_amp = ma.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if ma.size else None
+    d.mode_phase = mp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if ma.size else None
+    d.fft_n[:] = [int(x) for x in fft_n]
+    d.prec = int(prec)
+    d.flags = int(flags)
+    return d, (tau, mm, ma, mp)
+
+
+def plan(cell, prec: int = PW_FP64, nbands: Optional[int] = None, fft_n=(0, 0, 0)) -> Info:
+    d, keep = make_desc(cell, prec, nbands, fft_n)
+    info = Info()
+    _check(lib().pw_plan(ctypes.byref(d), ctypes.byref(info)))
+    return info
+
+
+def plan_gvectors(cell, nbands: Optional[int] = None, fft_n=(0, 0, 0)) -> np.ndarray:
+    info = plan(cell, PW_FP64, nbands, fft_n)
+    d, keep = make_desc(cell, PW_FP64, nbands, fft_n)
+    out = np.empty((info.npw, 3), np.int32)
+    _check(lib().pw_plan_gvectors(ctypes.byref(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+    return out
+
+
+class Handle:
+    """A set-up cell on the current torch CUDA device and stream."""
+
+    def __init__(self, cell, prec: int = PW_FP64, nbands: Optional[int] = None, fft_n=(0, 0, 0),
+                 device=None, stream=None, flags: int = 0):
+        import torch
+
+        self._torch = torch
+        self.prec = prec
+        self.dtype = torch.complex128 if prec == PW_FP64 else torch.complex64
+        d, self._keep = make_desc(cell, prec, nbands, fft_n, flags)
+        self.info = Info()
+        _check(lib().pw_plan(ctypes.byref(d), ctypes.byref(self.info)))
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.arena = torch.empty(int(self.info.footprint_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = ctypes.c_void_p()
+        _check(lib().pw_setup(ctypes.byref(d), ctypes.c_void_p(self.arena.data_ptr()),
+                              ctypes.c_size_t(self.arena.numel()), ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.byref(h)))
+        self._h = h
+        _check(lib().pw_query(self._h, ctypes.byref(self.info)), self._h)
+        self.npw = int(self.info.npw)
+        self.nbands = int(self.info.nbands)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pw_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gvectors(self) -> np.ndarray:
+        out = np.empty((self.npw, 3), np.int32)
+        _check(lib().pw_get_gvectors(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), self._h)
+        return out
+
+    def empty_block(self, nb: int, ld: Optional[int] = None):
+        ld = self.npw if ld is None else ld
+        return self._torch.empty((nb, ld), dtype=self.dtype, device=self.device)
+
+    def to_device(self, X: np.ndarray, ld: Optional[int] = None):
+        """numpy (npw, nb) in this handle's plane-wave order -> device block (nb, ld)."""
+        nb = X.shape[1]
+        t = self._torch.zeros((nb, self.npw if ld is None else ld), dtype=self.dtype)
+        t[:, : self.npw] = self._torch.from_numpy(np.ascontiguousarray(X.T)).to(self.dtype)
+        return t.to(self.device)
+
+    def to_host(self, T) -> np.ndarray:
+        """device block (nb, ld) -> numpy (npw, nb) complex128."""
+        return T[:, : self.npw].cpu().numpy().astype(np.complex128).T.copy()
+
+    def _check_block(self, T):
+        torch = self._torch
+        if T.dtype != self.dtype or T.device != self.device or T.dim() != 2 or T.stride(1) != 1:
+            raise ValueError("block must be a (nb, ld) row-contiguous tensor of the handle's dtype and device")
+        return int(T.shape[0]), int(T.stride(0))
+
+    def apply_h(self, X, HX=None):
+        nb, ld = self._check_block(X)
+        if HX is None:
+            HX = self._torch.zeros_like(X)
+        nb2, ld2 = self._check_block(HX)
+        if nb2 != nb or ld2 != ld:
+            raise ValueError("X and HX must have the same shape and stride")
+        _check(lib().pw_apply_h(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(HX.data_ptr()), nb, ld),
+               self._h)
+        return HX
+
+    def eig_step(self, X, degree: int, a_lo: float = float("nan"), a: float = float("nan"),
+                 b: float = float("nan"), HX=None):
+        """One step on X (in place).  Returns (eig, resid, bounds) as numpy arrays."""
+        nb, ld = self._check_block(X)
+        p = StepParams(int(degree), float(a_lo), float(a), float(b), 1 if HX is not None else 0)
+        eig = np.empty(nb)
+        res = np.empty(nb)
+        bnd = np.empty(3)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().pw_eig_step(self._h, ctypes.c_void_p(X.data_ptr()),
+                                 ctypes.c_void_p(HX.data_ptr() if HX is not None else 0), nb, ld, ctypes.byref(p),
+                                 eig.ctypes.data_as(dp), res.ctypes.data_as(dp), bnd.ctypes.data_as(dp)), self._h)
+        return eig, res, bnd
+
+    def spectrum_bound(self, steps: int = 20, seed: int = 1) -> float:
+        out = ctypes.c_double()
+        _check(lib().pw_spectrum_bound(self._h, steps, seed, ctypes.byref(out)), self._h)
+        return out.value
+
+    def solve(self, X, nocc: int, tol: float, degree: int = 10, max_steps: int = 200, b: Optional[float] = None):
+        """Repeat steps (first m = 0) until max residual over the lowest nocc bands <= tol."""
+        bmax = self.spectrum_bound() if b is None else b
+        eig, res, bnd = self.eig_step(X, 0, b=bmax)
+        steps = 1
+        while float(res[:nocc].max()) > tol and steps < max_steps:
+            eig, res, bnd = self.eig_step(X, degree, bnd[0], bnd[1], bmax)
+            steps += 1
+        return eig, res, steps, float(res[:nocc].max()) <= tol
+
+
+def permutation_to(miller_from: np.ndarray, miller_to: np.ndarray) -> np.ndarray:
+    """Index array p with miller_from[p] == miller_to (row order conversion between bases)."""
+    key = lambda m: ((m[:, 0].astype(np.int64) + 4096) * 8192 + (m[:, 1] + 4096)) * 8192 + (m[:, 2] + 4096)
+    kf, kt = key(np.asarray(miller_from)), key(np.asarray(miller_to))
+    order = np.argsort(kf)
+    pos = np.searchsorted(kf[order], kt)
+    p = order[pos]
+    if not np.array_equal(kf[p], kt):
+        raise ValueError("Miller sets differ")
+    return p
