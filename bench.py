@@ -1,0 +1,280 @@
+#!/usr/bin/env python
+"""Benchmark of one block-eigensolver step (the whole hot path) on one MI355X.
+
+One step = degree-m Chebyshev filter (m H applications, each: stick/plane FFTs with V(r),
+projector GEMMs, fused update) + W = H Y + [S | H_s] = Y^H [Y | W] + FP64 generalised
+eigensolve + rotation + residual norms.  Default workload: Si512 (4x4x4 diamond cells,
+a = 10.26 bohr), E_cut = 20 Ha, 1088 bands, degree 10, mixed precision (FP32 complex FFTs
+and GEMMs, FP64 eigensolve and residuals); the FP64 form of the same step is timed beside
+it and one step of each from the same block gives the eigenvalue difference.
+
+Prints one JSON line.  Inputs are synthetic and seeded; they are resident in device memory
+before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+METRIC = "eig-steps/sec & HΨ band-apps/sec, mixed vs FP64 @|Δε|≤1e-5 Ha; p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def phase_work(name: str, info, nb: int, m: int, steps: int, real_bytes: int):
+    """Algorithmic work of a phase over the timed region: (amount, kind) with kind 'flop' or 'byte'."""
+    npw, nproj, nst = int(info.npw), int(info.nproj), int(info.nst)
+    n1, n2, n3 = (int(x) for x in info.fft_n)
+    nr = n1 * n2 * n3
+    cb = 2 * real_bytes
+    happs = steps * (m + 1)  # H applications of nb bands in the timed steps
+    bands = happs * nb
+    if name == "proj" or name == "nl":
+        return 8.0 * npw * nproj * nb * happs, "flop"
+    if name == "gram":
+        return 8.0 * npw * nb * (2 * nb) * steps, "flop"
+    if name == "rotate":
+        return 8.0 * npw * nb * nb * 2 * steps, "flop"
+    if name == "sticks_inv" or name == "sticks_fwd":
+        return float(bands) * (npw + nst * n3) * cb, "byte"
+    if name == "plane":
+        return float(bands) * (2.0 * nst * n3 * cb + nr * real_bytes), "byte"
+    if name == "resid":
+        return 2.0 * npw * nb * cb * steps, "byte"
+    return None, None
+
+
+def run_steps(h, X, m, steps, bounds, b):
+    import torch
+
+    eig = res = None
+    for _ in range(steps):
+        eig, res, bnd = h.eig_step(X, m, bounds[0], bounds[1], b)
+        bounds = (bnd[0], bnd[1])
+    torch.cuda.synchronize()
+    return eig, res, bounds
+
+
+def cpu_baseline(cell, nb: int, m: int, sample_bands: int = 32):
+    """Time the oracle on a bounded sample and extrapolate to one step."""
+    import scipy.linalg
+    from oracle import pw_oracle as O
+    from paper_2406_10765_amd import synth
+
+    cores = len(os.sched_getaffinity(0))
+    O.FFT_WORKERS = cores
+    try:
+        from threadpoolctl import threadpool_limits
+
+        limiter = threadpool_limits(limits=cores)
+    except Exception:  # pragma: no cover
+        limiter = None
+    t0 = time.time()
+    model = O.model_from_cell(cell)
+    t_model = time.time() - t0
+    X = synth.initial_block(model.miller, cell.L, sample_bands, 5)
+    t0 = time.time()
+    W = O.apply_h(model, X)
+    t_apply = time.time() - t0
+    t0 = time.time()
+    S = X.conj().T @ X
+    Hs = X.conj().T @ W
+    C = np.eye(sample_bands, dtype=complex)
+    _ = X @ C
+    _ = W @ C
+    t_rr = time.time() - t0
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb))
+    A = A @ A.conj().T + nb * np.eye(nb)
+    Bm = rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb))
+    Bm = 0.5 * (Bm + Bm.conj().T)
+    t0 = time.time()
+    scipy.linalg.eigh(Bm, A)
+    t_eig = time.time() - t0
+    step = (m + 1) * (nb / sample_bands) * t_apply + (nb / sample_bands) ** 2 * t_rr + t_eig
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {
+        "value": 1.0 / step,
+        "unit": "eig-steps/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"oracle H application on {sample_bands} of {nb} bands ({t_apply:.2f} s) and the "
+                   f"Rayleigh-Ritz products on that block ({t_rr:.2f} s), extrapolated linearly in bands "
+                   f"(quadratically for the products) to one degree-{m} step, plus a timed FP64 "
+                   f"generalised eigensolve of size {nb} ({t_eig:.2f} s); model build {t_model:.1f} s not counted"),
+        "extrapolated_step_s": step,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="si512")
+    ap.add_argument("--degree", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2406_10765_amd import pw, synth
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written by one copy kernel")
+        del src, dst
+    cell = synth.make_cell(args.workload)
+    nb, m = cell.nbands, args.degree
+
+    # ---- mixed precision (the headline) --------------------------------------------------
+    t0 = time.time()
+    hm = pw.Handle(cell, pw.PW_MIXED)
+    G = hm.gvectors()
+    X0 = synth.initial_block(G, cell.L, nb, synth.SEED_X0 + synth.WORKLOADS[args.workload]["index"])
+    b = hm.spectrum_bound(20, 1)
+    X = hm.to_device(X0)
+    eig, res, bnd = hm.eig_step(X, 0, b=b)
+    bounds = (bnd[0], bnd[1])
+    log(f"setup {time.time() - t0:.1f}s  npw={hm.npw} nb={nb} b={b:.4f} fused_planes={hm.info.fused_planes}")
+    eig, res, bounds = run_steps(hm, X, m, args.warmup, bounds, b)
+    hm.reset_stats()
+    hm.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, res, bounds = run_steps(hm, X, m, args.steps, bounds, b)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = hm.stats()
+    hm.set_timing(False)
+    ms_step = 1000.0 * dt / args.steps
+    value = 1000.0 / ms_step
+    band_apps = (m + 1) * nb / (ms_step / 1000.0)
+    log(f"mixed: {ms_step:.1f} ms/step, max resid(occ) {res[:cell.nocc].max():.2e}")
+
+    phases = {}
+    dom, dom_ms = None, -1.0
+    for name, st in stats.items():
+        if st["launches"] == 0:
+            continue
+        amount, kind = phase_work(name, hm.info, nb, m, args.steps, 4)
+        entry = {"launches": st["launches"], "ms_total": round(st["ms"], 3),
+                 "ms_per_launch": round(st["ms"] / st["launches"], 4)}
+        if amount is not None:
+            if kind == "flop":
+                entry["tflops"] = round(amount / (st["ms"] * 1e-3) / 1e12, 2)
+                entry["frac_peak"] = round(entry["tflops"] / PEAK_MFMA_TFLOPS["fp32"], 4)
+            else:
+                entry["gbs"] = round(amount / (st["ms"] * 1e-3) / 1e9, 1)
+                entry["frac_peak"] = round(entry["gbs"] / PEAK_HBM_GBS, 4)
+            if st["ms"] > dom_ms:
+                dom, dom_ms = name, st["ms"]
+        phases[name] = entry
+    d = phases[dom]
+    amount, kind = phase_work(dom, hm.info, nb, m, args.steps, 4)
+    per_launch = amount / stats[dom]["launches"]
+    if kind == "flop":
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": d["tflops"], "peak": PEAK_MFMA_TFLOPS["fp32"],
+                    "unit": "TFLOP/s", "frac": d["frac_peak"], "traffic": None,
+                    "algorithmic_per_launch": per_launch, "avg_launch_ms": d["ms_per_launch"]}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": d["frac_peak"], "traffic": None, "algorithmic_per_launch": per_launch,
+                    "avg_launch_ms": d["ms_per_launch"]}
+
+    # ---- FP64 form and accuracy of one step from the same block -----------------------------
+    fp64 = None
+    accuracy = None
+    Xm = X.clone()
+    bounds_m = bounds
+    info = hm.info
+    del hm
+    torch.cuda.empty_cache()
+    if not args.no_fp64:
+        hd = pw.Handle(cell, pw.PW_FP64)
+        Xd = Xm.to(torch.complex128)
+        e64, r64, _ = hd.eig_step(Xd.clone(), m, bounds_m[0], bounds_m[1], b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xt = Xd.clone()
+        bd = bounds_m
+        for _ in range(args.fp64_steps):
+            e, r, bb = hd.eig_step(Xt, m, bd[0], bd[1], b)
+            bd = (bb[0], bb[1])
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t0
+        ms64 = 1000.0 * dt64 / args.fp64_steps
+        fp64 = {"value": 1000.0 / ms64, "unit": "eig-steps/s", "ms_per_step": round(ms64, 2),
+                "band_apps_per_sec": (m + 1) * nb / (ms64 / 1000.0)}
+        del hd
+        torch.cuda.empty_cache()
+        hm2 = pw.Handle(cell, pw.PW_MIXED)
+        e32, r32, _ = hm2.eig_step(Xm.clone(), m, bounds_m[0], bounds_m[1], b)
+        nocc = cell.nocc
+        accuracy = {"max_abs_deig_occ_mixed_vs_fp64_Ha": float(np.abs(e32[:nocc] - e64[:nocc]).max()),
+                    "bands_compared": nocc, "what": "one degree-%d step from the same block" % m}
+        del hm2
+        log(f"fp64: {ms64:.1f} ms/step; one-step |de| mixed vs fp64 = {accuracy['max_abs_deig_occ_mixed_vs_fp64_Ha']:.2e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cell, nb, m)
+        log(f"cpu baseline: {cpu['extrapolated_step_s']:.1f} s/step (extrapolated), {cpu['cores']} cores")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "eig-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload.capitalize()}: {cell.natoms} Si atoms ({'x'.join(str(int(round(L / synth.A0_BOHR))) for L in cell.L)} diamond cells, a=10.26 bohr), "
+                               f"Ecut {cell.ecut:g} Ha, Gamma point, {G.shape[0]} plane waves, {nb} bands, "
+                               f"degree-{m} Chebyshev-filtered Rayleigh-Ritz step, mixed precision",
+                   "npw": int(G.shape[0]), "nbands": nb, "degree": m, "ecut_ha": cell.ecut,
+                   "fft_grid": list(int(x) for x in pw.plan(cell, pw.PW_MIXED).fft_n), "precision": "mixed"},
+        "band_apps_per_sec": band_apps,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64": fp64,
+        "accuracy": accuracy,
+        "phases": phases,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

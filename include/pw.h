@@ -160,6 +160,39 @@ pw_status pw_eig_step(pw_handle *h, void *X_dev, void *HX_dev, int nb, int ld, c
  */
 pw_status pw_spectrum_bound(pw_handle *h, int steps, unsigned long long seed, double *bmax);
 
+/*
+ * Per-phase device time.  While timing is on, every kernel launch of a call is bracketed by
+ * HIP events recorded on the handle's stream; the elapsed times are accumulated per phase.
+ * pw_get_stats synchronises the stream and fills PW_NPHASES entries.
+ */
+typedef enum {
+  PW_PH_STICKS_INV = 0, /* sphere -> sticks, inverse z FFT */
+  PW_PH_PLANE,          /* fused plane pass: 2D FFT, * V(r), 2D FFT */
+  PW_PH_PENCIL_YINV,    /* pencil form: inverse y FFT */
+  PW_PH_PENCIL_X,       /* pencil form: x FFT, * V(r), x FFT */
+  PW_PH_PENCIL_YFWD,    /* pencil form: forward y FFT */
+  PW_PH_STICKS_FWD,     /* sticks -> sphere, forward z FFT */
+  PW_PH_PROJ,           /* P = beta^H Y (split-K MFMA GEMM) */
+  PW_PH_PROJ_REDUCE,    /* split sum and D scaling of P */
+  PW_PH_NL,             /* beta (D P) + kinetic + local + Chebyshev update (MFMA GEMM, fused epilogue) */
+  PW_PH_GRAM,           /* [S | H_s] = Y^H [Y | W] (split-K MFMA GEMM) */
+  PW_PH_GRAM_REDUCE,    /* split sum and Hermitian parts */
+  PW_PH_EIGSOLVE,       /* FP64 Cholesky + generalised eigensolve */
+  PW_PH_ROTATE,         /* X' = Y C, W' = W C (MFMA GEMM) */
+  PW_PH_RESID,          /* residual norms */
+  PW_PH_OTHER,          /* conversions and copies */
+  PW_NPHASES
+} pw_phase;
+
+typedef struct {
+  long long launches;
+  double ms;
+} pw_phase_stat;
+
+pw_status pw_set_timing(pw_handle *h, int on);
+pw_status pw_get_stats(pw_handle *h, pw_phase_stat *out);
+pw_status pw_reset_stats(pw_handle *h);
+
 pw_status pw_destroy(pw_handle *h);
 const char *pw_last_error(const pw_handle *h);
 const char *pw_status_string(pw_status s);

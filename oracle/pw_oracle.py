@@ -39,6 +39,9 @@ import scipy.linalg
 
 TWO_PI = 2.0 * math.pi
 
+# Worker threads for scipy.fft (-1: all CPUs); the CPU-baseline timing sets it explicitly.
+FFT_WORKERS = -1
+
 
 # ----------------------------------------------------------------------------
 # Basis and grid (Section II-A: E_cut fixes the basis and the real-space grid)
@@ -241,12 +244,12 @@ def gather_from_grid(f: np.ndarray, miller: np.ndarray) -> np.ndarray:
 def to_real_space(c: np.ndarray, miller: np.ndarray, grid: Sequence[int]) -> np.ndarray:
     """psi(r_j) = sum_G c_G exp(+i G.r_j): unnormalised inverse DFT (bands first for blocks)."""
     f = scatter_to_grid(c, miller, grid)
-    return scipy.fft.ifftn(f, axes=(-3, -2, -1), norm="forward", workers=-1)
+    return scipy.fft.ifftn(f, axes=(-3, -2, -1), norm="forward", workers=FFT_WORKERS)
 
 
 def to_g_space(f: np.ndarray, miller: np.ndarray) -> np.ndarray:
     """c_G = (1/N_r) sum_j f(r_j) exp(-i G.r_j), gathered on the sphere."""
-    F = scipy.fft.fftn(f, axes=(-3, -2, -1), norm="forward", workers=-1)
+    F = scipy.fft.fftn(f, axes=(-3, -2, -1), norm="forward", workers=FFT_WORKERS)
     return gather_from_grid(F, miller)
 
 

@@ -37,8 +37,63 @@ struct pw_handle_s {
   size_t max_lds = kDefaultMaxLds;
   std::string err;
   double bmax_cached = NAN;
+  // phase timers
+  bool timing = false;
+  hipEvent_t open_ev = nullptr;
+  struct Rec {
+    int ph;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> pending;
+  pw_phase_stat stats[PW_NPHASES] = {};
+
   template <typename X>
   X* at(size_t off) const { return reinterpret_cast<X*>(arena + off); }
+
+  hipEvent_t take_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void tbegin() {
+    if (!timing) return;
+    open_ev = take_event();
+    if (open_ev) hipEventRecord(open_ev, stream);
+  }
+  void tend(int ph) {
+    if (!timing || !open_ev) return;
+    hipEvent_t b = take_event();
+    if (!b) return;
+    hipEventRecord(b, stream);
+    pending.push_back({ph, open_ev, b});
+    open_ev = nullptr;
+  }
+  // Requires the stream to be synchronised.
+  void resolve() {
+    for (const Rec& r : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        stats[r.ph].ms += ms;
+        stats[r.ph].launches += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  ~pw_handle_s() {
+    for (const Rec& r : pending) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : pool) hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -50,6 +105,14 @@ namespace {
       h->err = std::string(#call) + ": " + hipGetErrorString(e_);                     \
       return PW_EDEVICE;                                                              \
     }                                                                                 \
+  } while (0)
+
+// Launch `call` bracketed by the phase timer of `ph`.
+#define PW_TIMED(ph, call) \
+  do {                     \
+    h->tbegin();           \
+    PW_HIP(call);          \
+    h->tend(ph);           \
   } while (0)
 
 pw_status fail(pw_handle_s* h, pw_status s, const std::string& m) {
@@ -81,11 +144,18 @@ struct Engine {
     const cplx<T>* tw1 = h->at<cplx<T>>(P.lay.tw1);
     const cplx<T>* tw2 = h->at<cplx<T>>(P.lay.tw2);
     const cplx<T>* tw3 = h->at<cplx<T>>(P.lay.tw3);
+    hipStream_t sm = h->stream;
     for (int b0 = 0; b0 < nb; b0 += P.fft_batch) {
       const int nbt = std::min(P.fft_batch, nb - b0);
-      PW_HIP(launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, h->stream));
-      PW_HIP(launch_planes<T>(SB, G1, V, nbt, st, cs, g, tw1, tw2, scale, 0, nullptr, P.fl, h->stream));
-      PW_HIP(launch_sticks_fwd<T>(SB, Z + (long)b0 * ldz, ldz, nbt, st, g, tw3, P.fl, h->stream));
+      PW_TIMED(PW_PH_STICKS_INV, launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, sm));
+      if (P.fl.fused) {
+        PW_TIMED(PW_PH_PLANE, launch_plane_fused<T>(SB, V, nbt, st, g, tw1, tw2, scale, 0, (T*)nullptr, P.fl, sm));
+      } else {
+        PW_TIMED(PW_PH_PENCIL_YINV, launch_pencil_yinv<T>(SB, G1, nbt, st, cs, g, tw2, P.fl, sm));
+        PW_TIMED(PW_PH_PENCIL_X, launch_pencil_x<T>(G1, V, nbt, g, tw1, 0, (T*)nullptr, P.fl, sm));
+        PW_TIMED(PW_PH_PENCIL_YFWD, launch_pencil_yfwd<T>(SB, G1, nbt, st, cs, g, tw2, scale, P.fl, sm));
+      }
+      PW_TIMED(PW_PH_STICKS_FWD, launch_sticks_fwd<T>(SB, Z + (long)b0 * ldz, ldz, nbt, st, g, tw3, P.fl, sm));
     }
     return PW_OK;
   }
@@ -99,10 +169,11 @@ struct Engine {
     cplx<T>* PT = h->at<cplx<T>>(P.lay.pt);
     if (P.nproj > 0) {
       double2* parts = h->at<double2>(P.lay.parts);
-      PW_HIP(launch_gemm_cn<T>(beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw, P.nsplit_proj, parts,
-                               h->stream));
-      PW_HIP(launch_reduce_parts<T>(parts, P.nsplit_proj, P.nproj, nb, h->at<double>(P.lay.dscale), 4, nullptr, 0,
-                                    PT, P.nproj, h->stream));
+      PW_TIMED(PW_PH_PROJ, launch_gemm_cn<T>(beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw,
+                                             P.nsplit_proj, parts, h->stream));
+      PW_TIMED(PW_PH_PROJ_REDUCE, launch_reduce_parts<T>(parts, P.nsplit_proj, P.nproj, nb,
+                                                         h->at<double>(P.lay.dscale), 4, nullptr, 0, PT, P.nproj,
+                                                         h->stream));
     }
     EpiH e;
     e.mode = 1;
@@ -116,7 +187,7 @@ struct Engine {
     e.ldz = ldz;
     e.Yp = Yp;
     e.ldp = ldp;
-    PW_HIP(launch_gemm_nn<T>(beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e, h->stream));
+    PW_TIMED(PW_PH_NL, launch_gemm_nn<T>(beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e, h->stream));
     return PW_OK;
   }
 
@@ -128,7 +199,7 @@ struct Engine {
     EpiH e;
     std::memset(&e, 0, sizeof(e));
     e.mode = 0;
-    PW_HIP(launch_gemm_nn<T>(A, lda, C, nb, P.npw, nb, nb, out, ldo, e, h->stream));
+    PW_TIMED(PW_PH_ROTATE, launch_gemm_nn<T>(A, lda, C, nb, P.npw, nb, nb, out, ldo, e, h->stream));
     return PW_OK;
   }
 
@@ -171,20 +242,25 @@ struct Engine {
     // [S | H_s] = Y^H [Y | W]
     double2* parts = h->at<double2>(P.lay.parts);
     double2* SH = h->at<double2>(P.lay.sh);
-    PW_HIP(launch_gemm_cn<T>(Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram, parts, h->stream));
-    PW_HIP(launch_reduce_parts<T>(parts, P.nsplit_gram, nb, 2 * nb, nullptr, 0, SH, nb, (cplx<T>*)nullptr, 0,
-                                  h->stream));
+    PW_TIMED(PW_PH_GRAM, launch_gemm_cn<T>(Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram, parts,
+                                           h->stream));
     double2* S = SH;
     double2* Hs = SH + (size_t)nb * nb;
+    h->tbegin();
+    PW_HIP(launch_reduce_parts<T>(parts, P.nsplit_gram, nb, 2 * nb, nullptr, 0, SH, nb, (cplx<T>*)nullptr, 0,
+                                  h->stream));
     PW_HIP(launch_hermitize(S, nb, nb, h->stream));
     PW_HIP(launch_hermitize(Hs, nb, nb, h->stream));
+    h->tend(PW_PH_GRAM_REDUCE);
     // FP64 generalised eigensolve: Hs C = S C diag(lambda), C^H S C = I
     double* eig_d = h->at<double>(P.lay.eig);
     int* info_d = h->at<int>(P.lay.info);
+    h->tbegin();
     rocblas_status rs = rocsolver_zhegvd(h->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, nb,
                                          reinterpret_cast<rocblas_double_complex*>(Hs), nb,
                                          reinterpret_cast<rocblas_double_complex*>(S), nb, eig_d,
                                          h->at<double>(P.lay.ework), info_d);
+    h->tend(PW_PH_EIGSOLVE);
     if (rs != rocblas_status_success)
       return fail(h, PW_EDEVICE, std::string("rocsolver_zhegvd: ") + rocblas_status_to_string(rs));
     int info = 0;
@@ -198,7 +274,7 @@ struct Engine {
       C = reinterpret_cast<const cplx<T>*>(Hs);
     } else {
       cplx<T>* ct = h->at<cplx<T>>(P.lay.ct);
-      PW_HIP(launch_convert_c64_to<T>(Hs, nb, ct, nb, nb, nb, h->stream));
+      PW_TIMED(PW_PH_OTHER, launch_convert_c64_to<T>(Hs, nb, ct, nb, nb, nb, h->stream));
       C = ct;
     }
     // X' = Y C (never in place), W' = W C
@@ -207,7 +283,7 @@ struct Engine {
     if (Y == X) {
       s = rotate(Y, ldy, C, nb, u1(), ldw);
       if (s != PW_OK) return s;
-      PW_HIP(launch_copy_cols<T>(u1(), ldw, X, ld, P.npw, nb, h->stream));
+      PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(u1(), ldw, X, ld, P.npw, nb, h->stream));
     } else {
       s = rotate(Y, ldy, C, nb, X, ld);
       if (s != PW_OK) return s;
@@ -215,10 +291,11 @@ struct Engine {
     s = rotate(W, ldw, C, nb, Wr, ldwr);
     if (s != PW_OK) return s;
     double* resid_d = h->at<double>(P.lay.resid);
-    PW_HIP(launch_resid<T>(Wr, ldwr, X, ld, eig_d, P.npw, nb, resid_d, h->stream));
+    PW_TIMED(PW_PH_RESID, launch_resid<T>(Wr, ldwr, X, ld, eig_d, P.npw, nb, resid_d, h->stream));
     PW_HIP(hipMemcpyAsync(eig_host, eig_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
     PW_HIP(hipMemcpyAsync(resid_host, resid_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
     PW_HIP(hipStreamSynchronize(h->stream));
+    h->resolve();
     for (int i = 0; i < nb; ++i)
       if (!std::isfinite(eig_host[i]) || !std::isfinite(resid_host[i]))
         return fail(h, PW_ENUMERIC, "non-finite eigenvalue or residual");
@@ -363,10 +440,16 @@ struct Engine {
       cplx<T>* SB = h->at<cplx<T>>(p.lay.sb);
       cplx<T>* G1 = h->at<cplx<T>>(p.lay.g1);
       const Stick* sti = h->at<Stick>(p.lay.sticks);
+      const cplx<T>* tw1 = h->at<cplx<T>>(p.lay.tw1);
+      const cplx<T>* tw2 = h->at<cplx<T>>(p.lay.tw2);
+      T* vr = h->at<T>(p.lay.vr);
       PW_HIP(launch_sticks_inv<T>(vgT, p.npw, SB, 1, sti, g, h->at<cplx<T>>(p.lay.tw3), p.fl, st));
-      PW_HIP(launch_planes<T>(SB, G1, (const T*)nullptr, 1, sti, h->at<int>(p.lay.colstart), g,
-                              h->at<cplx<T>>(p.lay.tw1), h->at<cplx<T>>(p.lay.tw2), (T)1, 1, h->at<T>(p.lay.vr),
-                              p.fl, st));
+      if (p.fl.fused) {
+        PW_HIP(launch_plane_fused<T>(SB, (const T*)nullptr, 1, sti, g, tw1, tw2, (T)1, 1, vr, p.fl, st));
+      } else {
+        PW_HIP(launch_pencil_yinv<T>(SB, G1, 1, sti, h->at<int>(p.lay.colstart), g, tw2, p.fl, st));
+        PW_HIP(launch_pencil_x<T>(G1, (const T*)nullptr, 1, g, tw1, 1, vr, p.fl, st));
+      }
     }
     if (p.nproj)
       PW_HIP(launch_beta_table<T>(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), p.natoms, p.L,
@@ -584,6 +667,32 @@ pw_status pw_spectrum_bound(pw_handle* h, int steps, unsigned long long seed, do
   if (steps < 2 || steps > 1000) return fail(h, PW_EINVAL, "steps out of range [2, 1000]");
   if (h->plan.prec == PW_FP64) return Engine<double>(h).spectrum_bound(steps, seed, bmax);
   return Engine<float>(h).spectrum_bound(steps, seed, bmax);
+}
+
+pw_status pw_set_timing(pw_handle* h, int on) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  if (!on && !h->pending.empty()) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, PW_EDEVICE, "stream synchronise failed");
+    h->resolve();
+  }
+  h->timing = on != 0;
+  return PW_OK;
+}
+
+pw_status pw_get_stats(pw_handle* h, pw_phase_stat* out) {
+  if (!h || !out) return fail(nullptr, PW_EINVAL, "null argument");
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, PW_EDEVICE, "stream synchronise failed");
+  h->resolve();
+  for (int i = 0; i < PW_NPHASES; ++i) out[i] = h->stats[i];
+  return PW_OK;
+}
+
+pw_status pw_reset_stats(pw_handle* h) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, PW_EDEVICE, "stream synchronise failed");
+  h->resolve();
+  for (int i = 0; i < PW_NPHASES; ++i) h->stats[i] = pw_phase_stat{0, 0.0};
+  return PW_OK;
 }
 
 pw_status pw_destroy(pw_handle* h) {

@@ -392,35 +392,40 @@ hipError_t launch_sticks_fwd(const cplx<T>* SB, cplx<T>* Z, long ldz, int nbatch
 }
 
 template <typename T>
-hipError_t launch_planes(cplx<T>* SB, cplx<T>* G1, const T* V, int nbatch, const Stick* st, const int* colstart,
-                         const GridDesc& g, const cplx<T>* tw1, const cplx<T>* tw2, T scale, int mode, T* vout,
-                         const FftLaunch& L, hipStream_t s) {
-  if (L.fused) {
-    const size_t lds = (size_t)(g.n1 * g.n2 + g.n1 + g.n2) * sizeof(cplx<T>);
-    dim3 grid(g.n3, nbatch);
-    hipLaunchKernelGGL(k_plane<T>, grid, dim3(L.plane_thr), lds, s, SB, V, st, g, tw1, tw2, scale, mode, vout);
-    return hipGetLastError();
-  }
-  {
-    const size_t lds = (size_t)(g.n2 * L.cx + g.n2) * sizeof(cplx<T>);
-    dim3 grid(ceil_div(g.n1a, L.cx), g.n3, nbatch);
-    hipLaunchKernelGGL(k_ycols_inv<T>, grid, dim3(L.col_thr), lds, s, SB, G1, st, colstart, g, tw2, L.cx);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  {
-    const size_t lds = (size_t)(L.cy * g.n1 + g.n1) * sizeof(cplx<T>);
-    dim3 grid(ceil_div(g.n2, L.cy), g.n3, nbatch);
-    hipLaunchKernelGGL(k_xrows<T>, grid, dim3(L.row_thr), lds, s, G1, V, g, tw1, L.cy, mode, vout);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || mode == 1) return e;
-  }
-  {
-    const size_t lds = (size_t)(g.n2 * L.cx + g.n2) * sizeof(cplx<T>);
-    dim3 grid(ceil_div(g.n1a, L.cx), g.n3, nbatch);
-    hipLaunchKernelGGL(k_ycols_fwd<T>, grid, dim3(L.col_thr), lds, s, SB, G1, st, colstart, g, tw2, L.cx, scale);
-    return hipGetLastError();
-  }
+hipError_t launch_plane_fused(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const GridDesc& g,
+                              const cplx<T>* tw1, const cplx<T>* tw2, T scale, int mode, T* vout, const FftLaunch& L,
+                              hipStream_t s) {
+  const size_t lds = (size_t)(g.n1 * g.n2 + g.n1 + g.n2) * sizeof(cplx<T>);
+  dim3 grid(g.n3, nbatch);
+  hipLaunchKernelGGL(k_plane<T>, grid, dim3(L.plane_thr), lds, s, SB, V, st, g, tw1, tw2, scale, mode, vout);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pencil_yinv(const cplx<T>* SB, cplx<T>* G1, int nbatch, const Stick* st, const int* colstart,
+                              const GridDesc& g, const cplx<T>* tw2, const FftLaunch& L, hipStream_t s) {
+  const size_t lds = (size_t)(g.n2 * L.cx + g.n2) * sizeof(cplx<T>);
+  dim3 grid(ceil_div(g.n1a, L.cx), g.n3, nbatch);
+  hipLaunchKernelGGL(k_ycols_inv<T>, grid, dim3(L.col_thr), lds, s, SB, G1, st, colstart, g, tw2, L.cx);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pencil_x(cplx<T>* G1, const T* V, int nbatch, const GridDesc& g, const cplx<T>* tw1, int mode,
+                           T* vout, const FftLaunch& L, hipStream_t s) {
+  const size_t lds = (size_t)(L.cy * g.n1 + g.n1) * sizeof(cplx<T>);
+  dim3 grid(ceil_div(g.n2, L.cy), g.n3, nbatch);
+  hipLaunchKernelGGL(k_xrows<T>, grid, dim3(L.row_thr), lds, s, G1, V, g, tw1, L.cy, mode, vout);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pencil_yfwd(cplx<T>* SB, const cplx<T>* G1, int nbatch, const Stick* st, const int* colstart,
+                              const GridDesc& g, const cplx<T>* tw2, T scale, const FftLaunch& L, hipStream_t s) {
+  const size_t lds = (size_t)(g.n2 * L.cx + g.n2) * sizeof(cplx<T>);
+  dim3 grid(ceil_div(g.n1a, L.cx), g.n3, nbatch);
+  hipLaunchKernelGGL(k_ycols_fwd<T>, grid, dim3(L.col_thr), lds, s, SB, G1, st, colstart, g, tw2, L.cx, scale);
+  return hipGetLastError();
 }
 
 bool fft_plan_launch(const GridDesc& g, int real_bytes, size_t max_lds, FftLaunch* L) {
@@ -468,9 +473,15 @@ void pw_allow_large_lds() {
                                            const cplx<T>*, const FftLaunch&, hipStream_t);                      \
   template hipError_t launch_sticks_fwd<T>(const cplx<T>*, cplx<T>*, long, int, const Stick*, const GridDesc&, \
                                            const cplx<T>*, const FftLaunch&, hipStream_t);                      \
-  template hipError_t launch_planes<T>(cplx<T>*, cplx<T>*, const T*, int, const Stick*, const int*,           \
-                                       const GridDesc&, const cplx<T>*, const cplx<T>*, T, int, T*,             \
-                                       const FftLaunch&, hipStream_t);
+  template hipError_t launch_plane_fused<T>(cplx<T>*, const T*, int, const Stick*, const GridDesc&,           \
+                                            const cplx<T>*, const cplx<T>*, T, int, T*, const FftLaunch&,      \
+                                            hipStream_t);                                                      \
+  template hipError_t launch_pencil_yinv<T>(const cplx<T>*, cplx<T>*, int, const Stick*, const int*,          \
+                                            const GridDesc&, const cplx<T>*, const FftLaunch&, hipStream_t);   \
+  template hipError_t launch_pencil_x<T>(cplx<T>*, const T*, int, const GridDesc&, const cplx<T>*, int, T*,   \
+                                         const FftLaunch&, hipStream_t);                                       \
+  template hipError_t launch_pencil_yfwd<T>(cplx<T>*, const cplx<T>*, int, const Stick*, const int*,          \
+                                            const GridDesc&, const cplx<T>*, T, const FftLaunch&, hipStream_t);
 PW_INST_FFT(float)
 PW_INST_FFT(double)
 

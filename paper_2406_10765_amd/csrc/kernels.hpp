@@ -23,11 +23,23 @@ hipError_t launch_sticks_inv(const cplx<T>* X, long ldx, cplx<T>* SB, int nbatch
 template <typename T>
 hipError_t launch_sticks_fwd(const cplx<T>* SB, cplx<T>* Z, long ldz, int nbatch, const Stick* st,
                              const GridDesc& g, const cplx<T>* tw3, const FftLaunch& L, hipStream_t s);
-// mode 0: V multiply round trip (result scaled by `scale`); mode 1: inverse only, real part to vout
+// Plane stage.  Fused form (whole plane in LDS): mode 0 = inverse 2D FFT, * V, forward 2D FFT,
+// gather * scale; mode 1 = inverse only, real part to vout[z][y][x].
 template <typename T>
-hipError_t launch_planes(cplx<T>* SB, cplx<T>* G1, const T* V, int nbatch, const Stick* st, const int* colstart,
-                         const GridDesc& g, const cplx<T>* tw1, const cplx<T>* tw2, T scale, int mode, T* vout,
-                         const FftLaunch& L, hipStream_t s);
+hipError_t launch_plane_fused(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const GridDesc& g,
+                              const cplx<T>* tw1, const cplx<T>* tw2, T scale, int mode, T* vout, const FftLaunch& L,
+                              hipStream_t s);
+// Pencil form: y inverse (sticks -> G1), x rows (inverse, * V, forward; mode 1: inverse only to vout),
+// y forward (G1 -> sticks * scale).
+template <typename T>
+hipError_t launch_pencil_yinv(const cplx<T>* SB, cplx<T>* G1, int nbatch, const Stick* st, const int* colstart,
+                              const GridDesc& g, const cplx<T>* tw2, const FftLaunch& L, hipStream_t s);
+template <typename T>
+hipError_t launch_pencil_x(cplx<T>* G1, const T* V, int nbatch, const GridDesc& g, const cplx<T>* tw1, int mode,
+                           T* vout, const FftLaunch& L, hipStream_t s);
+template <typename T>
+hipError_t launch_pencil_yfwd(cplx<T>* SB, const cplx<T>* G1, int nbatch, const Stick* st, const int* colstart,
+                              const GridDesc& g, const cplx<T>* tw2, T scale, const FftLaunch& L, hipStream_t s);
 
 // --------------------------------------------------------------- GEMM ------
 // C_part[s] = A^H B over the s-th K chunk.  A: K x M, B: K x N (column-major; columns of B

@@ -74,6 +74,14 @@ class StepParams(ctypes.Structure):
     ]
 
 
+PHASES = ["sticks_inv", "plane", "pencil_yinv", "pencil_x", "pencil_yfwd", "sticks_fwd", "proj", "proj_reduce",
+          "nl", "gram", "gram_reduce", "eigsolve", "rotate", "resid", "other"]
+
+
+class PhaseStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_longlong), ("ms", ctypes.c_double)]
+
+
 class PWError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -109,6 +117,9 @@ def lib() -> ctypes.CDLL:
         "pw_eig_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, P(StepParams), P(ctypes.c_double),
                          P(ctypes.c_double), P(ctypes.c_double)]),
         "pw_spectrum_bound": ([vp, ctypes.c_int, ctypes.c_ulonglong, P(ctypes.c_double)]),
+        "pw_set_timing": ([vp, ctypes.c_int]),
+        "pw_get_stats": ([vp, P(PhaseStat)]),
+        "pw_reset_stats": ([vp]),
         "pw_destroy": ([vp]),
     }
     for name, args in sig.items():
@@ -264,6 +275,18 @@ class Handle:
         out = ctypes.c_double()
         _check(lib().pw_spectrum_bound(self._h, steps, seed, ctypes.byref(out)), self._h)
         return out.value
+
+    def set_timing(self, on: bool):
+        _check(lib().pw_set_timing(self._h, 1 if on else 0), self._h)
+
+    def reset_stats(self):
+        _check(lib().pw_reset_stats(self._h), self._h)
+
+    def stats(self) -> dict:
+        """Per-phase {launches, ms} measured with HIP events on the handle's stream."""
+        arr = (PhaseStat * len(PHASES))()
+        _check(lib().pw_get_stats(self._h, arr), self._h)
+        return {name: {"launches": int(arr[i].launches), "ms": float(arr[i].ms)} for i, name in enumerate(PHASES)}
 
     def solve(self, X, nocc: int, tol: float, degree: int = 10, max_steps: int = 200, b: Optional[float] = None):
         """Repeat steps (first m = 0) until max residual over the lowest nocc bands <= tol."""
