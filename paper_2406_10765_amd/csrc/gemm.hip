@@ -6,7 +6,9 @@
 //   * "cn": C = A^H B with a very long inner dimension K = N_pw (projections
 //     beta^H Y, Gram Y^H Y, projected Hamiltonian Y^H W).  Split over K; each
 //     split writes complex-double partials that a second kernel sums in a
-//     fixed order (deterministic, no atomics).
+//     fixed order (deterministic, no atomics).  In fp32 the MFMA accumulators
+//     are moved into fp64 registers every 256 K values, so the long sums keep
+//     fp64-like accuracy.
 //   * "nn": C = A B with K = N_proj or N_b and M = N_pw rows (beta (D P),
 //     rotation Y C).  A fused epilogue assembles H Y or the Chebyshev update.
 //
@@ -17,6 +19,12 @@
 // operand B[k][j] from lane j + 16 k for both precisions; accumulator element r
 // of lane l holds C[4 (l / 16) + r][l % 16] for f32 but C[l / 16 + 4 r][l % 16]
 // for f64 (measured with one-hot operands on gfx950).
+//
+// Structure of one workgroup (4 waves in a 2 x 2 arrangement): global loads of
+// the next K tile go to registers (16-byte loads where the leading dimension
+// allows) while the MFMAs run on the current tile; the tiles live in two LDS
+// buffers, so each K tile costs one barrier.  Tiles are handed out XCD by XCD:
+// consecutive tiles, which share operand panels, run on the same L2.
 
 #include <type_traits>
 
@@ -44,77 +52,225 @@ template <> struct MF<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int G_WM = 2, G_WN = 2;          // 16x16 blocks per wave (rows, cols)
-constexpr int G_BM = 32 * G_WM, G_BN = 32 * G_WN, G_BK = 16;
-constexpr int G_FLUSH = 16;                // fp32: move partial sums to fp64 every 16 K tiles
+constexpr int kBK = 16;     // K per tile (complex elements)
+constexpr int kFlush = 16;  // fp32 cn: K tiles per move into fp64 registers
+constexpr int kXcd = 8;     // XCDs per MI355X
 
-template <typename T>
+// 16 bytes = U complex elements (U = 2 for fp32, 1 for fp64)
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+  using type = float4;
+  static constexpr int U = 2;
+};
+template <> struct Vec16<double> {
+  using type = double2;
+  static constexpr int U = 1;
+};
+
+// Tile index -> (tm, tn, split) with the tiles of one XCD contiguous.  Launch order
+// sends workgroup w to XCD w % 8.
+__device__ __forceinline__ int xcd_tile(int w, int total) {
+  const int per = total / kXcd, rem = total % kXcd;
+  const int x = w % kXcd, i = w / kXcd;
+  // XCDs 0..rem-1 get per + 1 tiles, the others per
+  return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+// Loader of a K-contiguous operand panel: kBK values of NC columns starting at (k0, c0).
+// Element (k, c) goes to S[k * LDS_LD + c].
+template <typename T, int NC, bool VEC>
+struct KcLoader {
+  static constexpr int U = VEC ? Vec16<T>::U : 1;
+  static constexpr int UNITS = kBK / U * NC;  // loads per tile
+  static constexpr int PER = (UNITS + 255) / 256;
+  cplx<T> r[PER][U];
+  __device__ __forceinline__ void load(const cplx<T>* __restrict__ P, long ld, const cplx<T>* __restrict__ P2, long ld2,
+                                       int ncol1, int ncols, int c0, int k0, int kend, int tid) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      const int ku = idx % (kBK / U), c = idx / (kBK / U);
+      const int gc = c0 + c, gk = k0 + ku * U;
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[q][u] = mk<T>(0, 0);
+      if (idx < UNITS && gc < ncols) {
+        const cplx<T>* col = gc < ncol1 ? P + (long)gc * ld : P2 + (long)(gc - ncol1) * ld2;
+        if (VEC && gk + U <= kend) {
+          const typename Vec16<T>::type v = *reinterpret_cast<const typename Vec16<T>::type*>(col + gk);
+          if constexpr (std::is_same<T, float>::value) {
+            r[q][0] = mk<T>(v.x, v.y);
+            r[q][U - 1] = mk<T>(v.z, v.w);
+          } else {
+            r[q][0] = mk<T>(v.x, v.y);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (gk + u < kend) r[q][u] = col[gk + u];
+        }
+      }
+    }
+  }
+  template <int LDS_LD>
+  __device__ __forceinline__ void store(cplx<T>* S, int tid) const {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < UNITS) {
+        const int ku = idx % (kBK / U), c = idx / (kBK / U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) S[(ku * U + u) * LDS_LD + c] = r[q][u];
+      }
+    }
+  }
+};
+
+// Loader of an M-contiguous operand panel (nn A): NR rows x kBK columns of a column-major matrix.
+template <typename T, int NR, bool VEC>
+struct McLoader {
+  static constexpr int U = VEC ? Vec16<T>::U : 1;
+  static constexpr int UNITS = NR / U * kBK;
+  static constexpr int PER = (UNITS + 255) / 256;
+  cplx<T> r[PER][U];
+  __device__ __forceinline__ void load(const cplx<T>* __restrict__ P, long ld, int nrows, int r0, int k0, int kend,
+                                       int tid) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      const int mu = idx % (NR / U), k = idx / (NR / U);
+      const int gm = r0 + mu * U, gk = k0 + k;
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[q][u] = mk<T>(0, 0);
+      if (idx < UNITS && gk < kend) {
+        const cplx<T>* col = P + (long)gk * ld;
+        if (VEC && gm + U <= nrows) {
+          const typename Vec16<T>::type v = *reinterpret_cast<const typename Vec16<T>::type*>(col + gm);
+          if constexpr (std::is_same<T, float>::value) {
+            r[q][0] = mk<T>(v.x, v.y);
+            r[q][U - 1] = mk<T>(v.z, v.w);
+          } else {
+            r[q][0] = mk<T>(v.x, v.y);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (gm + u < nrows) r[q][u] = col[gm + u];
+        }
+      }
+    }
+  }
+  template <int LDS_LD>
+  __device__ __forceinline__ void store(cplx<T>* S, int tid) const {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < UNITS) {
+        const int mu = idx % (NR / U), k = idx / (NR / U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) S[k * LDS_LD + mu * U + u] = r[q][u];
+      }
+    }
+  }
+};
+
+// Wave-level MFMA accumulation over one K tile held in LDS.
+// sA: kBK x (BM + 1) (m contiguous), sB: kBK x (BN + 1) (n contiguous).
+template <typename T, int WBM, int WBN, bool CONJ_A>
+__device__ __forceinline__ void mma_tile(const cplx<T>* sA, const cplx<T>* sB, int lda_s, int ldb_s, int mo, int no,
+                                         int lane, typename MF<T>::acc (&cr)[WBM][WBN],
+                                         typename MF<T>::acc (&ci)[WBM][WBN]) {
+#pragma unroll
+  for (int kk = 0; kk < kBK; kk += 4) {
+    cplx<T> av[WBM], bv[WBN];
+    const int kr = kk + (lane >> 4);
+#pragma unroll
+    for (int a = 0; a < WBM; ++a) av[a] = sA[kr * lda_s + mo + a * 16 + (lane & 15)];
+#pragma unroll
+    for (int b = 0; b < WBN; ++b) bv[b] = sB[kr * ldb_s + no + b * 16 + (lane & 15)];
+#pragma unroll
+    for (int a = 0; a < WBM; ++a)
+#pragma unroll
+      for (int b = 0; b < WBN; ++b) cr[a][b] = MF<T>::mma(av[a].x, bv[b].x, cr[a][b]);
+#pragma unroll
+    for (int a = 0; a < WBM; ++a)
+#pragma unroll
+      for (int b = 0; b < WBN; ++b) ci[a][b] = MF<T>::mma(av[a].x, bv[b].y, ci[a][b]);
+#pragma unroll
+    for (int a = 0; a < WBM; ++a) {
+      const T ai = CONJ_A ? av[a].y : -av[a].y;
+#pragma unroll
+      for (int b = 0; b < WBN; ++b) cr[a][b] = MF<T>::mma(ai, bv[b].y, cr[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < WBM; ++a) {
+      const T ai = CONJ_A ? -av[a].y : av[a].y;
+#pragma unroll
+      for (int b = 0; b < WBN; ++b) ci[a][b] = MF<T>::mma(ai, bv[b].x, ci[a][b]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// cn: part[s] = A^H B over K chunk s.  Workgroup tile BM x BN (waves 2 x 2).
+// ------------------------------------------------------------------------------------------
+template <typename T, int BM, int BN, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_cn(const cplx<T>* __restrict__ A, long lda,
                                                  const cplx<T>* __restrict__ B, long ldb,
-                                                 const cplx<T>* __restrict__ B2, long ldb2, int ncol1, int M,
-                                                 int N, int K, int kchunk, double2* __restrict__ part) {
+                                                 const cplx<T>* __restrict__ B2, long ldb2, int ncol1, int M, int N,
+                                                 int K, int kchunk, int tiles_m, int tiles_n,
+                                                 double2* __restrict__ part) {
+  constexpr int WBM = BM / 32, WBN = BN / 32;  // 16x16 blocks per wave
+  constexpr int LA = BM + 1, LB = BN + 1;
   using acc_t = typename MF<T>::acc;
-  __shared__ cplx<T> sA[G_BK][G_BM + 1];
-  __shared__ cplx<T> sB[G_BK][G_BN + 1];
+  __shared__ cplx<T> sA[2][kBK * LA];
+  __shared__ cplx<T> sB[2][kBK * LB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int i0 = blockIdx.x * G_BM, j0 = blockIdx.y * G_BN, sp = blockIdx.z;
+  const int nsplit = gridDim.x / (tiles_m * tiles_n);
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  // tiles of one split are contiguous; inside a split, n fastest
+  const int sp = t / (tiles_m * tiles_n);
+  const int tr = t - sp * tiles_m * tiles_n;
+  const int tm = tr / tiles_n, tn = tr - tm * tiles_n;
+  (void)nsplit;
+  const int i0 = tm * BM, j0 = tn * BN;
   const int kb = sp * kchunk, ke = min(K, kb + kchunk);
-  acc_t cr[G_WM][G_WN], ci[G_WM][G_WN];
-  double dr[G_WM][G_WN][4], di[G_WM][G_WN][4];
+  const int mo = (wave & 1) * (BM / 2), no = (wave >> 1) * (BN / 2);
+  acc_t cr[WBM][WBN], ci[WBM][WBN];
+  double dr[WBM][WBN][4], di[WBM][WBN][4];
 #pragma unroll
-  for (int a = 0; a < G_WM; ++a)
+  for (int a = 0; a < WBM; ++a)
 #pragma unroll
-    for (int b = 0; b < G_WN; ++b) {
+    for (int b = 0; b < WBN; ++b) {
       cr[a][b] = acc_t{0, 0, 0, 0};
       ci[a][b] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
     }
-  const cplx<T> zero = mk<T>(0, 0);
-  int tile = 0;
-  for (int k0 = kb; k0 < ke; k0 += G_BK, ++tile) {
-#pragma unroll
-    for (int r = 0; r < G_BK * G_BM / 256; ++r) {
-      const int idx = tid + r * 256;
-      const int kk = idx & (G_BK - 1), ii = idx / G_BK;
-      const int gi = i0 + ii, gk = k0 + kk;
-      sA[kk][ii] = (gi < M && gk < ke) ? A[(long)gi * lda + gk] : zero;
+  KcLoader<T, BM, VEC> la;
+  KcLoader<T, BN, VEC> lb;
+  const int ntiles = ke > kb ? (ke - kb + kBK - 1) / kBK : 0;
+  if (ntiles > 0) {
+    la.load(A, lda, A, lda, M, M, i0, kb, ke, tid);
+    lb.load(B, ldb, B2, ldb2, ncol1, N, j0, kb, ke, tid);
+    la.template store<LA>(sA[0], tid);
+    lb.template store<LB>(sB[0], tid);
+  }
+  __syncthreads();
+  for (int it = 0; it < ntiles; ++it) {
+    const int cur = it & 1;
+    const bool more = it + 1 < ntiles;
+    if (more) {
+      const int kn = kb + (it + 1) * kBK;
+      la.load(A, lda, A, lda, M, M, i0, kn, ke, tid);
+      lb.load(B, ldb, B2, ldb2, ncol1, N, j0, kn, ke, tid);
     }
-#pragma unroll
-    for (int r = 0; r < G_BK * G_BN / 256; ++r) {
-      const int idx = tid + r * 256;
-      const int kk = idx & (G_BK - 1), jj = idx / G_BK;
-      const int gj = j0 + jj, gk = k0 + kk;
-      cplx<T> v = zero;
-      if (gj < N && gk < ke) v = gj < ncol1 ? B[(long)gj * ldb + gk] : B2[(long)(gj - ncol1) * ldb2 + gk];
-      sB[kk][jj] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < G_BK; kk += 4) {
-      cplx<T> av[G_WM], bv[G_WN];
-#pragma unroll
-      for (int a = 0; a < G_WM; ++a) av[a] = sA[kk + (lane >> 4)][wm * 16 * G_WM + a * 16 + (lane & 15)];
-#pragma unroll
-      for (int b = 0; b < G_WN; ++b) bv[b] = sB[kk + (lane >> 4)][wn * 16 * G_WN + b * 16 + (lane & 15)];
-#pragma unroll
-      for (int a = 0; a < G_WM; ++a)
-#pragma unroll
-        for (int b = 0; b < G_WN; ++b) {
-          cr[a][b] = MF<T>::mma(av[a].x, bv[b].x, cr[a][b]);
-          cr[a][b] = MF<T>::mma(av[a].y, bv[b].y, cr[a][b]);
-          ci[a][b] = MF<T>::mma(av[a].x, bv[b].y, ci[a][b]);
-          ci[a][b] = MF<T>::mma(-av[a].y, bv[b].x, ci[a][b]);
-        }
-    }
-    __syncthreads();
+    mma_tile<T, WBM, WBN, true>(sA[cur], sB[cur], LA, LB, mo, no, lane, cr, ci);
     if constexpr (std::is_same<T, float>::value) {
-      if ((tile & (G_FLUSH - 1)) == G_FLUSH - 1) {
+      if ((it % kFlush) == kFlush - 1) {
 #pragma unroll
-        for (int a = 0; a < G_WM; ++a)
+        for (int a = 0; a < WBM; ++a)
 #pragma unroll
-          for (int b = 0; b < G_WN; ++b) {
+          for (int b = 0; b < WBN; ++b) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               dr[a][b][r] += (double)cr[a][b][r];
@@ -125,15 +281,20 @@ __global__ __launch_bounds__(256) void k_gemm_cn(const cplx<T>* __restrict__ A, 
           }
       }
     }
+    if (more) {
+      la.template store<LA>(sA[cur ^ 1], tid);
+      lb.template store<LB>(sB[cur ^ 1], tid);
+    }
+    __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < G_WM; ++a)
+  for (int a = 0; a < WBM; ++a)
 #pragma unroll
-    for (int b = 0; b < G_WN; ++b) {
-      const int col = j0 + wn * 16 * G_WN + b * 16 + (lane & 15);
+    for (int b = 0; b < WBN; ++b) {
+      const int col = j0 + no + b * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = i0 + wm * 16 * G_WM + a * 16 + MF<T>::row(lane, r);
+        const int row = i0 + mo + a * 16 + MF<T>::row(lane, r);
         if (row < M && col < N) {
           double2 v;
           v.x = dr[a][b][r] + (double)cr[a][b][r];
@@ -166,57 +327,53 @@ __global__ void k_reduce_parts(const double2* __restrict__ part, int nsplit, int
   if (outT) outT[(long)j * ldoT + i] = mk<T>((T)s.x, (T)s.y);
 }
 
-template <typename T>
+// ------------------------------------------------------------------------------------------
+// nn: out = epilogue(A B).  A: M x K (m contiguous), B: K x N (k contiguous).
+// ------------------------------------------------------------------------------------------
+template <typename T, int BM, int BN, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_nn(const cplx<T>* __restrict__ A, long lda,
                                                  const cplx<T>* __restrict__ B, long ldb, int M, int N, int K,
-                                                 cplx<T>* out, long ldo, EpiH e) {
+                                                 int tiles_n, cplx<T>* out, long ldo, EpiH e) {
+  constexpr int WBM = BM / 32, WBN = BN / 32;
+  constexpr int LA = BM + 1, LB = BN + 1;
   using acc_t = typename MF<T>::acc;
-  __shared__ cplx<T> sA[G_BK][G_BM + 1];
-  __shared__ cplx<T> sB[G_BK][G_BN + 1];
+  __shared__ cplx<T> sA[2][kBK * LA];
+  __shared__ cplx<T> sB[2][kBK * LB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int i0 = blockIdx.x * G_BM, j0 = blockIdx.y * G_BN;
-  acc_t cr[G_WM][G_WN], ci[G_WM][G_WN];
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tm = t / tiles_n, tn = t - tm * tiles_n;  // n fastest: workgroups sharing an A panel are adjacent
+  const int i0 = tm * BM, j0 = tn * BN;
+  const int mo = (wave & 1) * (BM / 2), no = (wave >> 1) * (BN / 2);
+  acc_t cr[WBM][WBN], ci[WBM][WBN];
 #pragma unroll
-  for (int a = 0; a < G_WM; ++a)
+  for (int a = 0; a < WBM; ++a)
 #pragma unroll
-    for (int b = 0; b < G_WN; ++b) {
+    for (int b = 0; b < WBN; ++b) {
       cr[a][b] = acc_t{0, 0, 0, 0};
       ci[a][b] = acc_t{0, 0, 0, 0};
     }
-  const cplx<T> zero = mk<T>(0, 0);
-  for (int k0 = 0; k0 < K; k0 += G_BK) {
-#pragma unroll
-    for (int r = 0; r < G_BK * G_BM / 256; ++r) {
-      const int idx = tid + r * 256;
-      const int ii = idx & (G_BM - 1), kk = idx / G_BM;
-      const int gi = i0 + ii, gk = k0 + kk;
-      sA[kk][ii] = (gi < M && gk < K) ? A[(long)gk * lda + gi] : zero;
+  McLoader<T, BM, VEC> la;
+  KcLoader<T, BN, VEC> lb;
+  const int ntiles = (K + kBK - 1) / kBK;
+  if (ntiles > 0) {
+    la.load(A, lda, M, i0, 0, K, tid);
+    lb.load(B, ldb, B, ldb, N, N, j0, 0, K, tid);
+    la.template store<LA>(sA[0], tid);
+    lb.template store<LB>(sB[0], tid);
+  }
+  __syncthreads();
+  for (int it = 0; it < ntiles; ++it) {
+    const int cur = it & 1;
+    const bool more = it + 1 < ntiles;
+    if (more) {
+      const int kn = (it + 1) * kBK;
+      la.load(A, lda, M, i0, kn, K, tid);
+      lb.load(B, ldb, B, ldb, N, N, j0, kn, K, tid);
     }
-#pragma unroll
-    for (int r = 0; r < G_BK * G_BN / 256; ++r) {
-      const int idx = tid + r * 256;
-      const int kk = idx & (G_BK - 1), jj = idx / G_BK;
-      const int gj = j0 + jj, gk = k0 + kk;
-      sB[kk][jj] = (gj < N && gk < K) ? B[(long)gj * ldb + gk] : zero;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < G_BK; kk += 4) {
-      cplx<T> av[G_WM], bv[G_WN];
-#pragma unroll
-      for (int a = 0; a < G_WM; ++a) av[a] = sA[kk + (lane >> 4)][wm * 16 * G_WM + a * 16 + (lane & 15)];
-#pragma unroll
-      for (int b = 0; b < G_WN; ++b) bv[b] = sB[kk + (lane >> 4)][wn * 16 * G_WN + b * 16 + (lane & 15)];
-#pragma unroll
-      for (int a = 0; a < G_WM; ++a)
-#pragma unroll
-        for (int b = 0; b < G_WN; ++b) {
-          cr[a][b] = MF<T>::mma(av[a].x, bv[b].x, cr[a][b]);
-          cr[a][b] = MF<T>::mma(-av[a].y, bv[b].y, cr[a][b]);
-          ci[a][b] = MF<T>::mma(av[a].x, bv[b].y, ci[a][b]);
-          ci[a][b] = MF<T>::mma(av[a].y, bv[b].x, ci[a][b]);
-        }
+    mma_tile<T, WBM, WBN, false>(sA[cur], sB[cur], LA, LB, mo, no, lane, cr, ci);
+    if (more) {
+      la.template store<LA>(sA[cur ^ 1], tid);
+      lb.template store<LB>(sB[cur ^ 1], tid);
     }
     __syncthreads();
   }
@@ -226,13 +383,13 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const cplx<T>* __restrict__ A, 
   const cplx<T>* Yp = static_cast<const cplx<T>*>(e.Yp);
   const T alpha = (T)e.alpha, cc = (T)e.c, beta = (T)e.beta;
 #pragma unroll
-  for (int a = 0; a < G_WM; ++a)
+  for (int a = 0; a < WBM; ++a)
 #pragma unroll
-    for (int b = 0; b < G_WN; ++b) {
-      const int col = j0 + wn * 16 * G_WN + b * 16 + (lane & 15);
+    for (int b = 0; b < WBN; ++b) {
+      const int col = j0 + no + b * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = i0 + wm * 16 * G_WM + a * 16 + MF<T>::row(lane, r);
+        const int row = i0 + mo + a * 16 + MF<T>::row(lane, r);
         if (row < M && col < N) {
           cplx<T> v = mk<T>(cr[a][b][r], ci[a][b][r]);
           if (e.mode == 1) {
@@ -253,16 +410,56 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const cplx<T>* __restrict__ A, 
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------
+template <typename T> struct CnShape;
+template <> struct CnShape<float> {
+  static constexpr int BM = 128, BN = 64;
+};
+template <> struct CnShape<double> {
+  static constexpr int BM = 64, BN = 64;
+};
+template <typename T> struct NnShape;
+template <> struct NnShape<float> {
+  static constexpr int BM = 128, BN = 128;
+};
+template <> struct NnShape<double> {
+  static constexpr int BM = 128, BN = 64;
+};
+
+static inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+template <typename T>
+static bool vec_ok(const void* p, long ld) {
+  return aligned16(p) && (sizeof(T) == 8 || (ld % 2) == 0);
+}
+
+int gemm_cn_tiles(int M, int N, bool fp64) {
+  const int bm = fp64 ? CnShape<double>::BM : CnShape<float>::BM;
+  const int bn = fp64 ? CnShape<double>::BN : CnShape<float>::BN;
+  return ceil_div(M, bm) * ceil_div(N, bn);
+}
+
 template <typename T>
 hipError_t launch_gemm_cn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const cplx<T>* B2, long ldb2,
                           int ncol1, int M, int N, int K, int nsplit, double2* part, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  constexpr int BM = CnShape<T>::BM, BN = CnShape<T>::BN;
   int kchunk = ceil_div(K, nsplit);
-  kchunk = ceil_div(kchunk, G_BK) * G_BK;
-  if (kchunk <= 0) kchunk = G_BK;
-  dim3 grid(ceil_div(M, G_BM), ceil_div(N, G_BN), nsplit);
-  hipLaunchKernelGGL(k_gemm_cn<T>, grid, dim3(256), 0, s, A, lda, B, ldb, B2 ? B2 : B, ldb2, ncol1, M, N, K,
-                     kchunk, part);
+  kchunk = ceil_div(kchunk, kBK) * kBK;
+  if (kchunk <= 0) kchunk = kBK;
+  const int tm = ceil_div(M, BM), tn = ceil_div(N, BN);
+  const cplx<T>* b2 = B2 ? B2 : B;
+  const long l2 = B2 ? ldb2 : ldb;
+  const bool vec = vec_ok<T>(A, lda) && vec_ok<T>(B, ldb) && vec_ok<T>(b2, l2);
+  dim3 grid(tm * tn * nsplit);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_cn<T, BM, BN, true>), grid, dim3(256), 0, s, A, lda, B, ldb, b2, l2, ncol1, M, N, K,
+                       kchunk, tm, tn, part);
+  else
+    hipLaunchKernelGGL((k_gemm_cn<T, BM, BN, false>), grid, dim3(256), 0, s, A, lda, B, ldb, b2, l2, ncol1, M, N, K,
+                       kchunk, tm, tn, part);
   return hipGetLastError();
 }
 
@@ -280,8 +477,15 @@ template <typename T>
 hipError_t launch_gemm_nn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb, int M, int N, int K,
                           cplx<T>* out, long ldo, const EpiH& e, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid(ceil_div(M, G_BM), ceil_div(N, G_BN));
-  hipLaunchKernelGGL(k_gemm_nn<T>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, out, ldo, e);
+  constexpr int BM = NnShape<T>::BM, BN = NnShape<T>::BN;
+  const int tm = ceil_div(M, BM), tn = ceil_div(N, BN);
+  const bool vec = vec_ok<T>(A, lda) && vec_ok<T>(B, ldb);
+  dim3 grid(tm * tn);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, tn, out, ldo, e);
+  else
+    hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, tn, out, ldo,
+                       e);
   return hipGetLastError();
 }
 

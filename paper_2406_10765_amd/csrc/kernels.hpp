@@ -44,6 +44,8 @@ hipError_t launch_pencil_yfwd(cplx<T>* SB, const cplx<T>* G1, int nbatch, const 
 // --------------------------------------------------------------- GEMM ------
 // C_part[s] = A^H B over the s-th K chunk.  A: K x M, B: K x N (column-major; columns of B
 // with index >= nsplit_col come from B2).  Partials are complex double, [s][N][M].
+// Number of output tiles of the cn kernel for an M x N result (used to choose the K split).
+int gemm_cn_tiles(int M, int N, bool fp64);
 template <typename T>
 hipError_t launch_gemm_cn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const cplx<T>* B2,
                           long ldb2, int ncol1, int M, int N, int K, int nsplit, double2* part, hipStream_t s);

@@ -184,9 +184,9 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
     if (s < 1) s = 1;
     return s;
   };
-  const int tb = (P.nbands + 63) / 64;
-  P.nsplit_proj = P.nproj ? pick_split(((P.nproj + 63) / 64) * tb, P.npw) : 1;
-  P.nsplit_gram = pick_split(tb * ((2 * P.nbands + 63) / 64), P.npw);
+  const bool f64 = P.prec == PW_FP64;
+  P.nsplit_proj = P.nproj ? pick_split(gemm_cn_tiles(P.nproj, P.nbands, f64), P.npw) : 1;
+  P.nsplit_gram = pick_split(gemm_cn_tiles(P.nbands, 2 * P.nbands, f64), P.npw);
 
   // --- arena layout --------------------------------------------------------------
   ArenaLayout& L = P.lay;
