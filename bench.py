@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+# bf16 split products: Gram / projected matrices (4 terms), projectors and rotations (3 terms)
+DEFAULT_MIXED_FLAGS = 2 | 4 | 8
+PEAK_BF16_TFLOPS = 2516.6
 METRIC = "eig-steps/sec & HΨ band-apps/sec, mixed vs FP64 @|Δε|≤1e-5 Ha; p99 latency"
 
 
@@ -131,6 +134,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--flags", type=int, default=None,
+                    help="mixed-precision product flags (bit 2: bf16 Gram, 4: bf16 projectors, 8: bf16 rotation)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -156,7 +161,8 @@ def main():
 
     # ---- mixed precision (the headline) --------------------------------------------------
     t0 = time.time()
-    hm = pw.Handle(cell, pw.PW_MIXED)
+    mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
+    hm = pw.Handle(cell, pw.PW_MIXED, flags=mflags)
     G = hm.gvectors()
     X0 = synth.initial_block(G, cell.L, nb, synth.SEED_X0 + synth.WORKLOADS[args.workload]["index"])
     b = hm.spectrum_bound(20, 1)
@@ -179,6 +185,14 @@ def main():
     band_apps = (m + 1) * nb / (ms_step / 1000.0)
     log(f"mixed: {ms_step:.1f} ms/step, max resid(occ) {res[:cell.nocc].max():.2e}")
 
+    # bf16 split terms executed per real product, by phase
+    nterm = {}
+    if mflags & 4:
+        nterm["proj"] = nterm["nl"] = 3
+    if mflags & 2:
+        nterm["gram"] = 4
+    if mflags & 8:
+        nterm["rotate"] = 3
     phases = {}
     dom, dom_ms = None, -1.0
     for name, st in stats.items():
@@ -190,7 +204,14 @@ def main():
         if amount is not None:
             if kind == "flop":
                 entry["tflops"] = round(amount / (st["ms"] * 1e-3) / 1e12, 2)
-                entry["frac_peak"] = round(entry["tflops"] / PEAK_MFMA_TFLOPS["fp32"], 4)
+                if name in nterm:
+                    entry["dtype"] = "bf16x%d" % nterm[name]
+                    entry["tflops_bf16_executed"] = round(entry["tflops"] * nterm[name], 2)
+                    entry["frac_peak"] = round(entry["tflops"] / PEAK_BF16_TFLOPS, 4)
+                    entry["frac_peak_executed"] = round(entry["tflops_bf16_executed"] / PEAK_BF16_TFLOPS, 4)
+                else:
+                    entry["dtype"] = "fp32"
+                    entry["frac_peak"] = round(entry["tflops"] / PEAK_MFMA_TFLOPS["fp32"], 4)
             else:
                 entry["gbs"] = round(amount / (st["ms"] * 1e-3) / 1e9, 1)
                 entry["frac_peak"] = round(entry["gbs"] / PEAK_HBM_GBS, 4)
@@ -201,7 +222,8 @@ def main():
     amount, kind = phase_work(dom, hm.info, nb, m, args.steps, 4)
     per_launch = amount / stats[dom]["launches"]
     if kind == "flop":
-        roofline = {"bound": "mfma", "kernel": dom, "achieved": d["tflops"], "peak": PEAK_MFMA_TFLOPS["fp32"],
+        peak = PEAK_BF16_TFLOPS if dom in nterm else PEAK_MFMA_TFLOPS["fp32"]
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": d["tflops"], "peak": peak,
                     "unit": "TFLOP/s", "frac": d["frac_peak"], "traffic": None,
                     "algorithmic_per_launch": per_launch, "avg_launch_ms": d["ms_per_launch"]}
     else:
@@ -235,7 +257,7 @@ def main():
                 "band_apps_per_sec": (m + 1) * nb / (ms64 / 1000.0)}
         del hd
         torch.cuda.empty_cache()
-        hm2 = pw.Handle(cell, pw.PW_MIXED)
+        hm2 = pw.Handle(cell, pw.PW_MIXED, flags=mflags)
         e32, r32, _ = hm2.eig_step(Xm.clone(), m, bounds_m[0], bounds_m[1], b)
         nocc = cell.nocc
         accuracy = {"max_abs_deig_occ_mixed_vs_fp64_Ha": float(np.abs(e32[:nocc] - e64[:nocc]).max()),
@@ -265,7 +287,8 @@ def main():
                                f"Ecut {cell.ecut:g} Ha, Gamma point, {G.shape[0]} plane waves, {nb} bands, "
                                f"degree-{m} Chebyshev-filtered Rayleigh-Ritz step, mixed precision",
                    "npw": int(G.shape[0]), "nbands": nb, "degree": m, "ecut_ha": cell.ecut,
-                   "fft_grid": list(int(x) for x in pw.plan(cell, pw.PW_MIXED).fft_n), "precision": "mixed"},
+                   "fft_grid": list(int(x) for x in pw.plan(cell, pw.PW_MIXED).fft_n), "precision": "mixed",
+                   "mixed_flags": mflags},
         "band_apps_per_sec": band_apps,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -55,6 +55,14 @@ typedef enum {
 /* Force the pencil form of the plane stage (three kernels through an HBM intermediate)
    even when a whole FFT plane fits in LDS; for testing that path on small cells. */
 #define PW_FLAG_PENCIL_FFT 1u
+/* PW_MIXED only: form the products with fp32 data split into two bf16 terms each
+   (hi*hi' + hi*lo' + lo*hi' on the bf16 matrix cores, fp32 accumulation; the Gram/projected
+   products also add lo*lo' and move their partial sums to fp64 every 256 plane waves):
+   GRAM = [S | H_s] = Y^H [Y | W];  KB = projector products beta^H Y and beta (D P);
+   ROT = rotations Y C and W C. */
+#define PW_FLAG_BF16_GRAM 2u
+#define PW_FLAG_BF16_KB 4u
+#define PW_FLAG_BF16_ROT 8u
 
 typedef enum {
   PW_FP64 = 0,  /* every product and FFT in double precision */

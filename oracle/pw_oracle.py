@@ -257,7 +257,8 @@ def build_model(L: Sequence[float], tau: np.ndarray, ecut: float, zval: float = 
                 rc: float = 1.0, gauss_c: float = 2.0, sigma: float = 0.8, d0: float = 1.5,
                 d1: float = -0.7, mode_miller: Optional[np.ndarray] = None,
                 mode_amp: Optional[np.ndarray] = None, mode_phase: Optional[np.ndarray] = None,
-                grid: Optional[Sequence[int]] = None, sf_sign: float = -1.0) -> Model:
+                grid: Optional[Sequence[int]] = None, sf_sign: float = -1.0,
+                with_projectors: bool = True) -> Model:
     L = np.asarray(L, float)
     tau = np.asarray(tau, float)
     mm = np.zeros((0, 3), np.int64) if mode_miller is None else np.asarray(mode_miller, np.int64)
@@ -271,12 +272,16 @@ def build_model(L: Sequence[float], tau: np.ndarray, ecut: float, zval: float = 
     vr_c = to_real_space(vg, miller, grid)
     scale = max(1.0, float(np.abs(vr_c).max()))
     assert float(np.abs(vr_c.imag).max()) <= 1e-12 * scale, "V(r) must be real"
-    B = projector_matrix(miller, L, tau, sigma, sf_sign) if (d0 != 0 or d1 != 0) else \
+    have = (d0 != 0 or d1 != 0) and tau.shape[0] > 0
+    B = projector_matrix(miller, L, tau, sigma, sf_sign) if (have and with_projectors) else \
         np.zeros((miller.shape[0], 0), complex)
-    D = np.tile(np.array([d0, d1, d1, d1]), tau.shape[0]) if B.shape[1] else np.zeros(0)
-    return Model(L=L, ecut=ecut, tau=tau, miller=miller, G=G, kin=kin, grid=grid,
-                 vr=vr_c.real.copy(), B=B, D=D, zval=zval, rc=rc, gauss_c=gauss_c,
-                 mode_miller=mm, mode_amp=ma, mode_phase=mp, sf_sign=sf_sign)
+    D = np.tile(np.array([d0, d1, d1, d1]), tau.shape[0]) if have else np.zeros(0)
+    m = Model(L=L, ecut=ecut, tau=tau, miller=miller, G=G, kin=kin, grid=grid,
+              vr=vr_c.real.copy(), B=B, D=D, zval=zval, rc=rc, gauss_c=gauss_c,
+              mode_miller=mm, mode_amp=ma, mode_phase=mp, sf_sign=sf_sign)
+    m.sigma = sigma
+    m.atomwise = have and not with_projectors
+    return m
 
 
 def model_from_cell(cell, **over) -> Model:
@@ -319,6 +324,17 @@ def dense_h(model: Model) -> np.ndarray:
     return H
 
 
+def apply_nonlocal_atomwise(model: Model, X: np.ndarray) -> np.ndarray:
+    """V_NL X = sum_a B_a D (B_a^H X), one atom at a time (Section III-A: the pseudopotential
+    of each atom is applied to every wavefunction).  Never forms the full projector matrix."""
+    out = np.zeros_like(X)
+    d = model.D[:4]
+    for a in range(model.tau.shape[0]):
+        Ba = projector_matrix(model.miller, model.L, model.tau[a:a + 1], model.sigma, model.sf_sign)
+        out += Ba @ (d[:, None] * (Ba.conj().T @ X))
+    return out
+
+
 def apply_h(model: Model, X: np.ndarray) -> np.ndarray:
     """Matrix-free H X: kinetic + FFT local potential + B (D (B^H X))."""
     X = np.asarray(X, complex)
@@ -332,6 +348,8 @@ def apply_h(model: Model, X: np.ndarray) -> np.ndarray:
     if model.B.shape[1]:
         P = model.B.conj().T @ Xb
         out = out + model.B @ (model.D[:, None] * P)
+    elif getattr(model, "atomwise", False):
+        out = out + apply_nonlocal_atomwise(model, Xb)
     return out[:, 0] if one else out
 
 

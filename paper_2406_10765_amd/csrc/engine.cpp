@@ -17,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pw.h"
@@ -132,6 +133,24 @@ struct Engine {
   cplx<T>* u1() const { return h->at<cplx<T>>(P.lay.u1); }
   cplx<T>* zb() const { return h->at<cplx<T>>(P.lay.zb); }
 
+  bool flag(unsigned f) const { return (P.flags & f) != 0; }
+
+  hipError_t cn(bool split16, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const cplx<T>* B2, long ldb2,
+                int ncol1, int M, int N, int K, int nsplit, double2* part, int nterm = 3) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (split16)
+        return launch_gemm_cn_bf16x3(A, lda, B, ldb, B2, ldb2, ncol1, M, N, K, nsplit, part, nterm, h->stream);
+    }
+    return launch_gemm_cn<T>(A, lda, B, ldb, B2, ldb2, ncol1, M, N, K, nsplit, part, h->stream);
+  }
+  hipError_t nn(bool split16, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, int M, int N, int K,
+                cplx<T>* out, long ldo, const EpiH& e) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (split16) return launch_gemm_nn_bf16x3(A, lda, B, ldb, M, N, K, out, ldo, e, h->stream);
+    }
+    return launch_gemm_nn<T>(A, lda, B, ldb, M, N, K, out, ldo, e, h->stream);
+  }
+
   // Local potential part: Z = P_sphere FFT_fwd[V FFT_inv[P_sphere^T Y]] for nb columns.
   pw_status local_part(const cplx<T>* Y, long ldy, cplx<T>* Z, long ldz, int nb) {
     const GridDesc& g = P.g;
@@ -169,8 +188,8 @@ struct Engine {
     cplx<T>* PT = h->at<cplx<T>>(P.lay.pt);
     if (P.nproj > 0) {
       double2* parts = h->at<double2>(P.lay.parts);
-      PW_TIMED(PW_PH_PROJ, launch_gemm_cn<T>(beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw,
-                                             P.nsplit_proj, parts, h->stream));
+      PW_TIMED(PW_PH_PROJ, cn(flag(PW_FLAG_BF16_KB), beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw,
+                              P.nsplit_proj, parts));
       PW_TIMED(PW_PH_PROJ_REDUCE, launch_reduce_parts<T>(parts, P.nsplit_proj, P.nproj, nb,
                                                          h->at<double>(P.lay.dscale), 4, nullptr, 0, PT, P.nproj,
                                                          h->stream));
@@ -187,7 +206,7 @@ struct Engine {
     e.ldz = ldz;
     e.Yp = Yp;
     e.ldp = ldp;
-    PW_TIMED(PW_PH_NL, launch_gemm_nn<T>(beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e, h->stream));
+    PW_TIMED(PW_PH_NL, nn(flag(PW_FLAG_BF16_KB), beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e));
     return PW_OK;
   }
 
@@ -199,7 +218,7 @@ struct Engine {
     EpiH e;
     std::memset(&e, 0, sizeof(e));
     e.mode = 0;
-    PW_TIMED(PW_PH_ROTATE, launch_gemm_nn<T>(A, lda, C, nb, P.npw, nb, nb, out, ldo, e, h->stream));
+    PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), A, lda, C, nb, P.npw, nb, nb, out, ldo, e));
     return PW_OK;
   }
 
@@ -242,8 +261,8 @@ struct Engine {
     // [S | H_s] = Y^H [Y | W]
     double2* parts = h->at<double2>(P.lay.parts);
     double2* SH = h->at<double2>(P.lay.sh);
-    PW_TIMED(PW_PH_GRAM, launch_gemm_cn<T>(Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram, parts,
-                                           h->stream));
+    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
+                            parts, 4));
     double2* S = SH;
     double2* Hs = SH + (size_t)nb * nb;
     h->tbegin();

@@ -51,7 +51,12 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   if (d->natoms < 0 || (d->natoms > 0 && !d->tau)) { *err = "bad atoms"; return PW_EINVAL; }
   if (d->nbands < 1) { *err = "nbands must be >= 1"; return PW_EINVAL; }
   if (d->prec != PW_FP64 && d->prec != PW_MIXED) { *err = "unknown precision"; return PW_EINVAL; }
-  if (d->flags & ~PW_FLAG_PENCIL_FFT) { *err = "unknown flag bits"; return PW_EINVAL; }
+  const unsigned known = PW_FLAG_PENCIL_FFT | PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT;
+  if (d->flags & ~known) { *err = "unknown flag bits"; return PW_EINVAL; }
+  if (d->prec == PW_FP64 && (d->flags & (PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT))) {
+    *err = "bf16 split products need PW_MIXED";
+    return PW_EINVAL;
+  }
   if (d->nmodes < 0 || (d->nmodes > 0 && (!d->mode_miller || !d->mode_amp || !d->mode_phase))) {
     *err = "bad perturbation modes";
     return PW_EINVAL;
@@ -84,6 +89,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   P.mode_amp.assign(d->mode_amp ? d->mode_amp : nullptr, d->mode_amp ? d->mode_amp + d->nmodes : nullptr);
   P.mode_phase.assign(d->mode_phase ? d->mode_phase : nullptr, d->mode_phase ? d->mode_phase + d->nmodes : nullptr);
   P.prec = d->prec;
+  P.flags = d->flags;
   P.real_bytes = d->prec == PW_FP64 ? 8 : 4;
 
   // --- sphere in stick order: n1, then n2, then n3 ascending -------------------
@@ -185,8 +191,12 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
     return s;
   };
   const bool f64 = P.prec == PW_FP64;
-  P.nsplit_proj = P.nproj ? pick_split(gemm_cn_tiles(P.nproj, P.nbands, f64), P.npw) : 1;
-  P.nsplit_gram = pick_split(gemm_cn_tiles(P.nbands, 2 * P.nbands, f64), P.npw);
+  const bool bkb = (P.flags & PW_FLAG_BF16_KB) != 0, bgr = (P.flags & PW_FLAG_BF16_GRAM) != 0;
+  P.nsplit_proj = P.nproj ? pick_split(bkb ? gemm_cn_bf16_tiles(P.nproj, P.nbands) : gemm_cn_tiles(P.nproj, P.nbands, f64),
+                                       P.npw)
+                          : 1;
+  P.nsplit_gram = pick_split(bgr ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands) : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
+                             P.npw);
 
   // --- arena layout --------------------------------------------------------------
   ArenaLayout& L = P.lay;

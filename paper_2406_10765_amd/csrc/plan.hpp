@@ -31,6 +31,7 @@ struct Plan {
   std::vector<int> mode_miller;
   std::vector<double> mode_amp, mode_phase;
   int prec;
+  unsigned flags;
   int real_bytes;  // 8 (FP64) or 4 (mixed)
   // basis
   int nmax[3];

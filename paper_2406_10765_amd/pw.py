@@ -141,6 +141,10 @@ def _check(status: int, handle=None):
 
 
 PW_FLAG_PENCIL_FFT = 1
+PW_FLAG_BF16_GRAM = 2
+PW_FLAG_BF16_KB = 4
+PW_FLAG_BF16_ROT = 8
+PW_FLAG_BF16_ALL = PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT
 
 
 def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,

@@ -1,0 +1,81 @@
+"""Full-size checks at the bench workload (Si512, all 1088 bands in one block, the launch
+configuration bench.py times): sampled columns against the oracle, and properties that hold
+at any size.  The oracle applies the projectors atom by atom so it never holds the 9.7 GB
+projector matrix.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pw_oracle as O
+from paper_2406_10765_amd import pw, synth
+
+pytestmark = pytest.mark.gpu
+
+COLS = [0, 1, 543, 1086, 1087]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def si512():
+    import torch
+    assert torch.cuda.is_available()
+    cell = synth.make_cell("si512")
+    model = O.model_from_cell(cell, with_projectors=False)
+    return cell, model
+
+
+@pytest.mark.parametrize("prec,tol", [(pw.PW_MIXED, 2e-5), (pw.PW_FP64, 1e-12)])
+def test_si512_apply_h_sampled_columns(si512, prec, tol):
+    cell, model = si512
+    say("Si512 apply_h full block, prec", prec)
+    h = pw.Handle(cell, prec)
+    p = pw.permutation_to(model.miller, h.gvectors())
+    X = synth.initial_block(h.gvectors(), cell.L, cell.nbands, 77)
+    if prec == pw.PW_MIXED:
+        X = X.astype(np.complex64).astype(np.complex128)
+    Xd = h.to_device(X)
+    HX = h.apply_h(Xd)
+    out = HX[COLS].cpu().numpy().astype(np.complex128).T[: h.npw]
+    inv = np.argsort(p)
+    ref = O.apply_h(model, X[:, COLS][inv])[p]
+    err = float(np.abs(out - ref).max() / np.abs(ref).max())
+    say("  rel err", err)
+    assert err < tol
+    h.close()
+
+
+def test_si512_mixed_step_properties(si512):
+    import torch
+
+    cell, model = si512
+    say("Si512 mixed step properties")
+    h = pw.Handle(cell, pw.PW_MIXED)
+    p = pw.permutation_to(model.miller, h.gvectors())
+    inv = np.argsort(p)
+    X0 = synth.initial_block(h.gvectors(), cell.L, cell.nbands, synth.SEED_X0 + 2)
+    Xd = h.to_device(X0)
+    b = h.spectrum_bound(20, 1)
+    e0, r0, bnd = h.eig_step(Xd, 0, b=b)
+    e1, r1, bnd = h.eig_step(Xd, 10, bnd[0], bnd[1], b)
+    assert np.all(np.diff(e1) >= 0)
+    assert e1[0] >= -10 and e1[-1] <= b
+    # orthonormality of the whole rotated block (fp64 Gram of the fp32 block, on the device)
+    Y = Xd[:, : h.npw].to(torch.complex128)
+    G = Y.conj() @ Y.T
+    dev = float((G - torch.eye(cell.nbands, dtype=G.dtype, device=G.device)).abs().max())
+    say("  max |X^H X - I|", dev)
+    assert dev < 1e-5
+    # sampled residuals against the oracle's H on the same (fp32) columns
+    cols = [0, 511, 1023]
+    x = Xd[cols].cpu().numpy().astype(np.complex128).T[: h.npw]
+    hx = O.apply_h(model, x[inv])[p]
+    rr = np.linalg.norm(hx - x * e1[cols][None, :], axis=0)
+    say("  resid lib", r1[cols], "oracle", rr)
+    assert np.abs(rr - r1[cols]).max() <= 1e-4 * max(1.0, rr.max())
+    h.close()

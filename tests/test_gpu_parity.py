@@ -208,3 +208,50 @@ def test_bad_block_arguments():
     X = h.empty_block(4)
     with pytest.raises(pw.PWError):
         h.eig_step(X, 3, 1.0, 0.5, 2.0)  # a_lo > a
+
+
+# --- split-bf16 products (mixed precision only) -----------------------------------------
+
+@pytest.mark.parametrize("name,nb", [("si8", 20), ("si64", 9)])
+def test_apply_h_bf16_projectors(name, nb):
+    say("apply_h bf16x3 projectors", name, nb)
+    err, h = apply_case(synth.make_cell(name, modes=True), pw.PW_MIXED, nb, 500 + nb, flags=pw.PW_FLAG_BF16_KB)
+    say("  rel err", err)
+    assert err < 5e-5
+
+
+def test_bf16_flags_need_mixed():
+    with pytest.raises(pw.PWError) as ei:
+        pw.Handle(synth.make_cell("si8"), pw.PW_FP64, flags=pw.PW_FLAG_BF16_GRAM)
+    assert ei.value.status == pw.PW_EINVAL
+
+
+@pytest.mark.parametrize("flags", [pw.PW_FLAG_BF16_GRAM, pw.PW_FLAG_BF16_ALL])
+def test_step_parity_si64_bf16(flags):
+    cell = synth.make_cell("si64")
+    model = O.model_from_cell(cell)
+    hop = lambda X: O.apply_h(model, X)
+    h = pw.Handle(cell, pw.PW_MIXED, flags=flags)
+    p = to_gpu_order(h, model)
+    inv = np.argsort(p)
+    X0g = synth.initial_block(h.gvectors(), cell.L, cell.nbands, synth.SEED_X0 + 1)
+    b = 1.01 * O.lanczos_max(hop, model.npw, 20, seed=3)
+    s1 = O.eig_step(hop, X0g[inv], 0, 0.0, 0.0, b)
+    s2 = O.eig_step(hop, s1.X, 10, s1.a_lo, s1.a, b)
+    Xd = h.to_device(X0g)
+    e1, r1, _ = h.eig_step(Xd, 0, b=b)
+    e2, r2, _ = h.eig_step(Xd, 10, s1.a_lo, s1.a, b)
+    d1 = np.abs(e1 - s1.eig)[: cell.nocc].max()
+    d2 = np.abs(e2 - s2.eig)[: cell.nocc].max()
+    say("si64 bf16 flags", flags, "m=0", d1, "m=10", d2)
+    assert d1 < 1e-5 and d2 < 1e-5
+
+
+def test_solve_si8_bf16_matches_dense(si8_dense):
+    cell, model, lam, V = si8_dense
+    h = pw.Handle(cell, pw.PW_MIXED, flags=pw.PW_FLAG_BF16_ALL)
+    Xd = h.to_device(synth.initial_block(h.gvectors(), cell.L, cell.nbands, synth.SEED_X0))
+    eig, res, steps, conv = h.solve(Xd, cell.nocc, 1e-4, degree=10, b=1.01 * lam[-1])
+    say("solve bf16 steps", steps, "max |de| occ", np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max())
+    assert conv
+    assert np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max() < 1e-5

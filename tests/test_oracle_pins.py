@@ -346,3 +346,13 @@ def test_solve_matches_arpack_si16():
     res = O.solve(hop, X0, b, nocc=cell.nocc, tol=1e-7)
     assert res.converged
     assert np.abs(res.eig[: cell.nocc] - ref).max() < 1e-8
+
+
+def test_atomwise_nonlocal_equals_matrix_form(si8):
+    cell, model, _, _, _ = si8
+    lite = O.model_from_cell(cell, with_projectors=False)
+    assert lite.B.shape[1] == 0 and lite.atomwise
+    X = synth.random_block(model.npw, 3, 12)
+    a = O.apply_h(model, X)
+    b = O.apply_h(lite, X)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
