@@ -167,7 +167,9 @@ struct Engine {
     for (int b0 = 0; b0 < nb; b0 += P.fft_batch) {
       const int nbt = std::min(P.fft_batch, nb - b0);
       PW_TIMED(PW_PH_STICKS_INV, launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, sm));
-      if (P.fl.fused) {
+      if (P.fl.sized) {
+        PW_TIMED(PW_PH_PLANE, launch_plane_n<T>(SB, V, nbt, st, g, tw1, scale, sm));
+      } else if (P.fl.fused) {
         PW_TIMED(PW_PH_PLANE, launch_plane_fused<T>(SB, V, nbt, st, g, tw1, tw2, scale, 0, (T*)nullptr, P.fl, sm));
       } else {
         PW_TIMED(PW_PH_PENCIL_YINV, launch_pencil_yinv<T>(SB, G1, nbt, st, cs, g, tw2, P.fl, sm));
@@ -606,6 +608,7 @@ pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes
   if (h->plan.fl.fused) {
     // allow large dynamic LDS for the fused plane kernel
     pw_allow_large_lds();
+    pw_allow_large_lds_plane_n();
   }
   s = h->plan.prec == PW_FP64 ? Engine<double>(h).setup() : Engine<float>(h).setup();
   if (s != PW_OK) {

@@ -14,6 +14,8 @@
 // Conventions: psi(r_j) = sum_G c_G exp(+i G.r_j) (unnormalised inverse) and
 // c_G = (1/N_r) sum_j f(r_j) exp(-i G.r_j); the 1/N_r is applied in stage 2.
 
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -450,6 +452,7 @@ bool fft_plan_launch(const GridDesc& g, int real_bytes, size_t max_lds, FftLaunc
       L->plane_thr = t;
     }
   }
+  L->sized = L->fused && plane_n_supported(g.n1, g.n2, real_bytes, max_lds) && std::getenv("PW_GENERIC_PLANE") == nullptr;
   L->cx = 16;
   while (L->cx > 1 && L->cx * g.n2 > 4096) L->cx /= 2;
   L->cy = 16;

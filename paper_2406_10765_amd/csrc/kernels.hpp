@@ -10,6 +10,7 @@ struct FftLaunch {
   int spw;        // sticks per workgroup in the z pass
   int stick_thr;  // threads per workgroup in the z pass
   bool fused;     // whole plane in LDS
+  bool sized;     // fused plane with a compile-time size kernel (register FFT stages)
   int plane_thr;
   int cx, cy;     // columns / rows per workgroup in the pencil form
   int col_thr, row_thr;
@@ -29,6 +30,12 @@ template <typename T>
 hipError_t launch_plane_fused(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const GridDesc& g,
                               const cplx<T>* tw1, const cplx<T>* tw2, T scale, int mode, T* vout, const FftLaunch& L,
                               hipStream_t s);
+// Compile-time-size fused plane (square planes of supported sizes); mode 0 only.
+bool plane_n_supported(int n1, int n2, int real_bytes, size_t max_lds);
+template <typename T>
+hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const GridDesc& g,
+                          const cplx<T>* tw, T scale, hipStream_t s);
+void pw_allow_large_lds_plane_n();
 // Pencil form: y inverse (sticks -> G1), x rows (inverse, * V, forward; mode 1: inverse only to vout),
 // y forward (G1 -> sticks * scale).
 template <typename T>
