@@ -229,14 +229,19 @@ class Handle:
         _check(lib().pw_get_gvectors(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), self._h)
         return out
 
+    @property
+    def ld(self) -> int:
+        """Default leading dimension: npw rounded up to 16 (aligned 16-byte loads in every column)."""
+        return (self.npw + 15) // 16 * 16
+
     def empty_block(self, nb: int, ld: Optional[int] = None):
-        ld = self.npw if ld is None else ld
+        ld = self.ld if ld is None else ld
         return self._torch.empty((nb, ld), dtype=self.dtype, device=self.device)
 
     def to_device(self, X: np.ndarray, ld: Optional[int] = None):
         """numpy (npw, nb) in this handle's plane-wave order -> device block (nb, ld)."""
         nb = X.shape[1]
-        t = self._torch.zeros((nb, self.npw if ld is None else ld), dtype=self.dtype)
+        t = self._torch.zeros((nb, self.ld if ld is None else ld), dtype=self.dtype)
         t[:, : self.npw] = self._torch.from_numpy(np.ascontiguousarray(X.T)).to(self.dtype)
         return t.to(self.device)
 

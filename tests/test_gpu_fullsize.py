@@ -30,11 +30,12 @@ def si512():
     return cell, model
 
 
-@pytest.mark.parametrize("prec,tol", [(pw.PW_MIXED, 2e-5), (pw.PW_FP64, 1e-12)])
-def test_si512_apply_h_sampled_columns(si512, prec, tol):
+@pytest.mark.parametrize("prec,flags,tol", [(pw.PW_MIXED, 0, 2e-5), (pw.PW_MIXED, pw.PW_FLAG_BF16_ALL, 5e-5),
+                                            (pw.PW_FP64, 0, 1e-12)])
+def test_si512_apply_h_sampled_columns(si512, prec, flags, tol):
     cell, model = si512
-    say("Si512 apply_h full block, prec", prec)
-    h = pw.Handle(cell, prec)
+    say("Si512 apply_h full block, prec", prec, "flags", flags)
+    h = pw.Handle(cell, prec, flags=flags)
     p = pw.permutation_to(model.miller, h.gvectors())
     X = synth.initial_block(h.gvectors(), cell.L, cell.nbands, 77)
     if prec == pw.PW_MIXED:
@@ -50,12 +51,13 @@ def test_si512_apply_h_sampled_columns(si512, prec, tol):
     h.close()
 
 
-def test_si512_mixed_step_properties(si512):
+@pytest.mark.parametrize("flags", [0, pw.PW_FLAG_BF16_ALL])
+def test_si512_mixed_step_properties(si512, flags):
     import torch
 
     cell, model = si512
-    say("Si512 mixed step properties")
-    h = pw.Handle(cell, pw.PW_MIXED)
+    say("Si512 mixed step properties, flags", flags)
+    h = pw.Handle(cell, pw.PW_MIXED, flags=flags)
     p = pw.permutation_to(model.miller, h.gvectors())
     inv = np.argsort(p)
     X0 = synth.initial_block(h.gvectors(), cell.L, cell.nbands, synth.SEED_X0 + 2)
