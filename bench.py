@@ -124,6 +124,59 @@ def cpu_baseline(cell, nb: int, m: int, sample_bands: int = 32):
     }
 
 
+def serving_leg(n, rate, slots, flags, degree):
+    """Poisson stream of eigen-solves (mixed precision) through the request loop."""
+    import threading
+
+    from paper_2406_10765_amd import pw, synth
+
+    mix = synth.serving_mix(n, rate)
+    srv = pw.Server(48 << 30, max_slots=slots)
+    tickets = [None] * n
+    t_base = srv.clock() + 0.5
+
+    def client():
+        for i, m in enumerate(mix):
+            t = t_base + m["t_arrive"]
+            while srv.clock() < t:
+                time.sleep(min(0.002, max(0.0, t - srv.clock())))
+            c = m["cell"]
+            tickets[i] = srv.submit(c, pw.PW_MIXED, flags, seed=m["seed"], tol=1e-4, max_steps=200,
+                                    degree=degree, nconv=c.nocc, t_arrive=t)
+
+    th = threading.Thread(target=client)
+    th.start()
+    res = [None] * n
+    while any(r is None for r in res):
+        for i, m in enumerate(mix):
+            if res[i] is None and tickets[i] is not None:
+                res[i] = srv.poll(tickets[i], m["cell"].nbands)
+        time.sleep(0.002)
+    th.join()
+    srv.close()
+    lat = np.array([r["t_done"] - r["t_arrive"] for r in res])
+    wait = np.array([r["t_admit"] - r["t_arrive"] for r in res])
+    t0 = min(r["t_arrive"] for r in res)
+    t1 = max(r["t_done"] for r in res)
+    band_apps = sum((1 + (r["steps"] - 1) * (degree + 1) + r["steps"]) * m["cell"].nbands for r, m in zip(res, mix))
+    by, svc = {}, {}
+    for r, m in zip(res, mix):
+        key = "%s_ecut%d" % (m["name"], int(m["cell"].ecut))
+        by.setdefault(m["name"], []).append(r["t_done"] - r["t_arrive"])
+        svc.setdefault(key, []).append(r["t_done"] - r["t_admit"])
+    return {
+        "requests": n, "rate_req_s": rate, "slots": slots,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_queue_wait_s": float(wait.mean()),
+        "throughput_req_s": n / (t1 - t0), "band_apps_per_sec": band_apps / (t1 - t0),
+        "makespan_s": t1 - t0,
+        "converged": int(sum(r["status"] == 0 for r in res)),
+        "mean_steps": float(np.mean([r["steps"] for r in res])),
+        "p50_latency_by_cell_s": {k: float(np.percentile(v, 50)) for k, v in sorted(by.items())},
+        "mean_service_by_cell_s": {k: float(np.mean(v)) for k, v in sorted(svc.items())},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +189,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--flags", type=int, default=None,
                     help="mixed-precision product flags (bit 2: bf16 Gram, 4: bf16 projectors, 8: bf16 rotation)")
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests in the serving mix (0 = skip; the full recipe has 200)")
+    ap.add_argument("--serving-rate", type=float, default=20.0)
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -148,6 +206,11 @@ def main():
     from paper_2406_10765_amd import pw, synth
 
     torch.cuda.set_device(0)
+    if args.serving_only:
+        mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
+        print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate, args.serving_slots,
+                                                 mflags, args.degree)}), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -265,6 +328,12 @@ def main():
         del hm2
         log(f"fp64: {ms64:.1f} ms/step; one-step |de| mixed vs fp64 = {accuracy['max_abs_deig_occ_mixed_vs_fp64_Ha']:.2e}")
 
+    serving = None
+    if args.serving_requests > 0:
+        serving = serving_leg(args.serving_requests, args.serving_rate, args.serving_slots, mflags, m)
+        log(f"serving: p50 {serving['p50_latency_s']:.3f}s p99 {serving['p99_latency_s']:.3f}s "
+            f"throughput {serving['throughput_req_s']:.2f} req/s, converged {serving['converged']}/{serving['requests']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cell, nb, m)
@@ -295,6 +364,7 @@ def main():
         "fp64": fp64,
         "accuracy": accuracy,
         "phases": phases,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

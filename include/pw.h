@@ -163,6 +163,13 @@ pw_status pw_eig_step(pw_handle *h, void *X_dev, void *HX_dev, int nb, int ld, c
                       double *eig_host, double *resid_host, double bounds_out[3]);
 
 /*
+ * Seeded starting block on the device: entry (g, j) = w_g (x + i y) / ||column j||, with x, y
+ * standard normal (Box-Muller on two splitmix64 outputs of the counter (seed, j, g)) and
+ * w_g = 1 / (1 + |G_g|^2).  X_dev: nb columns, ld >= npw.  Asynchronous.
+ */
+pw_status pw_random_block(pw_handle *h, void *X_dev, int nb, int ld, unsigned long long seed);
+
+/*
  * Upper bound estimate of the spectrum: 1.01 * (largest Ritz value + last off-diagonal) of a
  * `steps`-step Lanczos run on H from a seeded random vector.  Host result.
  */
@@ -203,6 +210,59 @@ pw_status pw_reset_stats(pw_handle *h);
 
 pw_status pw_destroy(pw_handle *h);
 const char *pw_last_error(const pw_handle *h);
+
+/*
+ * Serving: a request loop that takes eigen-solves of different cells as they arrive.
+ *
+ * The server owns max_slots host worker threads, each with its own HIP stream (default
+ * priority) on the device current at creation.  Requests are admitted first come, first
+ * served when a slot is free and the request's device footprint (pw_plan footprint plus its
+ * wavefunction block) fits in the free part of the caller's arena (first-fit); a request that
+ * could never fit fails with PW_ENOMEM at submission.  An admitted request builds its own
+ * handle inside its arena range, draws its seeded starting block, estimates the filter bound,
+ * and is advanced step by step (first step degree 0, then `degree`) until the residual norms
+ * of its lowest `nconv` bands are <= tol or max_steps is reached (PW_ENOTCONV, partial
+ * results kept).  Admitted requests run concurrently, so their kernels overlap on the device;
+ * each request's arithmetic is independent of the others (same results alone or in a mix).
+ * pw_submit / pw_poll / pw_server_clock are thread safe.
+ */
+#define PW_SERVER_DRY_RUN 1u /* testing: no device work; a request "runs" for 2 ms per step */
+
+typedef struct {
+  void *arena_dev;      /* device memory shared by all admitted requests (caller-owned) */
+  size_t arena_bytes;
+  int max_slots;        /* concurrent requests, 1..64 */
+  unsigned flags;       /* PW_SERVER_* */
+} pw_server_cfg;
+
+typedef struct {
+  pw_cell_desc cell;            /* copied at submission (tau and mode arrays too) */
+  unsigned long long seed;      /* starting block */
+  double tol;                   /* residual tolerance (Ha) */
+  int max_steps;                /* >= 1 */
+  int degree;                   /* Chebyshev degree of the steps after the first, >= 1 */
+  int nconv;                    /* lowest bands that must converge (0 = all nbands) */
+} pw_request;
+
+typedef struct {
+  pw_status status;     /* PW_OK, PW_ENOTCONV, or the error of the failing call */
+  int nbands, steps;
+  double *eig;          /* caller buffer of nbands doubles (filled by pw_poll), may be NULL */
+  double *resid;        /* caller buffer of nbands doubles, may be NULL */
+  double t_arrive, t_admit, t_done;  /* server clock (s) */
+} pw_result;
+
+typedef struct pw_server_s pw_server;
+
+pw_status pw_server_create(const pw_server_cfg *cfg, pw_server **s);
+/* Seconds since the server was created (monotonic clock). */
+double pw_server_clock(const pw_server *s);
+/* Queue a request; t_arrive on the server clock (NaN = now).  *ticket identifies it. */
+pw_status pw_submit(pw_server *s, const pw_request *r, double t_arrive, unsigned long long *ticket);
+/* PW_PENDING while queued or running; otherwise copies the result (once) and returns PW_OK. */
+pw_status pw_poll(pw_server *s, unsigned long long ticket, pw_result *out);
+/* Waits for running requests to finish; queued requests are dropped. */
+pw_status pw_server_destroy(pw_server *s);
 const char *pw_status_string(pw_status s);
 
 #ifdef __cplusplus

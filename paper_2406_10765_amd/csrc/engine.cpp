@@ -328,6 +328,14 @@ struct Engine {
     return PW_OK;
   }
 
+  pw_status random_block(cplx<T>* X, int nb, int ld, unsigned long long seed) {
+    double* nrm = h->at<double>(P.lay.resid);
+    PW_HIP(launch_random_block<T>(X, ld, P.npw, nb, h->at<T>(P.lay.kin), seed, h->stream));
+    PW_HIP(launch_resid<T>(X, ld, X, ld, (const double*)nullptr, P.npw, nb, nrm, h->stream));
+    PW_HIP(launch_scale_cols_inv<T>(X, ld, P.npw, nb, nrm, h->stream));
+    return PW_OK;
+  }
+
   // Lanczos estimate of the top of the spectrum (filter bound b).
   pw_status spectrum_bound(int steps, unsigned long long seed, double* out) {
     const int n = P.npw;
@@ -682,6 +690,14 @@ pw_status pw_eig_step(pw_handle* h, void* X, void* HX, int nb, int ld, const pw_
                                       bounds_out);
   return Engine<float>(h).eig_step(static_cast<float2*>(X), static_cast<float2*>(HX), nb, ld, q, eig, resid,
                                    bounds_out);
+}
+
+pw_status pw_random_block(pw_handle* h, void* X, int nb, int ld, unsigned long long seed) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  pw_status s = check_block(h, X, nb, ld);
+  if (s != PW_OK) return s;
+  if (h->plan.prec == PW_FP64) return Engine<double>(h).random_block(static_cast<double2*>(X), nb, ld, seed);
+  return Engine<float>(h).random_block(static_cast<float2*>(X), nb, ld, seed);
 }
 
 pw_status pw_spectrum_bound(pw_handle* h, int steps, unsigned long long seed, double* bmax) {

@@ -126,6 +126,12 @@ hipError_t launch_lanczos_step(cplx<T>* w, const cplx<T>* v, const cplx<T>* vp, 
                                hipStream_t s);
 template <typename T>
 hipError_t launch_scale_copy(const cplx<T>* in, cplx<T>* out, double scale, int n, hipStream_t s);
+// Seeded random block (see pw_random_block) and per-column scaling by 1 / norm.
+template <typename T>
+hipError_t launch_random_block(cplx<T>* X, long ld, int npw, int nb, const T* kin, unsigned long long seed,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_scale_cols_inv(cplx<T>* X, long ld, int npw, int nb, const double* norms, hipStream_t s);
 // Opt the fused plane kernels in to the full LDS of a workgroup.
 void pw_allow_large_lds();
 

@@ -144,14 +144,15 @@ __global__ __launch_bounds__(256) void k_resid(const cplx<T>* __restrict__ W, lo
                                                double* __restrict__ resid) {
   __shared__ double red[4];
   const int j = blockIdx.x;
-  const double l = lam[j];
+  const double l = lam ? lam[j] : 0.0;
   const cplx<T>* w = W + (long)j * ldw;
   const cplx<T>* x = X + (long)j * ldx;
+  const double lj = lam ? l : 0.0;
   double s = 0.0;
   for (int i = threadIdx.x; i < rows; i += blockDim.x) {
     const cplx<T> a = w[i], b = x[i];
-    const double rx = (double)a.x - l * (double)b.x;
-    const double ry = (double)a.y - l * (double)b.y;
+    const double rx = (double)a.x - lj * (double)b.x;
+    const double ry = (double)a.y - lj * (double)b.y;
     s += rx * rx + ry * ry;
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
@@ -221,6 +222,56 @@ hipError_t launch_scale_copy(const cplx<T>* in, cplx<T>* out, double scale, int 
   return hipGetLastError();
 }
 
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+template <typename T>
+__global__ void k_random_block(cplx<T>* __restrict__ X, long ld, int npw, int nb, const T* __restrict__ kin,
+                               unsigned long long seed) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)npw * nb) return;
+  const int j = (int)(idx / npw), g = (int)(idx - (long)j * npw);
+  const unsigned long long c = splitmix64(seed ^ splitmix64(((unsigned long long)j << 32) | (unsigned)g));
+  const unsigned long long d = splitmix64(c);
+  const double u1 = ((c >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double u2 = ((d >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double r = sqrt(-2.0 * log(u1)) / (1.0 + 2.0 * (double)kin[g]);
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  X[(long)j * ld + g] = mk<T>((T)(r * cs), (T)(r * sn));
+}
+
+template <typename T>
+__global__ void k_scale_cols_inv(cplx<T>* __restrict__ X, long ld, int npw, int nb, const double* __restrict__ nrm) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)npw * nb) return;
+  const int j = (int)(idx / npw), g = (int)(idx - (long)j * npw);
+  const T s = (T)(1.0 / nrm[j]);
+  cplx<T> v = X[(long)j * ld + g];
+  X[(long)j * ld + g] = mk<T>(v.x * s, v.y * s);
+}
+
+template <typename T>
+hipError_t launch_random_block(cplx<T>* X, long ld, int npw, int nb, const T* kin, unsigned long long seed,
+                               hipStream_t s) {
+  const long n = (long)npw * nb;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_random_block<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, X, ld, npw, nb, kin, seed);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale_cols_inv(cplx<T>* X, long ld, int npw, int nb, const double* norms, hipStream_t s) {
+  const long n = (long)npw * nb;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_cols_inv<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, X, ld, npw, nb, norms);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_fill_zero(cplx<T>* p, long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -286,6 +337,8 @@ hipError_t launch_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, 
   template hipError_t launch_lanczos_step<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, double, int, double*, \
                                              hipStream_t);                                                      \
   template hipError_t launch_scale_copy<T>(const cplx<T>*, cplx<T>*, double, int, hipStream_t);                 \
+  template hipError_t launch_random_block<T>(cplx<T>*, long, int, int, const T*, unsigned long long, hipStream_t); \
+  template hipError_t launch_scale_cols_inv<T>(cplx<T>*, long, int, int, const double*, hipStream_t);          \
   template hipError_t launch_resid<T>(const cplx<T>*, long, const cplx<T>*, long, const double*, int, int,      \
                                       double*, hipStream_t);
 PW_INST_MISC(float)

@@ -61,6 +61,16 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
     *err = "bad perturbation modes";
     return PW_EINVAL;
   }
+  for (int k = 0; k < d->nmodes; ++k)
+    if (!std::isfinite(d->mode_amp[k]) || !std::isfinite(d->mode_phase[k])) {
+      *err = "non-finite perturbation mode";
+      return PW_EINVAL;
+    }
+  if (!std::isfinite(d->zval) || !std::isfinite(d->rc) || !std::isfinite(d->gauss_c) || !std::isfinite(d->beta_sigma) ||
+      !std::isfinite(d->d0) || !std::isfinite(d->d1)) {
+    *err = "non-finite pseudopotential parameter";
+    return PW_EINVAL;
+  }
   const bool have_proj = (d->d0 != 0.0 || d->d1 != 0.0) && d->natoms > 0;
   if (have_proj && !(d->beta_sigma > 0.0)) { *err = "beta_sigma must be positive"; return PW_EINVAL; }
   if (d->natoms > 0 && d->zval != 0.0 && !(d->rc > 0.0)) { *err = "rc must be positive"; return PW_EINVAL; }

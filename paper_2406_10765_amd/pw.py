@@ -82,6 +82,25 @@ class PhaseStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_longlong), ("ms", ctypes.c_double)]
 
 
+PW_SERVER_DRY_RUN = 1
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("arena_dev", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
+                ("flags", ctypes.c_uint)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("cell", CellDesc), ("seed", ctypes.c_ulonglong), ("tol", ctypes.c_double),
+                ("max_steps", ctypes.c_int), ("degree", ctypes.c_int), ("nconv", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("nbands", ctypes.c_int), ("steps", ctypes.c_int),
+                ("eig", ctypes.POINTER(ctypes.c_double)), ("resid", ctypes.POINTER(ctypes.c_double)),
+                ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 class PWError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -120,12 +139,19 @@ def lib() -> ctypes.CDLL:
         "pw_set_timing": ([vp, ctypes.c_int]),
         "pw_get_stats": ([vp, P(PhaseStat)]),
         "pw_reset_stats": ([vp]),
+        "pw_random_block": ([vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_ulonglong]),
         "pw_destroy": ([vp]),
+        "pw_server_create": ([P(ServerCfg), P(vp)]),
+        "pw_submit": ([vp, P(Request), ctypes.c_double, P(ctypes.c_ulonglong)]),
+        "pw_poll": ([vp, ctypes.c_ulonglong, P(Result)]),
+        "pw_server_destroy": ([vp]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    L.pw_server_clock.argtypes = [vp]
+    L.pw_server_clock.restype = ctypes.c_double
     L.pw_last_error.argtypes = [vp]
     L.pw_last_error.restype = ctypes.c_char_p
     L.pw_status_string.argtypes = [ctypes.c_int]
@@ -280,6 +306,12 @@ class Handle:
                                  eig.ctypes.data_as(dp), res.ctypes.data_as(dp), bnd.ctypes.data_as(dp)), self._h)
         return eig, res, bnd
 
+    def random_block(self, nb: int, seed: int, ld: Optional[int] = None):
+        """Seeded starting block generated on the device."""
+        X = self.empty_block(nb, ld)
+        _check(lib().pw_random_block(self._h, ctypes.c_void_p(X.data_ptr()), nb, int(X.stride(0)), seed), self._h)
+        return X
+
     def spectrum_bound(self, steps: int = 20, seed: int = 1) -> float:
         out = ctypes.c_double()
         _check(lib().pw_spectrum_bound(self._h, steps, seed, ctypes.byref(out)), self._h)
@@ -318,3 +350,60 @@ def permutation_to(miller_from: np.ndarray, miller_to: np.ndarray) -> np.ndarray
     if not np.array_equal(kf[p], kt):
         raise ValueError("Miller sets differ")
     return p
+
+
+class Server:
+    """Request loop (pw_server_*).  The arena is a torch uint8 device tensor unless dry_run."""
+
+    def __init__(self, arena_bytes: int, max_slots: int, dry_run: bool = False):
+        self._arena = None
+        if dry_run:
+            ptr = 1 << 20  # never dereferenced
+        else:
+            import torch
+
+            self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+            ptr = self._arena.data_ptr()
+        cfg = ServerCfg(ctypes.c_void_p(ptr), ctypes.c_size_t(int(arena_bytes)), int(max_slots),
+                        PW_SERVER_DRY_RUN if dry_run else 0)
+        s = ctypes.c_void_p()
+        _check(lib().pw_server_create(ctypes.byref(cfg), ctypes.byref(s)))
+        self._s = s
+
+    def clock(self) -> float:
+        return float(lib().pw_server_clock(self._s))
+
+    def submit(self, cell, prec: int = PW_MIXED, flags: int = 0, seed: int = 1, tol: float = 1e-4,
+               max_steps: int = 200, degree: int = 10, nconv: int = 0, t_arrive: float = float("nan"),
+               nbands: Optional[int] = None) -> int:
+        d, keep = make_desc(cell, prec, nbands, (0, 0, 0), flags)
+        r = Request(d, seed, tol, max_steps, degree, nconv)
+        t = ctypes.c_ulonglong()
+        _check(lib().pw_submit(self._s, ctypes.byref(r), float(t_arrive), ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int, nbands: int):
+        """None while pending; else a dict with status, eig, resid, steps and times."""
+        eig = np.empty(nbands)
+        res = np.empty(nbands)
+        out = Result()
+        dp = ctypes.POINTER(ctypes.c_double)
+        out.eig = eig.ctypes.data_as(dp)
+        out.resid = res.ctypes.data_as(dp)
+        st = lib().pw_poll(self._s, ticket, ctypes.byref(out))
+        if st == PW_PENDING:
+            return None
+        _check(st)
+        return {"status": out.status, "eig": eig[: out.nbands], "resid": res[: out.nbands], "steps": out.steps,
+                "t_arrive": out.t_arrive, "t_admit": out.t_admit, "t_done": out.t_done}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().pw_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

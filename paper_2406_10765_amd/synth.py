@@ -204,3 +204,24 @@ def silicon_cell(ncells: Sequence[int], ecut: float, nbands: Optional[int] = Non
     nat = tau.shape[0]
     return Cell(L=L, tau=tau, ecut=ecut, nbands=2 * nat + 8 if nbands is None else nbands,
                 pseudo=pseudo, modes=md)
+
+
+SERVING_CELLS = {"si8": (1, 1, 1), "si16": (1, 1, 2), "si64": (2, 2, 2), "si216": (3, 3, 3)}
+
+
+def serving_mix(n_requests: int = 200, rate: float = 20.0, seed: int = SEED_ARRIVALS):
+    """Poisson arrivals (mean `rate` per second) of eigen-solves; each request draws its cell
+    uniformly from Si8, Si16, Si64, Si216, its cutoff uniformly from {10, 15, 20} Ha, and has
+    2 N + 8 bands and its own seeded displacements."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    t = np.cumsum(gaps)
+    names = list(SERVING_CELLS)
+    which = rng.integers(0, len(names), size=n_requests)
+    ecut = rng.choice(np.array([10.0, 15.0, 20.0]), size=n_requests)
+    out = []
+    for i in range(n_requests):
+        name = names[int(which[i])]
+        cell = silicon_cell(SERVING_CELLS[name], float(ecut[i]), disp_seed=SEED_REQUEST + i)
+        out.append({"t_arrive": float(t[i]), "name": name, "cell": cell, "seed": SEED_REQUEST + i})
+    return out
