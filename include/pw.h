@@ -98,6 +98,9 @@ typedef struct {
                                 otherwise must satisfy that bound and be 2^p 3^q (else PW_EINVAL) */
   int prec;                  /* pw_precision */
   unsigned flags;            /* bitwise OR of PW_FLAG_* (0 = defaults) */
+  int filter_block;          /* bands per block of the filter and of H applications; 0 = all bands
+                                while three full-size work blocks take <= 64 GiB, else blocks whose
+                                three work blocks take <= 16 GiB (a multiple of 64 bands) */
 } pw_cell_desc;
 
 typedef struct {
@@ -110,6 +113,7 @@ typedef struct {
   int nbands;
   int prec;
   int fused_planes;           /* 1 when each FFT plane is transformed inside LDS */
+  int filter_block;           /* bands per filter block (== nbands: one block) */
 } pw_info;
 
 typedef struct {

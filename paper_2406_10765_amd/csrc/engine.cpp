@@ -213,7 +213,86 @@ struct Engine {
   }
 
   pw_status apply_h(const cplx<T>* X, cplx<T>* HX, int nb, int ld) {
-    return hop(X, ld, nb, HX, ld, HX, ld, 1.0, 0.0, 0.0, nullptr, 0);
+    for (int c0 = 0; c0 < nb; c0 += P.nbb) {
+      const int w = std::min(P.nbb, nb - c0);
+      pw_status s = hop(X + (long)c0 * ld, ld, w, HX + (long)c0 * ld, ld, HX + (long)c0 * ld, ld, 1.0, 0.0, 0.0,
+                        nullptr, 0);
+      if (s != PW_OK) return s;
+    }
+    return PW_OK;
+  }
+
+  // Chebyshev filter of w columns Y0 (ld0) in place: on return the columns hold Y_m.
+  // Uses u0, u1 and zb (nbb columns each).
+  pw_status filter_block(cplx<T>* Y0, long ld0, int w, const pw_step_params& prm) {
+    const int m = prm.degree;
+    const long ldw = P.ldw;
+    if (m < 1) return PW_OK;
+    const double e = 0.5 * (prm.b - prm.a), c = 0.5 * (prm.b + prm.a);
+    const double s1 = e / (prm.a_lo - c), tau = 2.0 / s1;
+    pw_status s = hop(Y0, ld0, w, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0);
+    if (s != PW_OK) return s;
+    const cplx<T>* prev = Y0;
+    long ldprev = ld0;
+    cplx<T>* cur = u1();
+    double sg = s1;
+    for (int k = 1; k < m; ++k) {
+      const double sn = 1.0 / (tau - sg);
+      cplx<T>* dst = (prev == Y0) ? u0() : const_cast<cplx<T>*>(prev);
+      s = hop(cur, ldw, w, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev);
+      if (s != PW_OK) return s;
+      prev = cur;
+      ldprev = ldw;
+      cur = dst;
+      sg = sn;
+    }
+    PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(cur, ldw, Y0, ld0, P.npw, w, h->stream));
+    return PW_OK;
+  }
+
+  // Band-blocked step: the filter and W = H Y run on column blocks; residuals from W C - X (C Lambda).
+  pw_status eig_step_blocked(cplx<T>* X, cplx<T>* HX, int nb, int ld, const pw_step_params& prm, double* eig_host,
+                             double* resid_host, double* bounds_out) {
+    const long ldw = P.ldw;
+    cplx<T>* W = h->at<cplx<T>>(P.lay.wf);
+    pw_status s;
+    for (int c0 = 0; c0 < nb; c0 += P.nbb) {
+      const int w = std::min(P.nbb, nb - c0);
+      s = filter_block(X + (long)c0 * ld, ld, w, prm);
+      if (s != PW_OK) return s;
+      s = hop(X + (long)c0 * ld, ld, w, W + (long)c0 * ldw, ldw, zb(), ldw, 1.0, 0.0, 0.0, nullptr, 0);
+      if (s != PW_OK) return s;
+    }
+    s = project_solve(X, ld, W, ldw, nb);
+    if (s != PW_OK) return s;
+    const cplx<T>* C = coeffs(nb);
+    double* eig_d = h->at<double>(P.lay.eig);
+    double* resid_d = h->at<double>(P.lay.resid);
+    // CL = -C diag(lambda)
+    cplx<T>* CL = h->at<cplx<T>>(P.lay.ct2);
+    double2* Hs = h->at<double2>(P.lay.sh) + (size_t)nb * nb;
+    PW_TIMED(PW_PH_OTHER, launch_scale_cols_lam<T>(Hs, nb, CL, nb, nb, eig_d, -1.0, h->stream));
+    EpiH st;
+    std::memset(&st, 0, sizeof(st));
+    for (int c0 = 0; c0 < nb; c0 += P.nbb) {
+      const int w = std::min(P.nbb, nb - c0);
+      // zb = W C[:, blk];  u0 = X CL[:, blk] + zb;  resid = ||u0 columns||
+      PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), W, ldw, C + (long)c0 * nb, nb, P.npw, w, nb, zb(), ldw, st));
+      EpiH ad = st;
+      ad.mode = 2;
+      ad.Zl = zb();
+      ad.ldz = ldw;
+      PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), X, ld, CL + (long)c0 * nb, nb, P.npw, w, nb, u0(), ldw, ad));
+      PW_TIMED(PW_PH_RESID, launch_resid<T>(u0(), ldw, u0(), ldw, (const double*)nullptr, P.npw, w, resid_d + c0,
+                                            h->stream));
+      if (prm.want_hx && HX) {
+        PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(zb(), ldw, HX + (long)c0 * ld, ld, P.npw, w, h->stream));
+      }
+    }
+    // X' = X C into W's storage, then back into X
+    PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), X, ld, C, nb, P.npw, nb, nb, W, ldw, st));
+    PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(W, ldw, X, ld, P.npw, nb, h->stream));
+    return finish(nb, eig_host, resid_host, bounds_out, prm.b);
   }
 
   pw_status rotate(const cplx<T>* A, long lda, const cplx<T>* C, int nb, cplx<T>* out, long ldo) {
@@ -226,6 +305,7 @@ struct Engine {
 
   pw_status eig_step(cplx<T>* X, cplx<T>* HX, int nb, int ld, const pw_step_params& prm, double* eig_host,
                      double* resid_host, double* bounds_out) {
+    if (P.nbb < P.nbands) return eig_step_blocked(X, HX, nb, ld, prm, eig_host, resid_host, bounds_out);
     const int m = prm.degree;
     double bmax = prm.b;
     const long ldw = P.ldw;
@@ -260,44 +340,10 @@ struct Engine {
     cplx<T>* W = dead;
     s = hop(Y, ldy, nb, W, ldw, zb(), ldw, 1.0, 0.0, 0.0, nullptr, 0);
     if (s != PW_OK) return s;
-    // [S | H_s] = Y^H [Y | W]
-    double2* parts = h->at<double2>(P.lay.parts);
-    double2* SH = h->at<double2>(P.lay.sh);
-    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
-                            parts, 4));
-    double2* S = SH;
-    double2* Hs = SH + (size_t)nb * nb;
-    h->tbegin();
-    PW_HIP(launch_reduce_parts<T>(parts, P.nsplit_gram, nb, 2 * nb, nullptr, 0, SH, nb, (cplx<T>*)nullptr, 0,
-                                  h->stream));
-    PW_HIP(launch_hermitize(S, nb, nb, h->stream));
-    PW_HIP(launch_hermitize(Hs, nb, nb, h->stream));
-    h->tend(PW_PH_GRAM_REDUCE);
-    // FP64 generalised eigensolve: Hs C = S C diag(lambda), C^H S C = I
+    s = project_solve(Y, ldy, W, ldw, nb);
+    if (s != PW_OK) return s;
+    const cplx<T>* C = coeffs(nb);
     double* eig_d = h->at<double>(P.lay.eig);
-    int* info_d = h->at<int>(P.lay.info);
-    h->tbegin();
-    rocblas_status rs = rocsolver_zhegvd(h->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, nb,
-                                         reinterpret_cast<rocblas_double_complex*>(Hs), nb,
-                                         reinterpret_cast<rocblas_double_complex*>(S), nb, eig_d,
-                                         h->at<double>(P.lay.ework), info_d);
-    h->tend(PW_PH_EIGSOLVE);
-    if (rs != rocblas_status_success)
-      return fail(h, PW_EDEVICE, std::string("rocsolver_zhegvd: ") + rocblas_status_to_string(rs));
-    int info = 0;
-    PW_HIP(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    PW_HIP(hipStreamSynchronize(h->stream));
-    if (info > nb) return fail(h, PW_ENOTPD, "Cholesky of the Gram matrix failed (rank-deficient block)");
-    if (info > 0) return fail(h, PW_ENUMERIC, "dense eigensolver did not converge");
-    // C in the compute precision
-    const cplx<T>* C;
-    if constexpr (sizeof(T) == 8) {
-      C = reinterpret_cast<const cplx<T>*>(Hs);
-    } else {
-      cplx<T>* ct = h->at<cplx<T>>(P.lay.ct);
-      PW_TIMED(PW_PH_OTHER, launch_convert_c64_to<T>(Hs, nb, ct, nb, nb, nb, h->stream));
-      C = ct;
-    }
     // X' = Y C (never in place), W' = W C
     cplx<T>* Wr = (prm.want_hx && HX) ? HX : zb();
     const long ldwr = (prm.want_hx && HX) ? ld : ldw;
@@ -313,6 +359,60 @@ struct Engine {
     if (s != PW_OK) return s;
     double* resid_d = h->at<double>(P.lay.resid);
     PW_TIMED(PW_PH_RESID, launch_resid<T>(Wr, ldwr, X, ld, eig_d, P.npw, nb, resid_d, h->stream));
+    return finish(nb, eig_host, resid_host, bounds_out, bmax);
+  }
+
+  // [S | H_s] = Y^H [Y | W], Hermitian parts, FP64 generalised eigensolve (C in the H_s storage).
+  pw_status project_solve(const cplx<T>* Y, long ldy, const cplx<T>* W, long ldw, int nb) {
+    double2* parts = h->at<double2>(P.lay.parts);
+    double2* SH = h->at<double2>(P.lay.sh);
+    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
+                            parts, 4));
+    double2* S = SH;
+    double2* Hs = SH + (size_t)nb * nb;
+    h->tbegin();
+    PW_HIP(launch_reduce_parts<T>(parts, P.nsplit_gram, nb, 2 * nb, nullptr, 0, SH, nb, (cplx<T>*)nullptr, 0,
+                                  h->stream));
+    PW_HIP(launch_hermitize(S, nb, nb, h->stream));
+    PW_HIP(launch_hermitize(Hs, nb, nb, h->stream));
+    h->tend(PW_PH_GRAM_REDUCE);
+    // Hs C = S C diag(lambda), C^H S C = I
+    double* eig_d = h->at<double>(P.lay.eig);
+    int* info_d = h->at<int>(P.lay.info);
+    h->tbegin();
+    rocblas_status rs = rocsolver_zhegvd(h->blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, nb,
+                                         reinterpret_cast<rocblas_double_complex*>(Hs), nb,
+                                         reinterpret_cast<rocblas_double_complex*>(S), nb, eig_d,
+                                         h->at<double>(P.lay.ework), info_d);
+    h->tend(PW_PH_EIGSOLVE);
+    if (rs != rocblas_status_success)
+      return fail(h, PW_EDEVICE, std::string("rocsolver_zhegvd: ") + rocblas_status_to_string(rs));
+    int info = 0;
+    PW_HIP(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    PW_HIP(hipStreamSynchronize(h->stream));
+    if (info > nb) return fail(h, PW_ENOTPD, "Cholesky of the Gram matrix failed (rank-deficient block)");
+    if (info > 0) return fail(h, PW_ENUMERIC, "dense eigensolver did not converge");
+    return PW_OK;
+  }
+
+  // Eigenvector coefficients C in the compute precision.
+  const cplx<T>* coeffs(int nb) {
+    double2* Hs = h->at<double2>(P.lay.sh) + (size_t)nb * nb;
+    if constexpr (sizeof(T) == 8) {
+      return reinterpret_cast<const cplx<T>*>(Hs);
+    } else {
+      cplx<T>* ct = h->at<cplx<T>>(P.lay.ct);
+      h->tbegin();
+      (void)launch_convert_c64_to<T>(Hs, nb, ct, nb, nb, nb, h->stream);
+      h->tend(PW_PH_OTHER);
+      return ct;
+    }
+  }
+
+  pw_status finish(int nb, double* eig_host, double* resid_host, double* bounds_out, double bmax) {
+    double* eig_d = h->at<double>(P.lay.eig);
+    double* resid_d = h->at<double>(P.lay.resid);
+    PW_HIP(hipGetLastError());
     PW_HIP(hipMemcpyAsync(eig_host, eig_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
     PW_HIP(hipMemcpyAsync(resid_host, resid_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
     PW_HIP(hipStreamSynchronize(h->stream));
@@ -539,6 +639,7 @@ static void fill_info(const Plan& p, pw_info* out) {
   out->nbands = p.nbands;
   out->prec = p.prec;
   out->fused_planes = p.fl.fused ? 1 : 0;
+  out->filter_block = p.nbb;
 }
 
 pw_status pw_plan(const pw_cell_desc* desc, pw_info* out) {

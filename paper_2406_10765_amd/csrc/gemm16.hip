@@ -464,6 +464,11 @@ __global__ __launch_bounds__(256) void k_gemm_nn_bf16x3(const float2* __restrict
               v.y -= beta * p.y;
             }
           }
+          if (e.mode == 2) {
+            const auto z = Zl[(long)col * e.ldz + row];
+            v.x += z.x;
+            v.y += z.y;
+          }
           out[(long)col * ldo + row] = v;
         }
       }

@@ -67,7 +67,7 @@ hipError_t launch_reduce_parts(const double2* part, int nsplit, int M, int N, co
 //   out = alpha * ((kin_i - c) Y + Zl + acc) - beta * Yp      (EPI_H)
 //   out = acc                                                  (EPI_STORE)
 struct EpiH {
-  int mode;  // 0 = store, 1 = H / Chebyshev update
+  int mode;  // 0 = store, 1 = H / Chebyshev update, 2 = out = acc + Zl
   double alpha, c, beta;
   const void* kin;  // T[M]
   const void* Y;
@@ -113,6 +113,10 @@ hipError_t launch_convert_c64_to(const double2* in, long ldi, cplx<T>* out, long
 template <typename T>
 hipError_t launch_copy_cols(const cplx<T>* in, long ldi, cplx<T>* out, long ldo, int rows, int cols,
                             hipStream_t s);
+// out[:, j] = s * lam[j] * in[:, j] (complex double in, T out), n x n
+template <typename T>
+hipError_t launch_scale_cols_lam(const double2* in, long ldi, cplx<T>* out, long ldo, int n, const double* lam,
+                                 double s, hipStream_t st);
 // Hermitian part: A <- (A + A^H)/2, n x n complex double
 hipError_t launch_hermitize(double2* A, long lda, int n, hipStream_t s);
 // r_j = || W_j - lam_j X_j ||_2 with double accumulation; flag[0] |= non-finite seen

@@ -120,6 +120,17 @@ __global__ void k_copy_cols(const cplx<T>* __restrict__ in, long ldi, cplx<T>* _
   out[(long)j * ldo + i] = in[(long)j * ldi + i];
 }
 
+template <typename T>
+__global__ void k_scale_cols_lam(const double2* __restrict__ in, long ldi, cplx<T>* __restrict__ out, long ldo, int n,
+                                 const double* __restrict__ lam, double sc) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * n) return;
+  const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
+  const double f = sc * lam[j];
+  const double2 v = in[(long)j * ldi + i];
+  out[(long)j * ldo + i] = mk<T>((T)(f * v.x), (T)(f * v.y));
+}
+
 __global__ void k_hermitize(double2* A, long lda, int n) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)n * n) return;
@@ -313,6 +324,15 @@ hipError_t launch_copy_cols(const cplx<T>* in, long ldi, cplx<T>* out, long ldo,
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_scale_cols_lam(const double2* in, long ldi, cplx<T>* out, long ldo, int n, const double* lam,
+                                 double sc, hipStream_t st) {
+  const long m = (long)n * n;
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_cols_lam<T>, dim3(ceil_div(m, 256)), dim3(256), 0, st, in, ldi, out, ldo, n, lam, sc);
+  return hipGetLastError();
+}
+
 hipError_t launch_hermitize(double2* A, long lda, int n, hipStream_t s) {
   const long m = (long)n * n;
   if (m <= 0) return hipSuccess;
@@ -339,6 +359,8 @@ hipError_t launch_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, 
   template hipError_t launch_scale_copy<T>(const cplx<T>*, cplx<T>*, double, int, hipStream_t);                 \
   template hipError_t launch_random_block<T>(cplx<T>*, long, int, int, const T*, unsigned long long, hipStream_t); \
   template hipError_t launch_scale_cols_inv<T>(cplx<T>*, long, int, int, const double*, hipStream_t);          \
+  template hipError_t launch_scale_cols_lam<T>(const double2*, long, cplx<T>*, long, int, const double*, double,  \
+                                               hipStream_t);                                                     \
   template hipError_t launch_resid<T>(const cplx<T>*, long, const cplx<T>*, long, const double*, int, int,      \
                                       double*, hipStream_t);
 PW_INST_MISC(float)

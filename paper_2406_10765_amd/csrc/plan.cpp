@@ -182,6 +182,21 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
     return PW_EINVAL;
   }
 
+  // --- filter blocking -------------------------------------------------------------
+  {
+    const size_t col = (size_t)P.ldw * 2 * P.real_bytes;
+    if (d->filter_block < 0) { *err = "filter_block must be >= 0"; return PW_EINVAL; }
+    if (d->filter_block > 0) {
+      P.nbb = std::min(d->filter_block, P.nbands);
+    } else if (3 * col * (size_t)P.nbands <= (64ull << 30)) {
+      P.nbb = P.nbands;
+    } else {
+      long b = (long)((16ull << 30) / (3 * col)) / 64 * 64;
+      if (b < 64) b = 64;
+      P.nbb = (int)std::min<long>(b, P.nbands);
+    }
+  }
+
   // --- batching ------------------------------------------------------------------
   const size_t cb = 2 * (size_t)P.real_bytes;
   const size_t per_band_sb = (size_t)P.nst * g.n3 * cb;
@@ -190,7 +205,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   if (const char* e = std::getenv("PW_FFT_BATCH_MB")) budget = (size_t)std::atol(e) << 20;
   int fb = (int)(budget / (per_band_sb + per_band_g1));
   if (fb < 1) fb = 1;
-  if (fb > P.nbands) fb = P.nbands;
+  if (fb > P.nbb) fb = P.nbb;
   P.fft_batch = fb;
   auto pick_split = [](int tiles, int K) {
     int s = (2048 + tiles - 1) / tiles;
@@ -202,7 +217,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   };
   const bool f64 = P.prec == PW_FP64;
   const bool bkb = (P.flags & PW_FLAG_BF16_KB) != 0, bgr = (P.flags & PW_FLAG_BF16_GRAM) != 0;
-  P.nsplit_proj = P.nproj ? pick_split(bkb ? gemm_cn_bf16_tiles(P.nproj, P.nbands) : gemm_cn_tiles(P.nproj, P.nbands, f64),
+  P.nsplit_proj = P.nproj ? pick_split(bkb ? gemm_cn_bf16_tiles(P.nproj, P.nbb) : gemm_cn_tiles(P.nproj, P.nbb, f64),
                                        P.npw)
                           : 1;
   P.nsplit_gram = pick_split(bgr ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands) : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
@@ -234,16 +249,19 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   L.vg = take(sizeof(double) * 2 * P.npw);
   L.dscale = take(sizeof(double) * 4);
   L.beta = take(cb * P.ldw * P.nproj);
-  L.u0 = take(cb * P.ldw * nb);
-  L.u1 = take(cb * P.ldw * nb);
-  L.zb = take(cb * P.ldw * nb);
+  const bool blocked = P.nbb < P.nbands;
+  L.u0 = take(cb * P.ldw * P.nbb);
+  L.u1 = take(cb * P.ldw * P.nbb);
+  L.zb = take(cb * P.ldw * P.nbb);
+  L.wf = take(blocked ? cb * P.ldw * nb : 0);
   L.sb = take(per_band_sb * P.fft_batch);
   L.g1 = take(per_band_g1 * P.fft_batch);
-  L.pt = take(cb * std::max(1, P.nproj) * nb);
-  const size_t parts = std::max((size_t)P.nsplit_proj * P.nproj * nb, (size_t)P.nsplit_gram * nb * 2 * nb);
+  L.pt = take(cb * std::max(1, P.nproj) * P.nbb);
+  const size_t parts = std::max((size_t)P.nsplit_proj * P.nproj * P.nbb, (size_t)P.nsplit_gram * nb * 2 * nb);
   L.parts = take(16 * parts);
   L.sh = take(16 * nb * 2 * nb);
   L.ct = take(cb * nb * nb);
+  L.ct2 = take(blocked ? cb * nb * nb : 0);
   L.eig = take(sizeof(double) * nb);
   L.ework = take(sizeof(double) * nb);
   L.resid = take(sizeof(double) * nb);

@@ -15,7 +15,7 @@ constexpr size_t kDefaultMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 struct ArenaLayout {
   size_t miller, sticks, colstart, kin, tw1, tw2, tw3, vr, frac, mmil, mamp, mpha, vg, dscale;
-  size_t beta, u0, u1, zb, sb, g1, pt, parts, sh, ct, eig, ework, resid, info, scal, lanc;
+  size_t beta, u0, u1, zb, wf, sb, g1, pt, parts, sh, ct, ct2, eig, ework, resid, info, scal, lanc;
   size_t total;
 };
 
@@ -45,6 +45,7 @@ struct Plan {
   GridDesc g;
   FftLaunch fl;
   int fft_batch;               // bands per FFT launch group
+  int nbb;                     // bands per filter block (== nbands: unblocked step)
   int nsplit_proj, nsplit_gram;
   ArenaLayout lay;
 };

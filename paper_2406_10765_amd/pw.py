@@ -47,6 +47,7 @@ class CellDesc(ctypes.Structure):
         ("fft_n", ctypes.c_int * 3),
         ("prec", ctypes.c_int),
         ("flags", ctypes.c_uint),
+        ("filter_block", ctypes.c_int),
     ]
 
 
@@ -61,6 +62,7 @@ class Info(ctypes.Structure):
         ("nbands", ctypes.c_int),
         ("prec", ctypes.c_int),
         ("fused_planes", ctypes.c_int),
+        ("filter_block", ctypes.c_int),
     ]
 
 
@@ -174,7 +176,7 @@ PW_FLAG_BF16_ALL = PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT
 
 
 def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,
-              fft_n: Sequence[int] = (0, 0, 0), flags: int = 0):
+              fft_n: Sequence[int] = (0, 0, 0), flags: int = 0, filter_block: int = 0):
     """CellDesc from a synth.Cell; returns (desc, keepalive)."""
     p = cell.pseudo
     tau = np.ascontiguousarray(np.asarray(cell.tau, np.float64).reshape(-1))
@@ -196,11 +198,13 @@ def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,
     d.fft_n[:] = [int(x) for x in fft_n]
     d.prec = int(prec)
     d.flags = int(flags)
+    d.filter_block = int(filter_block)
     return d, (tau, mm, ma, mp)
 
 
-def plan(cell, prec: int = PW_FP64, nbands: Optional[int] = None, fft_n=(0, 0, 0)) -> Info:
-    d, keep = make_desc(cell, prec, nbands, fft_n)
+def plan(cell, prec: int = PW_FP64, nbands: Optional[int] = None, fft_n=(0, 0, 0), flags: int = 0,
+         filter_block: int = 0) -> Info:
+    d, keep = make_desc(cell, prec, nbands, fft_n, flags, filter_block)
     info = Info()
     _check(lib().pw_plan(ctypes.byref(d), ctypes.byref(info)))
     return info
@@ -218,13 +222,13 @@ class Handle:
     """A set-up cell on the current torch CUDA device and stream."""
 
     def __init__(self, cell, prec: int = PW_FP64, nbands: Optional[int] = None, fft_n=(0, 0, 0),
-                 device=None, stream=None, flags: int = 0):
+                 device=None, stream=None, flags: int = 0, filter_block: int = 0):
         import torch
 
         self._torch = torch
         self.prec = prec
         self.dtype = torch.complex128 if prec == PW_FP64 else torch.complex64
-        d, self._keep = make_desc(cell, prec, nbands, fft_n, flags)
+        d, self._keep = make_desc(cell, prec, nbands, fft_n, flags, filter_block)
         self.info = Info()
         _check(lib().pw_plan(ctypes.byref(d), ctypes.byref(self.info)))
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)

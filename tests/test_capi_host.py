@@ -96,3 +96,13 @@ def test_status_strings():
     L = pw.lib()
     for s in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert L.pw_status_string(s)
+
+
+def test_filter_block_planning():
+    si512, si4096 = synth.make_cell("si512"), synth.make_cell("si4096")
+    assert pw.plan(si512, pw.PW_MIXED).filter_block == si512.nbands  # fits: one block
+    info = pw.plan(si4096, pw.PW_MIXED)
+    assert 64 <= info.filter_block < si4096.nbands and info.filter_block % 64 == 0
+    # the blocked Si4096 mixed plan fits in the 288 GB of one MI355X next to the 55 GB block X
+    assert info.footprint_bytes + si4096.nbands * ((info.npw + 15) // 16 * 16) * 8 < 270e9
+    assert pw.plan(synth.make_cell("si8"), filter_block=8).filter_block == 8

@@ -255,3 +255,53 @@ def test_solve_si8_bf16_matches_dense(si8_dense):
     say("solve bf16 steps", steps, "max |de| occ", np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max())
     assert conv
     assert np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max() < 1e-5
+
+
+
+# --- band-blocked step (the memory plan of the largest cells), forced at small sizes ---------
+
+@pytest.mark.parametrize("prec,flags,etol", [(pw.PW_FP64, 0, 1e-10), (pw.PW_MIXED, 0, 1e-5),
+                                             (pw.PW_MIXED, pw.PW_FLAG_BF16_ALL, 1e-5)])
+def test_blocked_step_parity_si64(prec, flags, etol):
+    cell = synth.make_cell("si64")
+    model = O.model_from_cell(cell)
+    hop = lambda X: O.apply_h(model, X)
+    h = pw.Handle(cell, prec, flags=flags, filter_block=64)  # blocks of 64, 64, 16 bands
+    assert h.info.filter_block == 64
+    p = to_gpu_order(h, model)
+    inv = np.argsort(p)
+    X0g = synth.initial_block(h.gvectors(), cell.L, cell.nbands, synth.SEED_X0 + 1)
+    b = 1.01 * O.lanczos_max(hop, model.npw, 20, seed=3)
+    s1 = O.eig_step(hop, X0g[inv], 0, 0.0, 0.0, b)
+    s2 = O.eig_step(hop, s1.X, 10, s1.a_lo, s1.a, b)
+    Xd = h.to_device(X0g)
+    HX = h.empty_block(cell.nbands)
+    e1, r1, _ = h.eig_step(Xd, 0, b=b)
+    e2, r2, _ = h.eig_step(Xd, 10, s1.a_lo, s1.a, b, HX=HX)
+    d1 = np.abs(e1 - s1.eig)[: cell.nocc].max()
+    d2 = np.abs(e2 - s2.eig)[: cell.nocc].max()
+    say("blocked si64", prec, flags, "m=0", d1, "m=10", d2, "resid", np.abs(r2 - s2.resid).max())
+    assert d1 < etol and d2 < etol
+    if prec == pw.PW_FP64:
+        assert np.abs(r2 - s2.resid).max() < 1e-9
+        # H X' returned for the rotated block
+        Xn, HXn = h.to_host(Xd)[inv], h.to_host(HX)[inv]
+        assert np.abs(HXn - hop(Xn)).max() < 1e-10 * np.abs(HXn).max()
+    h.close()
+
+
+def test_blocked_apply_h_and_solve_si8():
+    cell = synth.make_cell("si8", modes=True)
+    err, h = apply_case(cell, pw.PW_FP64, 20, 600, flags=0)
+    model = O.model_from_cell(cell)
+    hb = pw.Handle(cell, pw.PW_FP64, filter_block=8)
+    p = to_gpu_order(hb, model)
+    X = synth.random_block(model.npw, 20, 601)
+    out = hb.to_host(hb.apply_h(hb.to_device(X[p])))
+    ref = O.apply_h(model, X)[p]
+    assert np.abs(out - ref).max() < 1e-12 * np.abs(ref).max()
+    lam = np.linalg.eigvalsh(O.dense_h(model))
+    Xd = hb.to_device(synth.initial_block(hb.gvectors(), cell.L, cell.nbands, synth.SEED_X0))
+    eig, res, steps, conv = hb.solve(Xd, cell.nocc, 1e-7, degree=10, b=1.01 * lam[-1])
+    say("blocked solve steps", steps, "max |de|", np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max())
+    assert conv and np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max() < 1e-8
