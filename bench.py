@@ -38,7 +38,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def phase_work(name: str, info, nb: int, m: int, steps: int, real_bytes: int):
+def phase_work(name: str, info, nb: int, m: int, steps: int, real_bytes: int, n1a: int = 0):
     """Algorithmic work of a phase over the timed region: (amount, kind) with kind 'flop' or 'byte'."""
     npw, nproj, nst = int(info.npw), int(info.nproj), int(info.nst)
     n1, n2, n3 = (int(x) for x in info.fft_n)
@@ -56,6 +56,10 @@ def phase_work(name: str, info, nb: int, m: int, steps: int, real_bytes: int):
         return float(bands) * (npw + nst * n3) * cb, "byte"
     if name == "plane":
         return float(bands) * (2.0 * nst * n3 * cb + nr * real_bytes), "byte"
+    if name == "pencil_yinv" or name == "pencil_yfwd":
+        return float(bands) * (nst * n3 + n3 * n2 * n1a) * cb, "byte"
+    if name == "pencil_x":
+        return float(bands) * (2.0 * n3 * n2 * n1a * cb + nr * real_bytes), "byte"
     if name == "resid":
         return 2.0 * npw * nb * cb * steps, "byte"
     return None, None
@@ -227,12 +231,13 @@ def main():
     mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
     hm = pw.Handle(cell, pw.PW_MIXED, flags=mflags)
     G = hm.gvectors()
-    X0 = synth.initial_block(G, cell.L, nb, synth.SEED_X0 + synth.WORKLOADS[args.workload]["index"])
+    n1a = 2 * int(np.abs(G[:, 0]).max()) + 1
     b = hm.spectrum_bound(20, 1)
-    X = hm.to_device(X0)
+    X = hm.random_block(nb, synth.SEED_X0 + synth.WORKLOADS[args.workload]["index"])
     eig, res, bnd = hm.eig_step(X, 0, b=b)
     bounds = (bnd[0], bnd[1])
     log(f"setup {time.time() - t0:.1f}s  npw={hm.npw} nb={nb} b={b:.4f} fused_planes={hm.info.fused_planes}")
+    log(f"first (degree 0) step done")
     eig, res, bounds = run_steps(hm, X, m, args.warmup, bounds, b)
     hm.reset_stats()
     hm.set_timing(True)
@@ -261,7 +266,7 @@ def main():
     for name, st in stats.items():
         if st["launches"] == 0:
             continue
-        amount, kind = phase_work(name, hm.info, nb, m, args.steps, 4)
+        amount, kind = phase_work(name, hm.info, nb, m, args.steps, 4, n1a)
         entry = {"launches": st["launches"], "ms_total": round(st["ms"], 3),
                  "ms_per_launch": round(st["ms"] / st["launches"], 4)}
         if amount is not None:
@@ -282,7 +287,7 @@ def main():
                 dom, dom_ms = name, st["ms"]
         phases[name] = entry
     d = phases[dom]
-    amount, kind = phase_work(dom, hm.info, nb, m, args.steps, 4)
+    amount, kind = phase_work(dom, hm.info, nb, m, args.steps, 4, n1a)
     per_launch = amount / stats[dom]["launches"]
     if kind == "flop":
         peak = PEAK_BF16_TFLOPS if dom in nterm else PEAK_MFMA_TFLOPS["fp32"]
@@ -297,12 +302,18 @@ def main():
     # ---- FP64 form and accuracy of one step from the same block -----------------------------
     fp64 = None
     accuracy = None
-    Xm = X.clone()
     bounds_m = bounds
     info = hm.info
-    del hm
+    ldp = (G.shape[0] + 15) // 16 * 16
+    fp64_bytes = pw.plan(cell, pw.PW_FP64).footprint_bytes + nb * ldp * (16 + 16 + 8)
+    fp64_fits = fp64_bytes <= torch.cuda.get_device_properties(0).total_memory
+    Xm = X.clone() if (fp64_fits and not args.no_fp64) else None
+    del hm, X
     torch.cuda.empty_cache()
-    if not args.no_fp64:
+    if not fp64_fits:
+        log(f"fp64 form skipped: needs {fp64_bytes / 1e9:.0f} GB with the projector table")
+        fp64 = {"skipped": "needs %.0f GB of device memory with the projector table" % (fp64_bytes / 1e9)}
+    elif not args.no_fp64:
         hd = pw.Handle(cell, pw.PW_FP64)
         Xd = Xm.to(torch.complex128)
         e64, r64, _ = hd.eig_step(Xd.clone(), m, bounds_m[0], bounds_m[1], b)

@@ -65,4 +65,14 @@ struct GridDesc {
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Blocks for a grid-stride loop over n elements with 256-thread blocks.  A dispatch counts
+// work-items per grid dimension in 32 bits, so element-wise kernels over blocks of billions of
+// entries loop instead of launching one work-item per element.
+inline int stride_blocks(long long n) {
+  const long long b = (n + 255) / 256;
+  return (int)(b < (1 << 20) ? (b > 0 ? b : 1) : (1 << 20));
+}
+#define PW_GRID_STRIDE(idx, total) \
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < (total); idx += (long)gridDim.x * blockDim.x)
+
 }  // namespace pw

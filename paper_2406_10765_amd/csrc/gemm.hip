@@ -309,22 +309,22 @@ template <typename T>
 __global__ void k_reduce_parts(const double2* __restrict__ part, int nsplit, int M, int N,
                                const double* __restrict__ dscale, int dper, double2* __restrict__ out64,
                                long ldo64, cplx<T>* __restrict__ outT, long ldoT) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)M * N) return;
-  const int j = (int)(idx / M), i = (int)(idx - (long)j * M);
-  double2 s = part[idx];
-  for (int p = 1; p < nsplit; ++p) {
-    const double2 v = part[(long)p * M * N + idx];
-    s.x += v.x;
-    s.y += v.y;
+  PW_GRID_STRIDE(idx, (long)M * N) {
+    const int j = (int)(idx / M), i = (int)(idx - (long)j * M);
+    double2 s = part[idx];
+    for (int p = 1; p < nsplit; ++p) {
+      const double2 v = part[(long)p * M * N + idx];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    if (dscale) {
+      const double d = dscale[i % dper];
+      s.x *= d;
+      s.y *= d;
+    }
+    if (out64) out64[(long)j * ldo64 + i] = s;
+    if (outT) outT[(long)j * ldoT + i] = mk<T>((T)s.x, (T)s.y);
   }
-  if (dscale) {
-    const double d = dscale[i % dper];
-    s.x *= d;
-    s.y *= d;
-  }
-  if (out64) out64[(long)j * ldo64 + i] = s;
-  if (outT) outT[(long)j * ldoT + i] = mk<T>((T)s.x, (T)s.y);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -473,7 +473,7 @@ hipError_t launch_reduce_parts(const double2* part, int nsplit, int M, int N, co
                                double2* out64, long ldo64, cplx<T>* outT, long ldoT, hipStream_t s) {
   const long n = (long)M * N;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_parts<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, part, nsplit, M, N, dscale,
+  hipLaunchKernelGGL(k_reduce_parts<T>, dim3(stride_blocks(n)), dim3(256), 0, s, part, nsplit, M, N, dscale,
                      dper > 0 ? dper : 1, out64, ldo64, outT, ldoT);
   return hipGetLastError();
 }

@@ -12,8 +12,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 template <typename T>
 __global__ void k_fill_zero(cplx<T>* p, long n) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = mk<T>(0, 0);
+  PW_GRID_STRIDE(i, n) p[i] = mk<T>(0, 0);
 }
 
 // exp(-2 pi i t) with t reduced to [-1/2, 1/2] first (exact phase from Miller indices)
@@ -104,48 +103,48 @@ __global__ void k_beta_table(const int* __restrict__ miller, int npw, const doub
 template <typename T>
 __global__ void k_convert(const double2* __restrict__ in, long ldi, cplx<T>* __restrict__ out, long ldo, int rows,
                           int cols) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)rows * cols) return;
-  const int j = (int)(idx / rows), i = (int)(idx - (long)j * rows);
-  const double2 v = in[(long)j * ldi + i];
-  out[(long)j * ldo + i] = mk<T>((T)v.x, (T)v.y);
+  PW_GRID_STRIDE(idx, (long)rows * cols) {
+    const int j = (int)(idx / rows), i = (int)(idx - (long)j * rows);
+    const double2 v = in[(long)j * ldi + i];
+    out[(long)j * ldo + i] = mk<T>((T)v.x, (T)v.y);
+  }
 }
 
 template <typename T>
 __global__ void k_copy_cols(const cplx<T>* __restrict__ in, long ldi, cplx<T>* __restrict__ out, long ldo, int rows,
                             int cols) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)rows * cols) return;
-  const int j = (int)(idx / rows), i = (int)(idx - (long)j * rows);
-  out[(long)j * ldo + i] = in[(long)j * ldi + i];
+  PW_GRID_STRIDE(idx, (long)rows * cols) {
+    const int j = (int)(idx / rows), i = (int)(idx - (long)j * rows);
+    out[(long)j * ldo + i] = in[(long)j * ldi + i];
+  }
 }
 
 template <typename T>
 __global__ void k_scale_cols_lam(const double2* __restrict__ in, long ldi, cplx<T>* __restrict__ out, long ldo, int n,
                                  const double* __restrict__ lam, double sc) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)n * n) return;
-  const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
-  const double f = sc * lam[j];
-  const double2 v = in[(long)j * ldi + i];
-  out[(long)j * ldo + i] = mk<T>((T)(f * v.x), (T)(f * v.y));
+  PW_GRID_STRIDE(idx, (long)n * n) {
+    const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
+    const double f = sc * lam[j];
+    const double2 v = in[(long)j * ldi + i];
+    out[(long)j * ldo + i] = mk<T>((T)(f * v.x), (T)(f * v.y));
+  }
 }
 
 __global__ void k_hermitize(double2* A, long lda, int n) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)n * n) return;
-  const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
-  if (i < j) return;
-  double2 a = A[(long)j * lda + i];
-  if (i == j) {
-    a.y = 0.0;
-    A[(long)j * lda + i] = a;
-    return;
+  PW_GRID_STRIDE(idx, (long)n * n) {
+    const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
+    if (i < j) continue;
+    double2 a = A[(long)j * lda + i];
+    if (i == j) {
+      a.y = 0.0;
+      A[(long)j * lda + i] = a;
+      continue;
+    }
+    const double2 b = A[(long)i * lda + j];
+    const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    A[(long)j * lda + i] = m;
+    A[(long)i * lda + j] = make_double2(m.x, -m.y);
   }
-  const double2 b = A[(long)i * lda + j];
-  const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-  A[(long)j * lda + i] = m;
-  A[(long)i * lda + j] = make_double2(m.x, -m.y);
 }
 
 // One workgroup per column; fp64 accumulation, wavefront shuffles then LDS.
@@ -216,8 +215,7 @@ __global__ __launch_bounds__(1024) void k_lanczos(cplx<T>* __restrict__ w, const
 
 template <typename T>
 __global__ void k_scale_copy(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, double scale, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = mk<T>((T)(in[i].x * scale), (T)(in[i].y * scale));
+  PW_GRID_STRIDE(i, (long)n) out[i] = mk<T>((T)(in[i].x * scale), (T)(in[i].y * scale));
 }
 
 template <typename T>
@@ -229,7 +227,7 @@ hipError_t launch_lanczos_step(cplx<T>* w, const cplx<T>* v, const cplx<T>* vp, 
 
 template <typename T>
 hipError_t launch_scale_copy(const cplx<T>* in, cplx<T>* out, double scale, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_copy<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, in, out, scale, n);
+  hipLaunchKernelGGL(k_scale_copy<T>, dim3(stride_blocks(n)), dim3(256), 0, s, in, out, scale, n);
   return hipGetLastError();
 }
 
@@ -243,27 +241,27 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
 template <typename T>
 __global__ void k_random_block(cplx<T>* __restrict__ X, long ld, int npw, int nb, const T* __restrict__ kin,
                                unsigned long long seed) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)npw * nb) return;
-  const int j = (int)(idx / npw), g = (int)(idx - (long)j * npw);
-  const unsigned long long c = splitmix64(seed ^ splitmix64(((unsigned long long)j << 32) | (unsigned)g));
-  const unsigned long long d = splitmix64(c);
-  const double u1 = ((c >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-  const double u2 = ((d >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-  const double r = sqrt(-2.0 * log(u1)) / (1.0 + 2.0 * (double)kin[g]);
-  double sn, cs;
-  sincospi(2.0 * u2, &sn, &cs);
-  X[(long)j * ld + g] = mk<T>((T)(r * cs), (T)(r * sn));
+  PW_GRID_STRIDE(idx, (long)npw * nb) {
+    const int j = (int)(idx / npw), g = (int)(idx - (long)j * npw);
+    const unsigned long long c = splitmix64(seed ^ splitmix64(((unsigned long long)j << 32) | (unsigned)g));
+    const unsigned long long d = splitmix64(c);
+    const double u1 = ((c >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((d >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double r = sqrt(-2.0 * log(u1)) / (1.0 + 2.0 * (double)kin[g]);
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    X[(long)j * ld + g] = mk<T>((T)(r * cs), (T)(r * sn));
+  }
 }
 
 template <typename T>
 __global__ void k_scale_cols_inv(cplx<T>* __restrict__ X, long ld, int npw, int nb, const double* __restrict__ nrm) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)npw * nb) return;
-  const int j = (int)(idx / npw), g = (int)(idx - (long)j * npw);
-  const T s = (T)(1.0 / nrm[j]);
-  cplx<T> v = X[(long)j * ld + g];
-  X[(long)j * ld + g] = mk<T>(v.x * s, v.y * s);
+  PW_GRID_STRIDE(idx, (long)npw * nb) {
+    const int j = (int)(idx / npw), g = (int)(idx - (long)j * npw);
+    const T s = (T)(1.0 / nrm[j]);
+    cplx<T> v = X[(long)j * ld + g];
+    X[(long)j * ld + g] = mk<T>(v.x * s, v.y * s);
+  }
 }
 
 template <typename T>
@@ -271,7 +269,7 @@ hipError_t launch_random_block(cplx<T>* X, long ld, int npw, int nb, const T* ki
                                hipStream_t s) {
   const long n = (long)npw * nb;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_random_block<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, X, ld, npw, nb, kin, seed);
+  hipLaunchKernelGGL(k_random_block<T>, dim3(stride_blocks(n)), dim3(256), 0, s, X, ld, npw, nb, kin, seed);
   return hipGetLastError();
 }
 
@@ -279,14 +277,14 @@ template <typename T>
 hipError_t launch_scale_cols_inv(cplx<T>* X, long ld, int npw, int nb, const double* norms, hipStream_t s) {
   const long n = (long)npw * nb;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_cols_inv<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, X, ld, npw, nb, norms);
+  hipLaunchKernelGGL(k_scale_cols_inv<T>, dim3(stride_blocks(n)), dim3(256), 0, s, X, ld, npw, nb, norms);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_fill_zero(cplx<T>* p, long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_zero<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n);
+  hipLaunchKernelGGL(k_fill_zero<T>, dim3(stride_blocks(n)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
@@ -312,7 +310,7 @@ hipError_t launch_convert_c64_to(const double2* in, long ldi, cplx<T>* out, long
                                  hipStream_t s) {
   const long n = (long)rows * cols;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_convert<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, in, ldi, out, ldo, rows, cols);
+  hipLaunchKernelGGL(k_convert<T>, dim3(stride_blocks(n)), dim3(256), 0, s, in, ldi, out, ldo, rows, cols);
   return hipGetLastError();
 }
 
@@ -320,7 +318,7 @@ template <typename T>
 hipError_t launch_copy_cols(const cplx<T>* in, long ldi, cplx<T>* out, long ldo, int rows, int cols, hipStream_t s) {
   const long n = (long)rows * cols;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_cols<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, in, ldi, out, ldo, rows, cols);
+  hipLaunchKernelGGL(k_copy_cols<T>, dim3(stride_blocks(n)), dim3(256), 0, s, in, ldi, out, ldo, rows, cols);
   return hipGetLastError();
 }
 
@@ -329,14 +327,14 @@ hipError_t launch_scale_cols_lam(const double2* in, long ldi, cplx<T>* out, long
                                  double sc, hipStream_t st) {
   const long m = (long)n * n;
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_cols_lam<T>, dim3(ceil_div(m, 256)), dim3(256), 0, st, in, ldi, out, ldo, n, lam, sc);
+  hipLaunchKernelGGL(k_scale_cols_lam<T>, dim3(stride_blocks(m)), dim3(256), 0, st, in, ldi, out, ldo, n, lam, sc);
   return hipGetLastError();
 }
 
 hipError_t launch_hermitize(double2* A, long lda, int n, hipStream_t s) {
   const long m = (long)n * n;
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hermitize, dim3(ceil_div(m, 256)), dim3(256), 0, s, A, lda, n);
+  hipLaunchKernelGGL(k_hermitize, dim3(stride_blocks(m)), dim3(256), 0, s, A, lda, n);
   return hipGetLastError();
 }
 
