@@ -30,7 +30,7 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f16 __attribute__((ext_vector_type(4)));
 
 constexpr int hBK = 16;  // complex K per tile = 32 real k' = one MFMA slab
-constexpr int hFlush = 16;
+constexpr int hFlush = 256;  // K tiles (4096 complex K) per fp32 MFMA accumulation before fp64
 constexpr int hXcd = 8;
 
 struct Split2 {
@@ -89,6 +89,22 @@ struct KcSplit {
   float v[PER][4];
   __device__ __forceinline__ void load(const float2* __restrict__ P, long ld, const float2* __restrict__ P2,
                                        long ld2, int ncol1, int ncols, int c0, int k0, int kend, int tid) {
+    if (VEC && c0 + NC <= ncols && k0 + hBK <= kend && (UNITS % 256) == 0) {
+      // whole tile inside the operand: no per-element checks
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * 256;
+        const int u = idx & 7, c = idx >> 3;
+        const int gc = c0 + c;
+        const float2* col = gc < ncol1 ? P + (long)gc * ld : P2 + (long)(gc - ncol1) * ld2;
+        const float4 x = *reinterpret_cast<const float4*>(col + k0 + 2 * u);
+        v[q][0] = x.x;
+        v[q][1] = x.y;
+        v[q][2] = x.z;
+        v[q][3] = x.w;
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * 256;
@@ -147,6 +163,19 @@ struct McSplit {
   float v[PER][4];
   __device__ __forceinline__ void load(const float2* __restrict__ P, long ld, int nrows, int r0, int k0, int kend,
                                        int tid) {
+    if (VEC && r0 + NR <= nrows && k0 + hBK <= kend && (UNITS % 256) == 0) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * 256;
+        const int mu = idx % (NR / 2), k = idx / (NR / 2);
+        const float4 x = *reinterpret_cast<const float4*>(P + (long)(k0 + k) * ld + r0 + 2 * mu);
+        v[q][0] = x.x;
+        v[q][1] = x.y;
+        v[q][2] = x.z;
+        v[q][3] = x.w;
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * 256;
@@ -276,17 +305,9 @@ __global__ __launch_bounds__(256) void k_gemm_cn_bf16x3(const float2* __restrict
   const int i0 = tm * BM, j0 = tn * BN;
   const int kb = sp * kchunk, ke = min(K, kb + kchunk);
   const int mo = (wave & 1) * (BM / 2), no = (wave >> 1) * (BN / 2);
+  // Two accumulation levels: the MFMA accumulators (fp32) over hFlush K tiles, then the fp64
+  // partial in global memory, which this workgroup alone owns.
   v4f16 cr[WBM][WBN], ci[WBM][WBN];
-  double dr[WBM][WBN][4], di[WBM][WBN][4];
-#pragma unroll
-  for (int a = 0; a < WBM; ++a)
-#pragma unroll
-    for (int b = 0; b < WBN; ++b) {
-      cr[a][b] = v4f16{0, 0, 0, 0};
-      ci[a][b] = v4f16{0, 0, 0, 0};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
-    }
   KcSplit<BM, VEC> la;
   KcSplit<BN, VEC> lb;
   const int ntiles = ke > kb ? (ke - kb + hBK - 1) / hBK : 0;
@@ -297,75 +318,77 @@ __global__ __launch_bounds__(256) void k_gemm_cn_bf16x3(const float2* __restrict
     lb.store(sBh[0], sBl[0], tid);
   }
   __syncthreads();
-  for (int it = 0; it < ntiles; ++it) {
-    const int cur = it & 1;
-    const bool more = it + 1 < ntiles;
-    if (more) {
-      const int kn = kb + (it + 1) * hBK;
-      la.load(A, lda, A, lda, M, M, i0, kn, ke, tid);
-      lb.load(B, ldb, B2, ldb2, ncol1, N, j0, kn, ke, tid);
-    }
-    v8bf ah[WBM], al[WBM];
+  bool stored = false;
+  int it = 0;
+  do {
+    const int fend = min(ntiles, it + hFlush);
 #pragma unroll
-    for (int a = 0; a < WBM; ++a) {
-      ah[a] = frag<BM>(sAh[cur], mo + a * 16, lane);
-      al[a] = frag<BM>(sAl[cur], mo + a * 16, lane);
-    }
+    for (int a = 0; a < WBM; ++a)
 #pragma unroll
-    for (int b = 0; b < WBN; ++b) {
-      const v8bf bh = frag<BN>(sBh[cur], no + b * 16, lane);
-      const v8bf bl = frag<BN>(sBl[cur], no + b * 16, lane);
-      const v8bf bh2 = swapneg(bh), bl2 = swapneg(bl);
+      for (int b = 0; b < WBN; ++b) cr[a][b] = ci[a][b] = v4f16{0, 0, 0, 0};
+    for (; it < fend; ++it) {
+      const int cur = it & 1;
+      const bool more = it + 1 < ntiles;
+      if (more) {
+        const int kn = kb + (it + 1) * hBK;
+        la.load(A, lda, A, lda, M, M, i0, kn, ke, tid);
+        lb.load(B, ldb, B2, ldb2, ncol1, N, j0, kn, ke, tid);
+      }
+      v8bf ah[WBM], al[WBM];
 #pragma unroll
       for (int a = 0; a < WBM; ++a) {
-        cr[a][b] = mma16(ah[a], bh, cr[a][b]);
-        ci[a][b] = mma16(ah[a], bh2, ci[a][b]);
-        cr[a][b] = mma16(ah[a], bl, cr[a][b]);
-        ci[a][b] = mma16(ah[a], bl2, ci[a][b]);
-        cr[a][b] = mma16(al[a], bh, cr[a][b]);
-        ci[a][b] = mma16(al[a], bh2, ci[a][b]);
-        if constexpr (NTERM == 4) {
-          cr[a][b] = mma16(al[a], bl, cr[a][b]);
-          ci[a][b] = mma16(al[a], bl2, ci[a][b]);
-        }
+        ah[a] = frag<BM>(sAh[cur], mo + a * 16, lane);
+        al[a] = frag<BM>(sAl[cur], mo + a * 16, lane);
       }
-    }
-    if ((it % hFlush) == hFlush - 1) {
 #pragma unroll
-      for (int a = 0; a < WBM; ++a)
+      for (int b = 0; b < WBN; ++b) {
+        const v8bf bh = frag<BN>(sBh[cur], no + b * 16, lane);
+        const v8bf bl = frag<BN>(sBl[cur], no + b * 16, lane);
+        const v8bf bh2 = swapneg(bh), bl2 = swapneg(bl);
 #pragma unroll
-        for (int b = 0; b < WBN; ++b) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            dr[a][b][r] += (double)cr[a][b][r];
-            di[a][b][r] += (double)ci[a][b][r];
+        for (int a = 0; a < WBM; ++a) {
+          cr[a][b] = mma16(ah[a], bh, cr[a][b]);
+          ci[a][b] = mma16(ah[a], bh2, ci[a][b]);
+          cr[a][b] = mma16(ah[a], bl, cr[a][b]);
+          ci[a][b] = mma16(ah[a], bl2, ci[a][b]);
+          cr[a][b] = mma16(al[a], bh, cr[a][b]);
+          ci[a][b] = mma16(al[a], bh2, ci[a][b]);
+          if constexpr (NTERM == 4) {
+            cr[a][b] = mma16(al[a], bl, cr[a][b]);
+            ci[a][b] = mma16(al[a], bl2, ci[a][b]);
           }
-          cr[a][b] = v4f16{0, 0, 0, 0};
-          ci[a][b] = v4f16{0, 0, 0, 0};
-        }
-    }
-    if (more) {
-      la.store(sAh[cur ^ 1], sAl[cur ^ 1], tid);
-      lb.store(sBh[cur ^ 1], sBl[cur ^ 1], tid);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < WBM; ++a)
-#pragma unroll
-    for (int b = 0; b < WBN; ++b) {
-      const int col = j0 + no + b * 16 + (lane & 15);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = i0 + mo + a * 16 + 4 * (lane >> 4) + r;
-        if (row < M && col < N) {
-          double2 v;
-          v.x = dr[a][b][r] + (double)cr[a][b][r];
-          v.y = di[a][b][r] + (double)ci[a][b][r];
-          part[((long)sp * N + col) * M + row] = v;
         }
       }
+      if (more) {
+        la.store(sAh[cur ^ 1], sAl[cur ^ 1], tid);
+        lb.store(sBh[cur ^ 1], sBl[cur ^ 1], tid);
+      }
+      __syncthreads();
     }
+#pragma unroll
+    for (int a = 0; a < WBM; ++a)
+#pragma unroll
+      for (int b = 0; b < WBN; ++b) {
+        const int col = j0 + no + b * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + mo + a * 16 + 4 * (lane >> 4) + r;
+          if (row < M && col < N) {
+            double2* dst = part + ((long)sp * N + col) * M + row;
+            double2 v;
+            v.x = (double)cr[a][b][r];
+            v.y = (double)ci[a][b][r];
+            if (stored) {
+              const double2 o = *dst;
+              v.x += o.x;
+              v.y += o.y;
+            }
+            *dst = v;
+          }
+        }
+      }
+    stored = true;
+  } while (it < ntiles);
 }
 
 // ------------------------------------------------------------------------------------------
