@@ -134,6 +134,11 @@ struct Engine {
   cplx<T>* zb() const { return h->at<cplx<T>>(P.lay.zb); }
 
   bool flag(unsigned f) const { return (P.flags & f) != 0; }
+  // With split-precision projector products the table is stored as bf16 hi and lo planes of
+  // one (re, im) word per entry, leading dimension ldw words, in the same arena bytes.
+  bool beta_planes() const { return std::is_same<T, float>::value && flag(PW_FLAG_BF16_KB); }
+  unsigned int* beta_hi() const { return h->at<unsigned int>(P.lay.beta); }
+  unsigned int* beta_lo() const { return beta_hi() + (size_t)P.ldw * P.nproj; }
 
   hipError_t cn(bool split16, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const cplx<T>* B2, long ldb2,
                 int ncol1, int M, int N, int K, int nsplit, double2* part, int nterm = 3) {
@@ -190,8 +195,14 @@ struct Engine {
     cplx<T>* PT = h->at<cplx<T>>(P.lay.pt);
     if (P.nproj > 0) {
       double2* parts = h->at<double2>(P.lay.parts);
-      PW_TIMED(PW_PH_PROJ, cn(flag(PW_FLAG_BF16_KB), beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw,
-                              P.nsplit_proj, parts));
+      if constexpr (std::is_same<T, float>::value) {
+        if (beta_planes()) {
+          PW_TIMED(PW_PH_PROJ, launch_gemm_cn_bf16x3_planes(beta_hi(), beta_lo(), P.ldw, Y, ldy, P.nproj, nb, P.npw,
+                                                            P.nsplit_proj, parts, h->stream));
+        }
+      }
+      if (!beta_planes())
+        PW_TIMED(PW_PH_PROJ, cn(false, beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw, P.nsplit_proj, parts));
       PW_TIMED(PW_PH_PROJ_REDUCE, launch_reduce_parts<T>(parts, P.nsplit_proj, P.nproj, nb,
                                                          h->at<double>(P.lay.dscale), 4, nullptr, 0, PT, P.nproj,
                                                          h->stream));
@@ -208,7 +219,14 @@ struct Engine {
     e.ldz = ldz;
     e.Yp = Yp;
     e.ldp = ldp;
-    PW_TIMED(PW_PH_NL, nn(flag(PW_FLAG_BF16_KB), beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e));
+    if constexpr (std::is_same<T, float>::value) {
+      if (beta_planes()) {
+        PW_TIMED(PW_PH_NL, launch_gemm_nn_bf16x3_planes(beta_hi(), beta_lo(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj,
+                                                        out, ldo, e, h->stream));
+        return PW_OK;
+      }
+    }
+    PW_TIMED(PW_PH_NL, nn(false, beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e));
     return PW_OK;
   }
 
@@ -580,7 +598,10 @@ struct Engine {
         PW_HIP(launch_pencil_x<T>(G1, (const T*)nullptr, 1, g, tw1, 1, vr, p.fl, st));
       }
     }
-    if (p.nproj)
+    if (p.nproj && beta_planes())
+      PW_HIP(launch_beta_planes(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), p.natoms, p.L,
+                                p.beta_sigma, beta_hi(), beta_lo(), p.ldw, st));
+    else if (p.nproj)
       PW_HIP(launch_beta_table<T>(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), p.natoms, p.L,
                                   p.beta_sigma, beta(), p.ldw, st));
     PW_HIP(hipStreamSynchronize(st));

@@ -17,10 +17,12 @@
 //
 // MFMA 16x16x32 bf16: lane l supplies 8 consecutive k' values of row/column l % 16 from k' slot
 // l / 16; the accumulator layout is that of the fp32 16x16x4 instruction (C[4 (l/16) + r][l % 16]).
-// LDS planes are stored [slot][row][8] so the 16 lanes of a slot read 256 contiguous bytes.
+// LDS planes are stored [slot][row][8] (rows swizzled within groups of 16) so the 16 lanes of a
+// slot read 256 contiguous bytes.
 
 #include <type_traits>
 
+#include "bf16split.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -32,27 +34,6 @@ typedef float v4f16 __attribute__((ext_vector_type(4)));
 constexpr int hBK = 16;  // complex K per tile = 32 real k' = one MFMA slab
 constexpr int hFlush = 256;  // K tiles (4096 complex K) per fp32 MFMA accumulation before fp64
 constexpr int hXcd = 8;
-
-struct Split2 {
-  unsigned short h, l;
-};
-
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  const __bf16 b = (__bf16)x;  // round to nearest even
-  return __builtin_bit_cast(unsigned short, b);
-}
-__device__ __forceinline__ float bf16_val(unsigned short u) {
-  return __builtin_bit_cast(float, (unsigned int)u << 16);
-}
-__device__ __forceinline__ Split2 split(float x) {
-  Split2 s;
-  s.h = bf16_bits(x);
-  s.l = bf16_bits(x - bf16_val(s.h));
-  return s;
-}
-__device__ __forceinline__ unsigned int pack(unsigned short lo16, unsigned short hi16) {
-  return (unsigned int)lo16 | ((unsigned int)hi16 << 16);
-}
 
 __device__ __forceinline__ int xcd_tile16(int w, int total) {
   const int per = total / hXcd, rem = total % hXcd;
@@ -77,7 +58,11 @@ __device__ __forceinline__ v4f16 mma16(v8bf a, v8bf b, v4f16 c) {
 // Plane of one K tile: [4 slots][NR rows][8 bf16]; element (row, k') at (k'/8)*NR*8 + row*8 + k'%8.
 template <int NR>
 __device__ __forceinline__ int plane_off(int row, int kp) {
-  return ((kp >> 3) * NR + row) * 8 + (kp & 7);
+  // Rows are permuted within aligned groups of 16 by XOR with 4 * slot, so that writers whose lanes
+  // span several slots and few rows still reach all 64 banks; a 16-row fragment read stays one
+  // conflict-free 256-byte group.
+  const int slot = kp >> 3;
+  return (slot * NR + (row ^ (4 * (slot & 3)))) * 8 + (kp & 7);
 }
 
 // Loader of a K-contiguous complex operand (cn A, cn B): kBK complex = 32 reals per column.
@@ -161,13 +146,21 @@ struct McSplit {
   static constexpr int UNITS = (NR / 2) * hBK;
   static constexpr int PER = (UNITS + 255) / 256;
   float v[PER][4];
+  // unit idx -> row pair mu, k: four consecutive k per group of four lanes, so that a wave covers
+  // 16 consecutive row pairs at 4 k (256 contiguous bytes per column)
+  __device__ __forceinline__ static void unit(int idx, int& mu, int& k) {
+    constexpr int NP = NR / 2;
+    k = (idx & 3) + 4 * (idx / (4 * NP));
+    mu = (idx >> 2) % NP;
+  }
   __device__ __forceinline__ void load(const float2* __restrict__ P, long ld, int nrows, int r0, int k0, int kend,
                                        int tid) {
     if (VEC && r0 + NR <= nrows && k0 + hBK <= kend && (UNITS % 256) == 0) {
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int idx = tid + q * 256;
-        const int mu = idx % (NR / 2), k = idx / (NR / 2);
+        int mu, k;
+        unit(idx, mu, k);
         const float4 x = *reinterpret_cast<const float4*>(P + (long)(k0 + k) * ld + r0 + 2 * mu);
         v[q][0] = x.x;
         v[q][1] = x.y;
@@ -179,7 +172,8 @@ struct McSplit {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * 256;
-      const int mu = idx % (NR / 2), k = idx / (NR / 2);
+      int mu, k;
+      unit(idx, mu, k);
       const int gm = r0 + 2 * mu, gk = k0 + k;
       v[q][0] = v[q][1] = v[q][2] = v[q][3] = 0.f;
       if (idx < UNITS && gk < kend) {
@@ -210,13 +204,20 @@ struct McSplit {
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * 256;
       if (idx < UNITS) {
-        const int mu = idx % (NR / 2), k = idx / (NR / 2);
-        const int o0 = plane_off<NR>(2 * mu, 2 * k), o1 = plane_off<NR>(2 * mu + 1, 2 * k);
-        Split2 a = split(v[q][0]), b = split(v[q][1]), c = split(v[q][2]), d = split(v[q][3]);
-        *reinterpret_cast<unsigned int*>(Hp + o0) = pack(a.h, b.h);
-        *reinterpret_cast<unsigned int*>(Lp + o0) = pack(a.l, b.l);
-        *reinterpret_cast<unsigned int*>(Hp + o1) = pack(c.h, d.h);
-        *reinterpret_cast<unsigned int*>(Lp + o1) = pack(c.l, d.l);
+        int mu, k;
+        unit(idx, mu, k);
+        const Split2 a = split(v[q][0]), b = split(v[q][1]), c = split(v[q][2]), d = split(v[q][3]);
+        const unsigned int w[4] = {pack(a.h, b.h), pack(a.l, b.l), pack(c.h, d.h), pack(c.l, d.l)};
+        // the two rows are written in an order that alternates every 8 units, which spreads
+        // each write instruction over 16 distinct rows modulo 16
+        const int f = (mu >> 3) & 1;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int r = e ^ f;
+          const int o = plane_off<NR>(2 * mu + r, 2 * k);
+          *reinterpret_cast<unsigned int*>(Hp + o) = w[2 * r];
+          *reinterpret_cast<unsigned int*>(Lp + o) = w[2 * r + 1];
+        }
       }
     }
   }
@@ -280,6 +281,154 @@ struct KcSplitB {
   }
 };
 
+// A-operand loaders with one interface: load(A0, A1, lda, extent, offset, k0, kend, tid) fetches
+// one K tile into registers, store(H, L, tid) writes its hi and lo planes.
+template <int NC, bool VEC>
+struct CnAF32 {  // cn A from fp32 data (NC columns of A), split on the fly
+  KcSplit<NC, VEC> l;
+  __device__ __forceinline__ void load(const void* A0, const void*, long lda, int ncols, int c0, int k0, int kend,
+                                       int tid) {
+    const float2* P = static_cast<const float2*>(A0);
+    l.load(P, lda, P, lda, ncols, ncols, c0, k0, kend, tid);
+  }
+  __device__ __forceinline__ void store(unsigned short* H, unsigned short* L, int tid) const { l.store(H, L, tid); }
+};
+
+template <int NR, bool VEC>
+struct NnAF32 {  // nn A from fp32 data (NR rows of A), split on the fly
+  McSplit<NR, VEC> l;
+  __device__ __forceinline__ void load(const void* A0, const void*, long lda, int nrows, int r0, int k0, int kend,
+                                       int tid) {
+    l.load(static_cast<const float2*>(A0), lda, nrows, r0, k0, kend, tid);
+  }
+  __device__ __forceinline__ void store(unsigned short* H, unsigned short* L, int tid) const { l.store(H, L, tid); }
+};
+
+// cn A from pre-split planes: a unit is 4 complex k (16 bytes) of one column in each plane, which
+// is one 8-value k' group of the LDS plane.
+template <int NC, bool VEC>
+struct CnAPlanes {
+  static constexpr int UNITS = 4 * NC;
+  static constexpr int PER = (UNITS + 255) / 256;
+  uint4 h[PER], l[PER];
+  __device__ __forceinline__ void load(const void* A0, const void* A1, long lda, int ncols, int c0, int k0, int kend,
+                                       int tid) {
+    const unsigned int* Hp = static_cast<const unsigned int*>(A0);
+    const unsigned int* Lp = static_cast<const unsigned int*>(A1);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      const int sl = idx & 3, c = idx >> 2;
+      const int gc = c0 + c, gk = k0 + 4 * sl;
+      h[q] = l[q] = uint4{0, 0, 0, 0};
+      if (idx < UNITS && gc < ncols) {
+        const long o = (long)gc * lda + gk;
+        if (VEC && gk + 4 <= kend) {
+          h[q] = *reinterpret_cast<const uint4*>(Hp + o);
+          l[q] = *reinterpret_cast<const uint4*>(Lp + o);
+        } else {
+          unsigned int th[4] = {0, 0, 0, 0}, tl[4] = {0, 0, 0, 0};
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (gk + e < kend) {
+              th[e] = Hp[o + e];
+              tl[e] = Lp[o + e];
+            }
+          h[q] = uint4{th[0], th[1], th[2], th[3]};
+          l[q] = uint4{tl[0], tl[1], tl[2], tl[3]};
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void store(unsigned short* H, unsigned short* L, int tid) const {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < UNITS) {
+        const int sl = idx & 3, c = idx >> 2;
+        const int off = plane_off<NC>(c, 8 * sl);
+        *reinterpret_cast<uint4*>(H + off) = h[q];
+        *reinterpret_cast<uint4*>(L + off) = l[q];
+      }
+    }
+  }
+};
+
+// nn A from pre-split planes: a unit is 4 consecutive rows at one k in each plane; each word is
+// the (re, im) pair at k' = 2k of its row.
+template <int NR, bool VEC>
+struct NnAPlanes {
+  static constexpr int UNITS = (NR / 4) * hBK;
+  static constexpr int PER = (UNITS + 255) / 256;
+  uint4 h[PER], l[PER];
+  // unit idx -> row quad mu, k: four consecutive k per group of four lanes; a wave covers 16
+  // consecutive row quads (256 contiguous bytes per column and plane) at 4 k
+  __device__ __forceinline__ static void unit(int idx, int& mu, int& k) {
+    constexpr int NQ = NR / 4;
+    k = (idx & 3) + 4 * (idx / (4 * NQ));
+    mu = (idx >> 2) % NQ;
+  }
+  __device__ __forceinline__ void load(const void* A0, const void* A1, long lda, int nrows, int r0, int k0, int kend,
+                                       int tid) {
+    const unsigned int* Hp = static_cast<const unsigned int*>(A0);
+    const unsigned int* Lp = static_cast<const unsigned int*>(A1);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      int mu, k;
+      unit(idx, mu, k);
+      const int gm = r0 + 4 * mu, gk = k0 + k;
+      h[q] = l[q] = uint4{0, 0, 0, 0};
+      if (idx < UNITS && gk < kend) {
+        const long o = (long)gk * lda + gm;
+        if (VEC && gm + 4 <= nrows) {
+          h[q] = *reinterpret_cast<const uint4*>(Hp + o);
+          l[q] = *reinterpret_cast<const uint4*>(Lp + o);
+        } else {
+          unsigned int th[4] = {0, 0, 0, 0}, tl[4] = {0, 0, 0, 0};
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (gm + e < nrows) {
+              th[e] = Hp[o + e];
+              tl[e] = Lp[o + e];
+            }
+          h[q] = uint4{th[0], th[1], th[2], th[3]};
+          l[q] = uint4{tl[0], tl[1], tl[2], tl[3]};
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void store(unsigned short* H, unsigned short* L, int tid) const {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < UNITS) {
+        int mu, k;
+        unit(idx, mu, k);
+        const unsigned int hv[4] = {h[q].x, h[q].y, h[q].z, h[q].w};
+        const unsigned int lv[4] = {l[q].x, l[q].y, l[q].z, l[q].w};
+        // rotate the row order by mu / 4 so that each write instruction covers 16 distinct rows
+        // modulo 16
+        const int f = (mu >> 2) & 3;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = (e + f) & 3;
+          const int off = plane_off<NR>(4 * mu + r, 2 * k);
+          unsigned int hw = hv[0], lw = lv[0];
+#pragma unroll
+          for (int j = 1; j < 4; ++j)
+            if (r == j) {
+              hw = hv[j];
+              lw = lv[j];
+            }
+          *reinterpret_cast<unsigned int*>(H + off) = hw;
+          *reinterpret_cast<unsigned int*>(L + off) = lw;
+        }
+      }
+    }
+  }
+};
+
 template <int NR>
 __device__ __forceinline__ v8bf frag(const unsigned short* plane, int row, int lane) {
   return *reinterpret_cast<const v8bf*>(plane + plane_off<NR>(row + (lane & 15), 8 * (lane >> 4)));
@@ -288,9 +437,9 @@ __device__ __forceinline__ v8bf frag(const unsigned short* plane, int row, int l
 // ------------------------------------------------------------------------------------------
 // cn: part[s] = A^H B over K chunk s (fp32 data, bf16x3 products, fp64 partials).
 // ------------------------------------------------------------------------------------------
-template <int BM, int BN, bool VEC, int NTERM>
-__global__ __launch_bounds__(256) void k_gemm_cn_bf16x3(const float2* __restrict__ A, long lda,
-                                                        const float2* __restrict__ B, long ldb,
+template <int BM, int BN, bool VEC, int NTERM, class AL>
+__global__ __launch_bounds__(256) void k_gemm_cn_bf16x3(const void* __restrict__ A0, const void* __restrict__ A1,
+                                                        long lda, const float2* __restrict__ B, long ldb,
                                                         const float2* __restrict__ B2, long ldb2, int ncol1, int M,
                                                         int N, int K, int kchunk, int tiles_m, int tiles_n,
                                                         double2* __restrict__ part) {
@@ -308,11 +457,11 @@ __global__ __launch_bounds__(256) void k_gemm_cn_bf16x3(const float2* __restrict
   // Two accumulation levels: the MFMA accumulators (fp32) over hFlush K tiles, then the fp64
   // partial in global memory, which this workgroup alone owns.
   v4f16 cr[WBM][WBN], ci[WBM][WBN];
-  KcSplit<BM, VEC> la;
+  AL la;
   KcSplit<BN, VEC> lb;
   const int ntiles = ke > kb ? (ke - kb + hBK - 1) / hBK : 0;
   if (ntiles > 0) {
-    la.load(A, lda, A, lda, M, M, i0, kb, ke, tid);
+    la.load(A0, A1, lda, M, i0, kb, ke, tid);
     lb.load(B, ldb, B2, ldb2, ncol1, N, j0, kb, ke, tid);
     la.store(sAh[0], sAl[0], tid);
     lb.store(sBh[0], sBl[0], tid);
@@ -331,7 +480,7 @@ __global__ __launch_bounds__(256) void k_gemm_cn_bf16x3(const float2* __restrict
       const bool more = it + 1 < ntiles;
       if (more) {
         const int kn = kb + (it + 1) * hBK;
-        la.load(A, lda, A, lda, M, M, i0, kn, ke, tid);
+        la.load(A0, A1, lda, M, i0, kn, ke, tid);
         lb.load(B, ldb, B2, ldb2, ncol1, N, j0, kn, ke, tid);
       }
       v8bf ah[WBM], al[WBM];
@@ -394,9 +543,10 @@ __global__ __launch_bounds__(256) void k_gemm_cn_bf16x3(const float2* __restrict
 // ------------------------------------------------------------------------------------------
 // nn: out = epilogue(A B) (fp32 data, bf16x3 products).
 // ------------------------------------------------------------------------------------------
-template <int BM, int BN, bool VEC>
-__global__ __launch_bounds__(256) void k_gemm_nn_bf16x3(const float2* __restrict__ A, long lda,
-                                                        const float2* __restrict__ B, long ldb, int M, int N, int K,
+template <int BM, int BN, class AL>
+__global__ __launch_bounds__(256) void k_gemm_nn_bf16x3(const void* __restrict__ A0, const void* __restrict__ A1,
+                                                        long lda, const float2* __restrict__ B, long ldb, int M, int N,
+                                                        int K,
                                                         int tiles_n, float2* out, long ldo, EpiH e) {
   constexpr int WBM = BM / 32, WBN = BN / 32;
   constexpr int PA = 4 * BM * 8, PB = 4 * BN * 8;
@@ -414,11 +564,11 @@ __global__ __launch_bounds__(256) void k_gemm_nn_bf16x3(const float2* __restrict
       cr[a][b] = v4f16{0, 0, 0, 0};
       ci[a][b] = v4f16{0, 0, 0, 0};
     }
-  McSplit<BM, VEC> la;
+  AL la;
   KcSplitB<BN> lb;
   const int ntiles = (K + hBK - 1) / hBK;
   if (ntiles > 0) {
-    la.load(A, lda, M, i0, 0, K, tid);
+    la.load(A0, A1, lda, M, i0, 0, K, tid);
     lb.load(B, ldb, N, j0, 0, K, tid);
     la.store(sAh[0], sAl[0], tid);
     lb.store(sRH[0], sRL[0], sIH[0], sIL[0], tid);
@@ -429,7 +579,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn_bf16x3(const float2* __restrict
     const bool more = it + 1 < ntiles;
     if (more) {
       const int kn = (it + 1) * hBK;
-      la.load(A, lda, M, i0, kn, K, tid);
+      la.load(A0, A1, lda, M, i0, kn, K, tid);
       lb.load(B, ldb, N, j0, kn, K, tid);
     }
     v8bf ah[WBM], al[WBM];
@@ -517,9 +667,10 @@ hipError_t launch_gemm_cn_bf16x3(const float2* A, long lda, const float2* B, lon
   const long l2 = B2 ? ldb2 : ldb;
   const bool vec = ok16(A, lda) && ok16(B, ldb) && ok16(b2, l2);
   dim3 grid(tm * tn * nsplit);
-#define PW_CN16(V, NT)                                                                                              \
-  hipLaunchKernelGGL((k_gemm_cn_bf16x3<kCnBM, kCnBN, V, NT>), grid, dim3(256), 0, s, A, lda, B, ldb, b2, l2, ncol1, \
-                     M, N, K, kchunk, tm, tn, part)
+#define PW_CN16(V, NT)                                                                                            \
+  hipLaunchKernelGGL((k_gemm_cn_bf16x3<kCnBM, kCnBN, V, NT, CnAF32<kCnBM, V>>), grid, dim3(256), 0, s,          \
+                     static_cast<const void*>(A), static_cast<const void*>(nullptr), lda, B, ldb, b2, l2, ncol1, M, \
+                     N, K, kchunk, tm, tn, part)
   if (nterm == 4) {
     if (vec) PW_CN16(true, 4); else PW_CN16(false, 4);
   } else {
@@ -529,18 +680,61 @@ hipError_t launch_gemm_cn_bf16x3(const float2* A, long lda, const float2* B, lon
   return hipGetLastError();
 }
 
+static inline bool ok_planes(const void* h, const void* l, long lda) {
+  return (reinterpret_cast<uintptr_t>(h) & 15) == 0 && (reinterpret_cast<uintptr_t>(l) & 15) == 0 && (lda % 4) == 0;
+}
+
+hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda, const float2* B,
+                                        long ldb, int M, int N, int K, int nsplit, double2* part, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  int kchunk = ceil_div(K, nsplit);
+  kchunk = ceil_div(kchunk, hBK) * hBK;
+  if (kchunk <= 0) kchunk = hBK;
+  const int tm = ceil_div(M, kCnBM), tn = ceil_div(N, kCnBN);
+  const bool vec = ok_planes(Ahi, Alo, lda) && ok16(B, ldb);
+  dim3 grid(tm * tn * nsplit);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_cn_bf16x3<kCnBM, kCnBN, true, 3, CnAPlanes<kCnBM, true>>), grid, dim3(256), 0, s,
+                       static_cast<const void*>(Ahi), static_cast<const void*>(Alo), lda, B, ldb, B, ldb, N, M, N, K,
+                       kchunk, tm, tn, part);
+  else
+    hipLaunchKernelGGL((k_gemm_cn_bf16x3<kCnBM, kCnBN, false, 3, CnAPlanes<kCnBM, false>>), grid, dim3(256), 0, s,
+                       static_cast<const void*>(Ahi), static_cast<const void*>(Alo), lda, B, ldb, B, ldb, N, M, N, K,
+                       kchunk, tm, tn, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, long ldb, int M, int N, int K,
                                  float2* out, long ldo, const EpiH& e, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int tm = ceil_div(M, kNnBM), tn = ceil_div(N, kNnBN);
   const bool vec = ok16(A, lda);
   dim3 grid(tm * tn);
+  const void* a0 = A;
   if (vec)
-    hipLaunchKernelGGL((k_gemm_nn_bf16x3<kNnBM, kNnBN, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, tn,
-                       out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<kNnBM, kNnBN, NnAF32<kNnBM, true>>), grid, dim3(256), 0, s, a0, nullptr,
+                       lda, B, ldb, M, N, K, tn, out, ldo, e);
   else
-    hipLaunchKernelGGL((k_gemm_nn_bf16x3<kNnBM, kNnBN, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, tn,
-                       out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<kNnBM, kNnBN, NnAF32<kNnBM, false>>), grid, dim3(256), 0, s, a0, nullptr,
+                       lda, B, ldb, M, N, K, tn, out, ldo, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda, const float2* B,
+                                        long ldb, int M, int N, int K, float2* out, long ldo, const EpiH& e,
+                                        hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int tm = ceil_div(M, kNnBM), tn = ceil_div(N, kNnBN);
+  const bool vec = ok_planes(Ahi, Alo, lda);
+  dim3 grid(tm * tn);
+  const void* a0 = Ahi;
+  const void* a1 = Alo;
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<kNnBM, kNnBN, NnAPlanes<kNnBM, true>>), grid, dim3(256), 0, s, a0, a1, lda,
+                       B, ldb, M, N, K, tn, out, ldo, e);
+  else
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<kNnBM, kNnBN, NnAPlanes<kNnBM, false>>), grid, dim3(256), 0, s, a0, a1, lda,
+                       B, ldb, M, N, K, tn, out, ldo, e);
   return hipGetLastError();
 }
 

@@ -88,6 +88,13 @@ hipError_t launch_gemm_cn_bf16x3(const float2* A, long lda, const float2* B, lon
                                  int ncol1, int M, int N, int K, int nsplit, double2* part, int nterm, hipStream_t s);
 hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, long ldb, int M, int N, int K,
                                  float2* out, long ldo, const EpiH& e, hipStream_t s);
+// The same products with A given as pre-split bf16 planes (launch_beta_planes layout): cn with
+// A = M columns of length K, nn with A = K columns of length M.  lda counts 32-bit words.
+hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda, const float2* B,
+                                        long ldb, int M, int N, int K, int nsplit, double2* part, hipStream_t s);
+hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda, const float2* B,
+                                        long ldb, int M, int N, int K, float2* out, long ldo, const EpiH& e,
+                                        hipStream_t s);
 
 // --------------------------------------------------------------- misc ------
 template <typename T>
@@ -107,6 +114,10 @@ hipError_t launch_vg_sphere(const int* miller, int npw, const double* frac, cons
 template <typename T>
 hipError_t launch_beta_table(const int* miller, int npw, const double* frac, int natoms, const double* L,
                              double sigma, cplx<T>* beta, long ld, hipStream_t s);
+// Projector table as bf16 hi/lo planes (one 32-bit (re, im) word per entry, column-major, leading
+// dimension ld; rows npw..ld-1 zero), for the split-precision projector GEMMs.
+hipError_t launch_beta_planes(const int* miller, int npw, const double* frac, int natoms, const double* L,
+                              double sigma, unsigned int* hi, unsigned int* lo, long ld, hipStream_t s);
 template <typename T>
 hipError_t launch_convert_c64_to(const double2* in, long ldi, cplx<T>* out, long ldo, int rows, int cols,
                                  hipStream_t s);
