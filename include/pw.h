@@ -63,6 +63,12 @@ typedef enum {
 #define PW_FLAG_BF16_GRAM 2u
 #define PW_FLAG_BF16_KB 4u
 #define PW_FLAG_BF16_ROT 8u
+/* Generate the projector matrix inside the projector GEMMs from per-plane-wave radial factors
+   and per-atom axis phase factors (e^{-i G.tau} = product of three 1D factors) instead of
+   storing the N_pw x 4 N_atoms table: O(N_pw + N_atoms N^(1/3)) memory in place of
+   O(N_pw N_atoms).  For cells whose table does not fit (Si4096 in FP64: 219 GB).
+   Not combinable with PW_FLAG_BF16_KB. */
+#define PW_FLAG_BETA_OTF 16u
 
 typedef enum {
   PW_FP64 = 0,  /* every product and FFT in double precision */

@@ -137,6 +137,22 @@ struct Engine {
   // With split-precision projector products the table is stored as bf16 hi and lo planes of
   // one (re, im) word per entry, leading dimension ldw words, in the same arena bytes.
   bool beta_planes() const { return std::is_same<T, float>::value && flag(PW_FLAG_BF16_KB); }
+  bool beta_otf() const { return flag(PW_FLAG_BETA_OTF); }
+  BetaGen beta_gen() const {
+    BetaGen bg;
+    bg.miller = h->at<int>(P.lay.miller);
+    bg.rad = h->at<double>(P.lay.brad);
+    bg.ph = h->at<double2>(P.lay.bph);
+    bg.h1 = P.hmax[0];
+    bg.h2 = P.hmax[1];
+    bg.h3 = P.hmax[2];
+    bg.o2 = 2 * P.hmax[0] + 1;
+    bg.o3 = bg.o2 + 2 * P.hmax[1] + 1;
+    bg.w = P.bwidth;
+    bg.npw = P.npw;
+    bg.natoms = P.natoms;
+    return bg;
+  }
   unsigned int* beta_hi() const { return h->at<unsigned int>(P.lay.beta); }
   unsigned int* beta_lo() const { return beta_hi() + (size_t)P.ldw * P.nproj; }
 
@@ -201,7 +217,9 @@ struct Engine {
                                                             P.nsplit_proj, parts, h->stream));
         }
       }
-      if (!beta_planes())
+      if (beta_otf())
+        PW_TIMED(PW_PH_PROJ, launch_gemm_cn_beta<T>(beta_gen(), Y, ldy, nb, P.nsplit_proj, parts, h->stream));
+      else if (!beta_planes())
         PW_TIMED(PW_PH_PROJ, cn(false, beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw, P.nsplit_proj, parts));
       PW_TIMED(PW_PH_PROJ_REDUCE, launch_reduce_parts<T>(parts, P.nsplit_proj, P.nproj, nb,
                                                          h->at<double>(P.lay.dscale), 4, nullptr, 0, PT, P.nproj,
@@ -225,6 +243,10 @@ struct Engine {
                                                         out, ldo, e, h->stream));
         return PW_OK;
       }
+    }
+    if (beta_otf()) {
+      PW_TIMED(PW_PH_NL, launch_gemm_nn_beta<T>(beta_gen(), PT, P.nproj, nb, out, ldo, e, h->stream));
+      return PW_OK;
     }
     PW_TIMED(PW_PH_NL, nn(false, beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e));
     return PW_OK;
@@ -598,7 +620,10 @@ struct Engine {
         PW_HIP(launch_pencil_x<T>(G1, (const T*)nullptr, 1, g, tw1, 1, vr, p.fl, st));
       }
     }
-    if (p.nproj && beta_planes())
+    if (p.nproj && beta_otf())
+      PW_HIP(launch_beta_gen_tables(beta_gen(), h->at<double>(p.lay.frac), p.L, p.beta_sigma,
+                                    h->at<double>(p.lay.brad), h->at<double2>(p.lay.bph), st));
+    else if (p.nproj && beta_planes())
       PW_HIP(launch_beta_planes(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), p.natoms, p.L,
                                 p.beta_sigma, beta_hi(), beta_lo(), p.ldw, st));
     else if (p.nproj)

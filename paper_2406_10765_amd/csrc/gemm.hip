@@ -173,6 +173,111 @@ struct McLoader {
   }
 };
 
+// A-operand loaders of one interface: load(A, lda, bg, extent, offset, k0, kend, tid) and
+// store<LDS_LD>(S, tid).  The table loaders ignore bg; the generator loaders ignore A.
+template <typename T, int NC, bool VEC>
+struct CnATable {  // cn A: NC columns of a table
+  KcLoader<T, NC, VEC> l;
+  __device__ __forceinline__ void load(const cplx<T>* A, long lda, const BetaGen&, int ncols, int c0, int k0, int kend,
+                                       int tid) {
+    l.load(A, lda, A, lda, ncols, ncols, c0, k0, kend, tid);
+  }
+  template <int LDS_LD>
+  __device__ __forceinline__ void store(cplx<T>* S, int tid) const {
+    l.template store<LDS_LD>(S, tid);
+  }
+};
+template <typename T, int NR, bool VEC>
+struct NnATable {  // nn A: NR rows of a table
+  McLoader<T, NR, VEC> l;
+  __device__ __forceinline__ void load(const cplx<T>* A, long lda, const BetaGen&, int nrows, int r0, int k0, int kend,
+                                       int tid) {
+    l.load(A, lda, nrows, r0, k0, kend, tid);
+  }
+  template <int LDS_LD>
+  __device__ __forceinline__ void store(cplx<T>* S, int tid) const {
+    l.template store<LDS_LD>(S, tid);
+  }
+};
+
+// The four projectors of atom a at plane wave g (zero outside the sphere / atom range).
+template <typename T>
+__device__ __forceinline__ void beta_gen4(const BetaGen& bg, int g, int a, cplx<T> (&v)[4]) {
+  if (g >= bg.npw || a >= bg.natoms) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = mk<T>(0, 0);
+    return;
+  }
+  const int n1 = bg.miller[3 * g], n2 = bg.miller[3 * g + 1], n3 = bg.miller[3 * g + 2];
+  const double2* p = bg.ph + (long)a * bg.w;
+  const double2 e1 = p[n1 + bg.h1], e2 = p[bg.o2 + n2 + bg.h2], e3 = p[bg.o3 + n3 + bg.h3];
+  const double2 e12 = make_double2(e1.x * e2.x - e1.y * e2.y, e1.x * e2.y + e1.y * e2.x);
+  const double2 e = make_double2(e12.x * e3.x - e12.y * e3.y, e12.x * e3.y + e12.y * e3.x);
+  const double4 r = *reinterpret_cast<const double4*>(bg.rad + 4 * (long)g);
+  v[0] = mk<T>((T)(r.x * e.x), (T)(r.x * e.y));
+  v[1] = mk<T>((T)(r.y * e.x), (T)(r.y * e.y));
+  v[2] = mk<T>((T)(r.z * e.x), (T)(r.z * e.y));
+  v[3] = mk<T>((T)(r.w * e.x), (T)(r.w * e.y));
+}
+
+template <typename T, int NC, bool VEC>
+struct CnABeta {  // cn A = beta: NC columns (NC / 4 atoms from column c0) x kBK plane waves
+  static constexpr int UNITS = kBK * (NC / 4);
+  static constexpr int PER = (UNITS + 255) / 256;
+  cplx<T> r[PER][4];
+  __device__ __forceinline__ void load(const cplx<T>*, long, const BetaGen& bg, int, int c0, int k0, int kend,
+                                       int tid) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      const int k = idx % kBK, al = idx / kBK;
+      const int g = k0 + k;
+      beta_gen4<T>(bg, (idx < UNITS && g < kend) ? g : bg.npw, c0 / 4 + al, r[q]);
+    }
+  }
+  template <int LDS_LD>
+  __device__ __forceinline__ void store(cplx<T>* S, int tid) const {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < UNITS) {
+        const int k = idx % kBK, al = idx / kBK;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) S[k * LDS_LD + 4 * al + m] = r[q][m];
+      }
+    }
+  }
+};
+
+template <typename T, int NR, bool VEC>
+struct NnABeta {  // nn A = beta: NR plane waves from r0 x kBK columns (kBK / 4 atoms from k0)
+  static constexpr int UNITS = NR * (kBK / 4);
+  static constexpr int PER = (UNITS + 255) / 256;
+  cplx<T> r[PER][4];
+  __device__ __forceinline__ void load(const cplx<T>*, long, const BetaGen& bg, int nrows, int r0, int k0, int kend,
+                                       int tid) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      const int mu = idx % NR, al = idx / NR;
+      const int g = r0 + mu, a = k0 / 4 + al;
+      beta_gen4<T>(bg, (idx < UNITS && g < nrows && 4 * a < kend) ? g : bg.npw, a, r[q]);
+    }
+  }
+  template <int LDS_LD>
+  __device__ __forceinline__ void store(cplx<T>* S, int tid) const {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < UNITS) {
+        const int mu = idx % NR, al = idx / NR;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) S[(4 * al + m) * LDS_LD + mu] = r[q][m];
+      }
+    }
+  }
+};
+
 // Wave-level MFMA accumulation over one K tile held in LDS.
 // sA: kBK x (BM + 1) (m contiguous), sB: kBK x (BN + 1) (n contiguous).
 template <typename T, int WBM, int WBN, bool CONJ_A>
@@ -213,12 +318,12 @@ __device__ __forceinline__ void mma_tile(const cplx<T>* sA, const cplx<T>* sB, i
 // ------------------------------------------------------------------------------------------
 // cn: part[s] = A^H B over K chunk s.  Workgroup tile BM x BN (waves 2 x 2).
 // ------------------------------------------------------------------------------------------
-template <typename T, int BM, int BN, bool VEC>
+template <typename T, int BM, int BN, bool VEC, class AL>
 __global__ __launch_bounds__(256) void k_gemm_cn(const cplx<T>* __restrict__ A, long lda,
                                                  const cplx<T>* __restrict__ B, long ldb,
                                                  const cplx<T>* __restrict__ B2, long ldb2, int ncol1, int M, int N,
                                                  int K, int kchunk, int tiles_m, int tiles_n,
-                                                 double2* __restrict__ part) {
+                                                 double2* __restrict__ part, BetaGen bg) {
   constexpr int WBM = BM / 32, WBN = BN / 32;  // 16x16 blocks per wave
   constexpr int LA = BM + 1, LB = BN + 1;
   using acc_t = typename MF<T>::acc;
@@ -246,11 +351,11 @@ __global__ __launch_bounds__(256) void k_gemm_cn(const cplx<T>* __restrict__ A, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) dr[a][b][r] = di[a][b][r] = 0.0;
     }
-  KcLoader<T, BM, VEC> la;
+  AL la;
   KcLoader<T, BN, VEC> lb;
   const int ntiles = ke > kb ? (ke - kb + kBK - 1) / kBK : 0;
   if (ntiles > 0) {
-    la.load(A, lda, A, lda, M, M, i0, kb, ke, tid);
+    la.load(A, lda, bg, M, i0, kb, ke, tid);
     lb.load(B, ldb, B2, ldb2, ncol1, N, j0, kb, ke, tid);
     la.template store<LA>(sA[0], tid);
     lb.template store<LB>(sB[0], tid);
@@ -261,7 +366,7 @@ __global__ __launch_bounds__(256) void k_gemm_cn(const cplx<T>* __restrict__ A, 
     const bool more = it + 1 < ntiles;
     if (more) {
       const int kn = kb + (it + 1) * kBK;
-      la.load(A, lda, A, lda, M, M, i0, kn, ke, tid);
+      la.load(A, lda, bg, M, i0, kn, ke, tid);
       lb.load(B, ldb, B2, ldb2, ncol1, N, j0, kn, ke, tid);
     }
     mma_tile<T, WBM, WBN, true>(sA[cur], sB[cur], LA, LB, mo, no, lane, cr, ci);
@@ -330,10 +435,10 @@ __global__ void k_reduce_parts(const double2* __restrict__ part, int nsplit, int
 // ------------------------------------------------------------------------------------------
 // nn: out = epilogue(A B).  A: M x K (m contiguous), B: K x N (k contiguous).
 // ------------------------------------------------------------------------------------------
-template <typename T, int BM, int BN, bool VEC>
+template <typename T, int BM, int BN, bool VEC, class AL>
 __global__ __launch_bounds__(256) void k_gemm_nn(const cplx<T>* __restrict__ A, long lda,
                                                  const cplx<T>* __restrict__ B, long ldb, int M, int N, int K,
-                                                 int tiles_n, cplx<T>* out, long ldo, EpiH e) {
+                                                 int tiles_n, cplx<T>* out, long ldo, EpiH e, BetaGen bg) {
   constexpr int WBM = BM / 32, WBN = BN / 32;
   constexpr int LA = BM + 1, LB = BN + 1;
   using acc_t = typename MF<T>::acc;
@@ -352,11 +457,11 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const cplx<T>* __restrict__ A, 
       cr[a][b] = acc_t{0, 0, 0, 0};
       ci[a][b] = acc_t{0, 0, 0, 0};
     }
-  McLoader<T, BM, VEC> la;
+  AL la;
   KcLoader<T, BN, VEC> lb;
   const int ntiles = (K + kBK - 1) / kBK;
   if (ntiles > 0) {
-    la.load(A, lda, M, i0, 0, K, tid);
+    la.load(A, lda, bg, M, i0, 0, K, tid);
     lb.load(B, ldb, B, ldb, N, N, j0, 0, K, tid);
     la.template store<LA>(sA[0], tid);
     lb.template store<LB>(sB[0], tid);
@@ -367,7 +472,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const cplx<T>* __restrict__ A, 
     const bool more = it + 1 < ntiles;
     if (more) {
       const int kn = (it + 1) * kBK;
-      la.load(A, lda, M, i0, kn, K, tid);
+      la.load(A, lda, bg, M, i0, kn, K, tid);
       lb.load(B, ldb, B, ldb, N, N, j0, kn, K, tid);
     }
     mma_tile<T, WBM, WBN, false>(sA[cur], sB[cur], LA, LB, mo, no, lane, cr, ci);
@@ -459,12 +564,35 @@ hipError_t launch_gemm_cn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb
   const long l2 = B2 ? ldb2 : ldb;
   const bool vec = vec_ok<T>(A, lda) && vec_ok<T>(B, ldb) && vec_ok<T>(b2, l2);
   dim3 grid(tm * tn * nsplit);
+  const BetaGen none{};
   if (vec)
-    hipLaunchKernelGGL((k_gemm_cn<T, BM, BN, true>), grid, dim3(256), 0, s, A, lda, B, ldb, b2, l2, ncol1, M, N, K,
-                       kchunk, tm, tn, part);
+    hipLaunchKernelGGL((k_gemm_cn<T, BM, BN, true, CnATable<T, BM, true>>), grid, dim3(256), 0, s, A, lda, B, ldb, b2,
+                       l2, ncol1, M, N, K, kchunk, tm, tn, part, none);
   else
-    hipLaunchKernelGGL((k_gemm_cn<T, BM, BN, false>), grid, dim3(256), 0, s, A, lda, B, ldb, b2, l2, ncol1, M, N, K,
-                       kchunk, tm, tn, part);
+    hipLaunchKernelGGL((k_gemm_cn<T, BM, BN, false, CnATable<T, BM, false>>), grid, dim3(256), 0, s, A, lda, B, ldb,
+                       b2, l2, ncol1, M, N, K, kchunk, tm, tn, part, none);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gemm_cn_beta(const BetaGen& bg, const cplx<T>* B, long ldb, int N, int nsplit, double2* part,
+                               hipStream_t s) {
+  const int M = 4 * bg.natoms, K = bg.npw;
+  if (M <= 0 || N <= 0) return hipSuccess;
+  constexpr int BM = CnShape<T>::BM, BN = CnShape<T>::BN;
+  static_assert(BM % 4 == 0, "tile must hold whole atoms");
+  int kchunk = ceil_div(K, nsplit);
+  kchunk = ceil_div(kchunk, kBK) * kBK;
+  if (kchunk <= 0) kchunk = kBK;
+  const int tm = ceil_div(M, BM), tn = ceil_div(N, BN);
+  const cplx<T>* A = nullptr;
+  dim3 grid(tm * tn * nsplit);
+  if (vec_ok<T>(B, ldb))
+    hipLaunchKernelGGL((k_gemm_cn<T, BM, BN, true, CnABeta<T, BM, true>>), grid, dim3(256), 0, s, A, 0L, B, ldb, B,
+                       ldb, N, M, N, K, kchunk, tm, tn, part, bg);
+  else
+    hipLaunchKernelGGL((k_gemm_cn<T, BM, BN, false, CnABeta<T, BM, false>>), grid, dim3(256), 0, s, A, 0L, B, ldb, B,
+                       ldb, N, M, N, K, kchunk, tm, tn, part, bg);
   return hipGetLastError();
 }
 
@@ -486,11 +614,32 @@ hipError_t launch_gemm_nn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb
   const int tm = ceil_div(M, BM), tn = ceil_div(N, BN);
   const bool vec = vec_ok<T>(A, lda) && vec_ok<T>(B, ldb);
   dim3 grid(tm * tn);
+  const BetaGen none{};
   if (vec)
-    hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, tn, out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, true, NnATable<T, BM, true>>), grid, dim3(256), 0, s, A, lda, B, ldb, M,
+                       N, K, tn, out, ldo, e, none);
   else
-    hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, tn, out, ldo,
-                       e);
+    hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, false, NnATable<T, BM, false>>), grid, dim3(256), 0, s, A, lda, B, ldb,
+                       M, N, K, tn, out, ldo, e, none);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gemm_nn_beta(const BetaGen& bg, const cplx<T>* B, long ldb, int N, cplx<T>* out, long ldo,
+                               const EpiH& e, hipStream_t s) {
+  const int M = bg.npw, K = 4 * bg.natoms;
+  if (M <= 0 || N <= 0) return hipSuccess;
+  constexpr int BM = NnShape<T>::BM, BN = NnShape<T>::BN;
+  static_assert(kBK % 4 == 0, "K tile must hold whole atoms");
+  const int tm = ceil_div(M, BM), tn = ceil_div(N, BN);
+  const cplx<T>* A = nullptr;
+  dim3 grid(tm * tn);
+  if (vec_ok<T>(B, ldb))
+    hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, true, NnABeta<T, BM, true>>), grid, dim3(256), 0, s, A, 0L, B, ldb, M, N,
+                       K, tn, out, ldo, e, bg);
+  else
+    hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, false, NnABeta<T, BM, false>>), grid, dim3(256), 0, s, A, 0L, B, ldb, M,
+                       N, K, tn, out, ldo, e, bg);
   return hipGetLastError();
 }
 
@@ -500,7 +649,11 @@ hipError_t launch_gemm_nn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb
   template hipError_t launch_reduce_parts<T>(const double2*, int, int, int, const double*, int, double2*,   \
                                              long, cplx<T>*, long, hipStream_t);                             \
   template hipError_t launch_gemm_nn<T>(const cplx<T>*, long, const cplx<T>*, long, int, int, int, cplx<T>*, \
-                                        long, const EpiH&, hipStream_t);
+                                        long, const EpiH&, hipStream_t);                                     \
+  template hipError_t launch_gemm_cn_beta<T>(const BetaGen&, const cplx<T>*, long, int, int, double2*,      \
+                                             hipStream_t);                                                   \
+  template hipError_t launch_gemm_nn_beta<T>(const BetaGen&, const cplx<T>*, long, int, cplx<T>*, long,     \
+                                             const EpiH&, hipStream_t);
 PW_INST_GEMM(float)
 PW_INST_GEMM(double)
 

@@ -53,6 +53,8 @@ hipError_t launch_pencil_yfwd(cplx<T>* SB, const cplx<T>* G1, int nbatch, const 
 // with index >= nsplit_col come from B2).  Partials are complex double, [s][N][M].
 // Number of output tiles of the cn kernel for an M x N result (used to choose the K split).
 int gemm_cn_tiles(int M, int N, bool fp64);
+
+
 template <typename T>
 hipError_t launch_gemm_cn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const cplx<T>* B2,
                           long ldb2, int ncol1, int M, int N, int K, int nsplit, double2* part, hipStream_t s);
@@ -77,6 +79,31 @@ struct EpiH {
   const void* Yp;  // may be null when beta == 0
   long ldp;
 };
+
+// Generator of the projector matrix inside the GEMM loaders, for cells whose table would not
+// fit:  beta[g, 4a+m] = rad[4g+m] * ph_a(n1) ph_a(n2) ph_a(n3), where rad holds
+// (c/sqrt(Omega)) e^{-sigma^2|G|^2/2} Y_m(G) per plane wave and ph_a the per-atom factors
+// e^{-2 pi i n f_d(a)} of each axis d (f = fractional position), n from -h_d to h_d.
+struct BetaGen {
+  const int* miller;    // 3 * npw
+  const double* rad;    // 4 * npw
+  const double2* ph;    // natoms * w
+  int h1, h2, h3;       // offsets of n = 0 in the three axis tables
+  int o2, o3;           // start of the axis-2 and axis-3 tables within one atom's row
+  int w;                // (2 h1 + 1) + (2 h2 + 1) + (2 h3 + 1)
+  int npw, natoms;
+};
+// part[s] = beta^H B over K chunk s with beta generated on the fly (M = 4 natoms columns).
+template <typename T>
+hipError_t launch_gemm_cn_beta(const BetaGen& bg, const cplx<T>* B, long ldb, int N, int nsplit, double2* part,
+                               hipStream_t s);
+// out = epilogue(beta B) with beta generated on the fly (K = 4 natoms).
+template <typename T>
+hipError_t launch_gemm_nn_beta(const BetaGen& bg, const cplx<T>* B, long ldb, int N, cplx<T>* out, long ldo,
+                               const EpiH& e, hipStream_t s);
+// Tables of BetaGen: rad (npw x 4) and the per-atom axis factors (natoms x w).
+hipError_t launch_beta_gen_tables(const BetaGen& bg, const double* frac, const double* L, double sigma,
+                                  double* rad, double2* ph, hipStream_t s);
 template <typename T>
 hipError_t launch_gemm_nn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb, int M, int N, int K,
                           cplx<T>* out, long ldo, const EpiH& e, hipStream_t s);

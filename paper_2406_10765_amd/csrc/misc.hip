@@ -128,6 +128,54 @@ __global__ void k_beta_planes(const int* __restrict__ miller, int npw, const dou
   }
 }
 
+// Tables of the on-the-fly projector generator: rad[4g+m] = (c/sqrt(Omega)) e^{-sigma^2|G|^2/2} Y_m(G)
+// and, per atom, e^{-2 pi i n f_d} for each axis d and n in [-h_d, h_d].
+__global__ void k_beta_rad(const int* __restrict__ miller, int npw, double L0, double L1, double L2, double sigma,
+                           double* __restrict__ rad) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= npw) return;
+  const int n1 = miller[3 * g], n2 = miller[3 * g + 1], n3 = miller[3 * g + 2];
+  const double gx = 2.0 * kPi * n1 / L0, gy = 2.0 * kPi * n2 / L1, gz = 2.0 * kPi * n3 / L2;
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  const double c = sqrt(32.0 * pow(kPi, 2.5) * sigma * sigma * sigma);
+  const double radial = c / sqrt(L0 * L1 * L2) * exp(-0.5 * sigma * sigma * g2);
+  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  const double gn = sqrt(g2);
+  const double inv = gn > 0.0 ? c1 / gn : 0.0;
+  rad[4 * (long)g] = radial * (0.5 / sqrt(kPi));
+  rad[4 * (long)g + 1] = radial * gx * inv;
+  rad[4 * (long)g + 2] = radial * gy * inv;
+  rad[4 * (long)g + 3] = radial * gz * inv;
+}
+
+__global__ void k_beta_phase(BetaGen bg, const double* __restrict__ frac, double2* __restrict__ ph) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= bg.w) return;
+  int d, n;
+  if (i < bg.o2) {
+    d = 0;
+    n = i - bg.h1;
+  } else if (i < bg.o3) {
+    d = 1;
+    n = i - bg.o2 - bg.h2;
+  } else {
+    d = 2;
+    n = i - bg.o3 - bg.h3;
+  }
+  ph[(long)a * bg.w + i] = expm2pi(n * frac[3 * a + d]);
+}
+
+hipError_t launch_beta_gen_tables(const BetaGen& bg, const double* frac, const double* L, double sigma, double* rad,
+                                  double2* ph, hipStream_t s) {
+  if (bg.npw > 0)
+    hipLaunchKernelGGL(k_beta_rad, dim3(ceil_div(bg.npw, 256)), dim3(256), 0, s, bg.miller, bg.npw, L[0], L[1], L[2],
+                       sigma, rad);
+  if (bg.natoms > 0)
+    hipLaunchKernelGGL(k_beta_phase, dim3(ceil_div(bg.w, 256), bg.natoms), dim3(256), 0, s, bg, frac, ph);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ void k_convert(const double2* __restrict__ in, long ldi, cplx<T>* __restrict__ out, long ldo, int rows,
                           int cols) {

@@ -51,8 +51,13 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   if (d->natoms < 0 || (d->natoms > 0 && !d->tau)) { *err = "bad atoms"; return PW_EINVAL; }
   if (d->nbands < 1) { *err = "nbands must be >= 1"; return PW_EINVAL; }
   if (d->prec != PW_FP64 && d->prec != PW_MIXED) { *err = "unknown precision"; return PW_EINVAL; }
-  const unsigned known = PW_FLAG_PENCIL_FFT | PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT;
+  const unsigned known =
+      PW_FLAG_PENCIL_FFT | PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT | PW_FLAG_BETA_OTF;
   if (d->flags & ~known) { *err = "unknown flag bits"; return PW_EINVAL; }
+  if ((d->flags & PW_FLAG_BETA_OTF) && (d->flags & PW_FLAG_BF16_KB)) {
+    *err = "PW_FLAG_BETA_OTF cannot be combined with PW_FLAG_BF16_KB";
+    return PW_EINVAL;
+  }
   if (d->prec == PW_FP64 && (d->flags & (PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT))) {
     *err = "bf16 split products need PW_MIXED";
     return PW_EINVAL;
@@ -248,7 +253,14 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   L.mpha = take(sizeof(double) * std::max<size_t>(1, P.mode_amp.size()));
   L.vg = take(sizeof(double) * 2 * P.npw);
   L.dscale = take(sizeof(double) * 4);
-  L.beta = take(cb * P.ldw * P.nproj);
+  const bool otf = (P.flags & PW_FLAG_BETA_OTF) != 0;
+  for (int i = 0; i < 3; ++i) P.hmax[i] = 0;
+  for (int gi = 0; gi < P.npw; ++gi)
+    for (int i = 0; i < 3; ++i) P.hmax[i] = std::max(P.hmax[i], std::abs(P.miller[3 * gi + i]));
+  P.bwidth = (2 * P.hmax[0] + 1) + (2 * P.hmax[1] + 1) + (2 * P.hmax[2] + 1);
+  L.beta = take(otf ? 0 : cb * P.ldw * P.nproj);
+  L.brad = take(otf ? sizeof(double) * 4 * P.npw : 0);
+  L.bph = take(otf ? 16 * (size_t)P.natoms * P.bwidth : 0);
   const bool blocked = P.nbb < P.nbands;
   L.u0 = take(cb * P.ldw * P.nbb);
   L.u1 = take(cb * P.ldw * P.nbb);

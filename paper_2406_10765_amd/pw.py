@@ -173,6 +173,7 @@ PW_FLAG_BF16_GRAM = 2
 PW_FLAG_BF16_KB = 4
 PW_FLAG_BF16_ROT = 8
 PW_FLAG_BF16_ALL = PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT
+PW_FLAG_BETA_OTF = 16
 
 
 def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,

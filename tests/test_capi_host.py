@@ -106,3 +106,22 @@ def test_filter_block_planning():
     # the blocked Si4096 mixed plan fits in the 288 GB of one MI355X next to the 55 GB block X
     assert info.footprint_bytes + si4096.nbands * ((info.npw + 15) // 16 * 16) * 8 < 270e9
     assert pw.plan(synth.make_cell("si8"), filter_block=8).filter_block == 8
+
+
+def test_generated_projector_plan():
+    si64, si4096 = synth.make_cell("si64"), synth.make_cell("si4096")
+    table = pw.plan(si64, pw.PW_FP64)
+    gen = pw.plan(si64, pw.PW_FP64, flags=pw.PW_FLAG_BETA_OTF)
+    # the 16-byte table of N_pw x 4 N_atoms entries is replaced by O(N_pw + N_atoms) tables
+    ldw = (gen.npw + 15) // 16 * 16
+    assert table.footprint_bytes - gen.footprint_bytes >= 16 * ldw * gen.nproj - 40 * ldw
+    # Si4096 in FP64 fits one MI355X only with generated projectors: plan + X below 288 GB
+    info = pw.plan(si4096, pw.PW_FP64, flags=pw.PW_FLAG_BETA_OTF)
+    x_bytes = si4096.nbands * ((info.npw + 15) // 16 * 16) * 16
+    assert info.filter_block < si4096.nbands
+    assert info.footprint_bytes + x_bytes < 260e9
+    assert pw.plan(si4096, pw.PW_FP64).footprint_bytes + x_bytes > 288e9
+    # not combinable with the pre-split projector planes
+    d, keep = _desc(si64, prec=pw.PW_MIXED, flags=pw.PW_FLAG_BETA_OTF | pw.PW_FLAG_BF16_KB)
+    info = pw.Info()
+    assert pw.lib().pw_plan(ctypes.byref(d), ctypes.byref(info)) == pw.PW_EINVAL

@@ -305,3 +305,41 @@ def test_blocked_apply_h_and_solve_si8():
     eig, res, steps, conv = hb.solve(Xd, cell.nocc, 1e-7, degree=10, b=1.01 * lam[-1])
     say("blocked solve steps", steps, "max |de|", np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max())
     assert conv and np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max() < 1e-8
+
+
+# --- projectors generated inside the GEMMs (no table) ------------------------------------------
+
+@pytest.mark.parametrize("name,prec,nb,tol", [("si8", pw.PW_FP64, 20, 1e-12), ("si64", pw.PW_FP64, 7, 1e-12),
+                                               ("si64", pw.PW_MIXED, 9, 2e-5)])
+def test_apply_h_generated_projectors(name, prec, nb, tol):
+    say("apply_h generated projectors", name, prec, nb)
+    err, h = apply_case(synth.make_cell(name, modes=True), prec, nb, 700 + nb, flags=pw.PW_FLAG_BETA_OTF)
+    say("  rel err", err)
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec,etol", [(pw.PW_FP64, 1e-10), (pw.PW_MIXED, 1e-5)])
+def test_blocked_step_generated_projectors_si64(prec, etol):
+    """The memory plan of Si4096 in FP64 (band blocks + generated projectors), forced at Si64,
+    against the oracle's step from the same block and bounds."""
+    cell = synth.make_cell("si64")
+    model = O.model_from_cell(cell)
+    hop = lambda X: O.apply_h(model, X)
+    h = pw.Handle(cell, prec, flags=pw.PW_FLAG_BETA_OTF, filter_block=64)
+    assert h.info.filter_block == 64
+    p = to_gpu_order(h, model)
+    inv = np.argsort(p)
+    X0g = synth.initial_block(h.gvectors(), cell.L, cell.nbands, synth.SEED_X0 + 1)
+    b = 1.01 * O.lanczos_max(hop, model.npw, 20, seed=3)
+    s1 = O.eig_step(hop, X0g[inv], 0, 0.0, 0.0, b)
+    s2 = O.eig_step(hop, s1.X, 10, s1.a_lo, s1.a, b)
+    Xd = h.to_device(X0g)
+    e1, r1, _ = h.eig_step(Xd, 0, b=b)
+    e2, r2, _ = h.eig_step(Xd, 10, s1.a_lo, s1.a, b)
+    d1 = np.abs(e1 - s1.eig)[: cell.nocc].max()
+    d2 = np.abs(e2 - s2.eig)[: cell.nocc].max()
+    say("generated projectors si64", prec, "m=0", d1, "m=10", d2)
+    assert d1 < etol and d2 < etol
+    if prec == pw.PW_FP64:
+        assert np.abs(r2 - s2.resid).max() < 1e-9
+    h.close()
