@@ -49,7 +49,8 @@ def phase_work(name: str, info, nb: int, m: int, steps: int, real_bytes: int, n1
     if name == "proj" or name == "nl":
         return 8.0 * npw * nproj * nb * happs, "flop"
     if name == "gram":
-        return 8.0 * npw * nb * (2 * nb) * steps, "flop"
+        # S = Y^H Y (Hermitian: one triangle, 4 N_pw N_b^2) and H_s = Y^H W (8 N_pw N_b^2)
+        return 12.0 * npw * nb * nb * steps, "flop"
     if name == "rotate":
         return 8.0 * npw * nb * nb * 2 * steps, "flop"
     if name == "sticks_inv" or name == "sticks_fwd":
@@ -65,14 +66,70 @@ def phase_work(name: str, info, nb: int, m: int, steps: int, real_bytes: int, n1
     return None, None
 
 
-def run_steps(h, X, m, steps, bounds, b):
+# flops the kernels execute per algorithmic flop: the Gram kernel forms all of S
+EXECUTED_PER_ALGORITHMIC = {"gram": 16.0 / 12.0}
+
+
+def phase_table(stats, info, nb, m, steps, real_bytes, n1a, nterm, fp64=False):
+    """Per-phase rates over the timed steps and the roofline entry of the longest phase."""
+    mfma_peak = PEAK_MFMA_TFLOPS["fp64" if fp64 else "fp32"]
+    phases = {}
+    dom, dom_ms = None, -1.0
+    for name, st in stats.items():
+        if st["launches"] == 0:
+            continue
+        amount, kind = phase_work(name, info, nb, m, steps, real_bytes, n1a)
+        entry = {"launches": st["launches"], "ms_total": round(st["ms"], 3),
+                 "ms_per_launch": round(st["ms"] / st["launches"], 4)}
+        if amount is not None:
+            if kind == "flop":
+                entry["tflops"] = round(amount / (st["ms"] * 1e-3) / 1e12, 2)
+                if name in nterm:
+                    ex = entry["tflops"] * nterm[name] * EXECUTED_PER_ALGORITHMIC.get(name, 1.0)
+                    entry["dtype"] = "bf16x%d" % nterm[name]
+                    entry["tflops_bf16_executed"] = round(ex, 2)
+                    entry["frac_peak"] = round(entry["tflops"] / PEAK_BF16_TFLOPS, 4)
+                    entry["frac_peak_executed"] = round(ex / PEAK_BF16_TFLOPS, 4)
+                else:
+                    entry["dtype"] = "fp64" if fp64 else "fp32"
+                    entry["frac_peak"] = round(entry["tflops"] / mfma_peak, 4)
+            else:
+                entry["gbs"] = round(amount / (st["ms"] * 1e-3) / 1e9, 1)
+                entry["frac_peak"] = round(entry["gbs"] / PEAK_HBM_GBS, 4)
+            if st["ms"] > dom_ms:
+                dom, dom_ms = name, st["ms"]
+        phases[name] = entry
+    if dom is None:
+        return phases, None, None
+    d = phases[dom]
+    amount, kind = phase_work(dom, info, nb, m, steps, real_bytes, n1a)
+    per_launch = amount / stats[dom]["launches"]
+    if kind == "flop":
+        peak = PEAK_BF16_TFLOPS if dom in nterm else mfma_peak
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": d["tflops"], "peak": peak, "unit": "TFLOP/s",
+                    "frac": d["frac_peak"], "traffic": None, "algorithmic_per_launch": per_launch,
+                    "avg_launch_ms": d["ms_per_launch"]}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": d["frac_peak"], "traffic": None, "algorithmic_per_launch": per_launch,
+                    "avg_launch_ms": d["ms_per_launch"]}
+    return phases, dom, roofline
+
+
+def run_steps(h, X, m, steps, bounds, b, keep_first=False):
     import torch
 
-    eig = res = None
-    for _ in range(steps):
+    eig = res = first = None
+    for i in range(steps):
         eig, res, bnd = h.eig_step(X, m, bounds[0], bounds[1], b)
         bounds = (bnd[0], bnd[1])
+        if i == 0:
+            first = eig.copy()
+        if steps > 1:
+            log(f"  step {i + 1}/{steps} done")
     torch.cuda.synchronize()
+    if keep_first:
+        return eig, res, bounds, first
     return eig, res, bounds
 
 
@@ -229,6 +286,13 @@ def main():
     # ---- mixed precision (the headline) --------------------------------------------------
     t0 = time.time()
     mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
+    dev_bytes = torch.cuda.get_device_properties(0).total_memory
+    minfo = pw.plan(cell, pw.PW_MIXED, flags=mflags)
+    ldp = (minfo.npw + 15) // 16 * 16
+    big = minfo.footprint_bytes + 2 * nb * ldp * 8 > 0.9 * dev_bytes
+    if big:
+        # band-blocked steps of minutes: report each filter block as it completes
+        os.environ["PW_PROGRESS"] = "1"
     hm = pw.Handle(cell, pw.PW_MIXED, flags=mflags)
     G = hm.gvectors()
     n1a = 2 * int(np.abs(G[:, 0]).max()) + 1
@@ -236,14 +300,19 @@ def main():
     X = hm.random_block(nb, synth.SEED_X0 + synth.WORKLOADS[args.workload]["index"])
     eig, res, bnd = hm.eig_step(X, 0, b=b)
     bounds = (bnd[0], bnd[1])
-    log(f"setup {time.time() - t0:.1f}s  npw={hm.npw} nb={nb} b={b:.4f} fused_planes={hm.info.fused_planes}")
-    log(f"first (degree 0) step done")
+    log(f"setup and first (degree 0) step {time.time() - t0:.1f}s  npw={hm.npw} nb={nb} b={b:.4f} "
+        f"fused_planes={hm.info.fused_planes} filter_block={hm.info.filter_block}")
     eig, res, bounds = run_steps(hm, X, m, args.warmup, bounds, b)
+    # snapshot of the block the timed steps start from (the FP64 form starts from it too)
+    snap = None
+    if not args.no_fp64:
+        snap = X.cpu() if big else X.clone()
+    bounds_m = bounds
     hm.reset_stats()
     hm.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    eig, res, bounds = run_steps(hm, X, m, args.steps, bounds, b)
+    eig, res, bounds, eig_first = run_steps(hm, X, m, args.steps, bounds, b, keep_first=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = hm.stats()
@@ -261,82 +330,57 @@ def main():
         nterm["gram"] = 4
     if mflags & 8:
         nterm["rotate"] = 3
-    phases = {}
-    dom, dom_ms = None, -1.0
-    for name, st in stats.items():
-        if st["launches"] == 0:
-            continue
-        amount, kind = phase_work(name, hm.info, nb, m, args.steps, 4, n1a)
-        entry = {"launches": st["launches"], "ms_total": round(st["ms"], 3),
-                 "ms_per_launch": round(st["ms"] / st["launches"], 4)}
-        if amount is not None:
-            if kind == "flop":
-                entry["tflops"] = round(amount / (st["ms"] * 1e-3) / 1e12, 2)
-                if name in nterm:
-                    entry["dtype"] = "bf16x%d" % nterm[name]
-                    entry["tflops_bf16_executed"] = round(entry["tflops"] * nterm[name], 2)
-                    entry["frac_peak"] = round(entry["tflops"] / PEAK_BF16_TFLOPS, 4)
-                    entry["frac_peak_executed"] = round(entry["tflops_bf16_executed"] / PEAK_BF16_TFLOPS, 4)
-                else:
-                    entry["dtype"] = "fp32"
-                    entry["frac_peak"] = round(entry["tflops"] / PEAK_MFMA_TFLOPS["fp32"], 4)
-            else:
-                entry["gbs"] = round(amount / (st["ms"] * 1e-3) / 1e9, 1)
-                entry["frac_peak"] = round(entry["gbs"] / PEAK_HBM_GBS, 4)
-            if st["ms"] > dom_ms:
-                dom, dom_ms = name, st["ms"]
-        phases[name] = entry
-    d = phases[dom]
-    amount, kind = phase_work(dom, hm.info, nb, m, args.steps, 4, n1a)
-    per_launch = amount / stats[dom]["launches"]
-    if kind == "flop":
-        peak = PEAK_BF16_TFLOPS if dom in nterm else PEAK_MFMA_TFLOPS["fp32"]
-        roofline = {"bound": "mfma", "kernel": dom, "achieved": d["tflops"], "peak": peak,
-                    "unit": "TFLOP/s", "frac": d["frac_peak"], "traffic": None,
-                    "algorithmic_per_launch": per_launch, "avg_launch_ms": d["ms_per_launch"]}
-    else:
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": d["frac_peak"], "traffic": None, "algorithmic_per_launch": per_launch,
-                    "avg_launch_ms": d["ms_per_launch"]}
+    phases, dom, roofline = phase_table(stats, hm.info, nb, m, args.steps, 4, n1a, nterm)
 
-    # ---- FP64 form and accuracy of one step from the same block -----------------------------
+    # ---- FP64 form from the same block and bounds -----------------------------------------
     fp64 = None
     accuracy = None
-    bounds_m = bounds
     info = hm.info
-    ldp = (G.shape[0] + 15) // 16 * 16
-    fp64_bytes = pw.plan(cell, pw.PW_FP64).footprint_bytes + nb * ldp * (16 + 16 + 8)
-    fp64_fits = fp64_bytes <= torch.cuda.get_device_properties(0).total_memory
-    Xm = X.clone() if (fp64_fits and not args.no_fp64) else None
     del hm, X
     torch.cuda.empty_cache()
-    if not fp64_fits:
-        log(f"fp64 form skipped: needs {fp64_bytes / 1e9:.0f} GB with the projector table")
-        fp64 = {"skipped": "needs %.0f GB of device memory with the projector table" % (fp64_bytes / 1e9)}
-    elif not args.no_fp64:
-        hd = pw.Handle(cell, pw.PW_FP64)
-        Xd = Xm.to(torch.complex128)
-        e64, r64, _ = hd.eig_step(Xd.clone(), m, bounds_m[0], bounds_m[1], b)
+    x64_bytes = nb * ldp * 16
+    fp64_flags = 0
+    if pw.plan(cell, pw.PW_FP64).footprint_bytes + x64_bytes > 0.9 * dev_bytes:
+        fp64_flags = pw.PW_FLAG_BETA_OTF  # projectors generated in the GEMMs (no table)
+    fp64_need = pw.plan(cell, pw.PW_FP64, flags=fp64_flags).footprint_bytes + x64_bytes
+    if args.no_fp64:
+        pass
+    elif fp64_need > 0.9 * dev_bytes:
+        log(f"fp64 form skipped: needs {fp64_need / 1e9:.0f} GB")
+        fp64 = {"skipped": "needs %.0f GB of device memory" % (fp64_need / 1e9)}
+    else:
+        hd = pw.Handle(cell, pw.PW_FP64, flags=fp64_flags)
+        Xd = hd.empty_block(nb)
+        chunk = 256
+        for c0 in range(0, nb, chunk):
+            Xd[c0:c0 + chunk].copy_(snap[c0:c0 + chunk].to("cuda", non_blocking=False))
+        del snap
+        steps64 = 1 if big else args.fp64_steps
+        if not big:
+            # warm the FP64 handle (solver workspace) on a copy, untimed
+            Xw = Xd.clone()
+            hd.eig_step(Xw, m, bounds_m[0], bounds_m[1], b)
+            del Xw
+        hd.reset_stats()
+        hd.set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Xt = Xd.clone()
-        bd = bounds_m
-        for _ in range(args.fp64_steps):
-            e, r, bb = hd.eig_step(Xt, m, bd[0], bd[1], b)
-            bd = (bb[0], bb[1])
+        e64, r64, bd, e64_first = run_steps(hd, Xd, m, steps64, bounds_m, b, keep_first=True)
         torch.cuda.synchronize()
         dt64 = time.perf_counter() - t0
-        ms64 = 1000.0 * dt64 / args.fp64_steps
-        fp64 = {"value": 1000.0 / ms64, "unit": "eig-steps/s", "ms_per_step": round(ms64, 2),
-                "band_apps_per_sec": (m + 1) * nb / (ms64 / 1000.0)}
-        del hd
-        torch.cuda.empty_cache()
-        hm2 = pw.Handle(cell, pw.PW_MIXED, flags=mflags)
-        e32, r32, _ = hm2.eig_step(Xm.clone(), m, bounds_m[0], bounds_m[1], b)
+        st64 = hd.stats()
+        hd.set_timing(False)
+        ms64 = 1000.0 * dt64 / steps64
+        ph64, dom64, roof64 = phase_table(st64, hd.info, nb, m, steps64, 8, n1a, {}, fp64=True)
+        fp64 = {"value": 1000.0 / ms64, "unit": "eig-steps/s", "ms_per_step": round(ms64, 2), "steps": steps64,
+                "band_apps_per_sec": (m + 1) * nb / (ms64 / 1000.0),
+                "generated_projectors": bool(fp64_flags & pw.PW_FLAG_BETA_OTF),
+                "roofline": roof64, "phases": ph64}
         nocc = cell.nocc
-        accuracy = {"max_abs_deig_occ_mixed_vs_fp64_Ha": float(np.abs(e32[:nocc] - e64[:nocc]).max()),
-                    "bands_compared": nocc, "what": "one degree-%d step from the same block" % m}
-        del hm2
+        accuracy = {"max_abs_deig_occ_mixed_vs_fp64_Ha": float(np.abs(eig_first[:nocc] - e64_first[:nocc]).max()),
+                    "bands_compared": nocc, "what": "first timed degree-%d step of each form, same block and bounds" % m}
+        del hd, Xd
+        torch.cuda.empty_cache()
         log(f"fp64: {ms64:.1f} ms/step; one-step |de| mixed vs fp64 = {accuracy['max_abs_deig_occ_mixed_vs_fp64_Ha']:.2e}")
 
     serving = None

@@ -12,7 +12,10 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
+#include <cstdio>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -38,6 +41,17 @@ struct pw_handle_s {
   size_t max_lds = kDefaultMaxLds;
   std::string err;
   double bmax_cached = NAN;
+  // PW_PROGRESS=1 in the environment: report each completed filter block of a band-blocked
+  // step on stderr (the stream is synchronised at each report).
+  bool progress = false;
+  std::chrono::steady_clock::time_point t_step;
+  void report(const char* what, int i, int n) {
+    if (!progress) return;
+    (void)hipStreamSynchronize(stream);
+    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_step).count();
+    std::fprintf(stderr, "pw: %s %d/%d done at %.1f s\n", what, i, n, t);
+    std::fflush(stderr);
+  }
   // phase timers
   bool timing = false;
   hipEvent_t open_ev = nullptr;
@@ -296,15 +310,19 @@ struct Engine {
     const long ldw = P.ldw;
     cplx<T>* W = h->at<cplx<T>>(P.lay.wf);
     pw_status s;
+    const int nblk = (nb + P.nbb - 1) / P.nbb;
+    h->t_step = std::chrono::steady_clock::now();
     for (int c0 = 0; c0 < nb; c0 += P.nbb) {
       const int w = std::min(P.nbb, nb - c0);
       s = filter_block(X + (long)c0 * ld, ld, w, prm);
       if (s != PW_OK) return s;
       s = hop(X + (long)c0 * ld, ld, w, W + (long)c0 * ldw, ldw, zb(), ldw, 1.0, 0.0, 0.0, nullptr, 0);
       if (s != PW_OK) return s;
+      h->report("filter block", c0 / P.nbb + 1, nblk);
     }
     s = project_solve(X, ld, W, ldw, nb);
     if (s != PW_OK) return s;
+    h->report("Gram and eigensolve", 1, 1);
     const cplx<T>* C = coeffs(nb);
     double* eig_d = h->at<double>(P.lay.eig);
     double* resid_d = h->at<double>(P.lay.resid);
@@ -735,6 +753,7 @@ pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes
   }
   h->device = dev;
   h->max_lds = device_max_lds();
+  if (const char* e = std::getenv("PW_PROGRESS")) h->progress = e[0] == '1';
   std::string err;
   pw_status s;
   try {
