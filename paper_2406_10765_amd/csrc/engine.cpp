@@ -44,6 +44,8 @@ struct pw_handle_s {
   // PW_PROGRESS=1 in the environment: report each completed filter block of a band-blocked
   // step on stderr (the stream is synchronised at each report).
   bool progress = false;
+  // Block whose bf16 planes the planes buffer holds (split-precision projectors), or null.
+  const void* yp_src = nullptr;
   std::chrono::steady_clock::time_point t_step;
   void report(const char* what, int i, int n) {
     if (!progress) return;
@@ -169,6 +171,8 @@ struct Engine {
   }
   unsigned int* beta_hi() const { return h->at<unsigned int>(P.lay.beta); }
   unsigned int* beta_lo() const { return beta_hi() + (size_t)P.ldw * P.nproj; }
+  unsigned int* yp_hi() const { return h->at<unsigned int>(P.lay.yp); }
+  unsigned int* yp_lo() const { return yp_hi() + (size_t)P.ldw * P.nbb; }
 
   hipError_t cn(bool split16, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const cplx<T>* B2, long ldb2,
                 int ncol1, int M, int N, int K, int nsplit, double2* part, int nterm = 3) {
@@ -218,8 +222,10 @@ struct Engine {
 
   // out = alpha ((kin - c) Y + Zl + B D B^H Y) - beta Yp, where Zl is first filled with the
   // local potential part.  Zl may equal out (apply_h); Yp may equal out (in-place update).
+  // planes_out: also write the bf16 planes of out (split-precision projectors), for a following
+  // hop on out.
   pw_status hop(const cplx<T>* Y, long ldy, int nb, cplx<T>* out, long ldo, cplx<T>* Zl, long ldz, double alpha,
-                double c, double beta_c, const cplx<T>* Yp, long ldp) {
+                double c, double beta_c, const cplx<T>* Yp, long ldp, bool planes_out = false) {
     pw_status s = local_part(Y, ldy, Zl, ldz, nb);
     if (s != PW_OK) return s;
     cplx<T>* PT = h->at<cplx<T>>(P.lay.pt);
@@ -227,8 +233,10 @@ struct Engine {
       double2* parts = h->at<double2>(P.lay.parts);
       if constexpr (std::is_same<T, float>::value) {
         if (beta_planes()) {
-          PW_TIMED(PW_PH_PROJ, launch_gemm_cn_bf16x3_planes(beta_hi(), beta_lo(), P.ldw, Y, ldy, P.nproj, nb, P.npw,
-                                                            P.nsplit_proj, parts, h->stream));
+          if (h->yp_src != static_cast<const void*>(Y))
+            PW_TIMED(PW_PH_OTHER, launch_split_planes(Y, ldy, P.npw, nb, yp_hi(), yp_lo(), P.ldw, h->stream));
+          PW_TIMED(PW_PH_PROJ, launch_gemm_cn_bf16x3_planes(beta_hi(), beta_lo(), P.ldw, yp_hi(), yp_lo(), P.ldw,
+                                                            P.nproj, nb, P.npw, P.nsplit_proj, parts, h->stream));
         }
       }
       if (beta_otf())
@@ -251,10 +259,19 @@ struct Engine {
     e.ldz = ldz;
     e.Yp = Yp;
     e.ldp = ldp;
+    e.ph = e.pl = nullptr;
+    e.ldpl = 0;
+    h->yp_src = nullptr;
     if constexpr (std::is_same<T, float>::value) {
       if (beta_planes()) {
+        if (planes_out) {
+          e.ph = yp_hi();
+          e.pl = yp_lo();
+          e.ldpl = P.ldw;
+        }
         PW_TIMED(PW_PH_NL, launch_gemm_nn_bf16x3_planes(beta_hi(), beta_lo(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj,
                                                         out, ldo, e, h->stream));
+        if (planes_out) h->yp_src = out;
         return PW_OK;
       }
     }
@@ -267,6 +284,7 @@ struct Engine {
   }
 
   pw_status apply_h(const cplx<T>* X, cplx<T>* HX, int nb, int ld) {
+    h->yp_src = nullptr;
     for (int c0 = 0; c0 < nb; c0 += P.nbb) {
       const int w = std::min(P.nbb, nb - c0);
       pw_status s = hop(X + (long)c0 * ld, ld, w, HX + (long)c0 * ld, ld, HX + (long)c0 * ld, ld, 1.0, 0.0, 0.0,
@@ -284,7 +302,7 @@ struct Engine {
     if (m < 1) return PW_OK;
     const double e = 0.5 * (prm.b - prm.a), c = 0.5 * (prm.b + prm.a);
     const double s1 = e / (prm.a_lo - c), tau = 2.0 / s1;
-    pw_status s = hop(Y0, ld0, w, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0);
+    pw_status s = hop(Y0, ld0, w, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0, true);
     if (s != PW_OK) return s;
     const cplx<T>* prev = Y0;
     long ldprev = ld0;
@@ -293,7 +311,7 @@ struct Engine {
     for (int k = 1; k < m; ++k) {
       const double sn = 1.0 / (tau - sg);
       cplx<T>* dst = (prev == Y0) ? u0() : const_cast<cplx<T>*>(prev);
-      s = hop(cur, ldw, w, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev);
+      s = hop(cur, ldw, w, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev, true);
       if (s != PW_OK) return s;
       prev = cur;
       ldprev = ldw;
@@ -301,6 +319,7 @@ struct Engine {
       sg = sn;
     }
     PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(cur, ldw, Y0, ld0, P.npw, w, h->stream));
+    if (h->yp_src == static_cast<const void*>(cur)) h->yp_src = Y0;  // same values
     return PW_OK;
   }
 
@@ -363,6 +382,7 @@ struct Engine {
 
   pw_status eig_step(cplx<T>* X, cplx<T>* HX, int nb, int ld, const pw_step_params& prm, double* eig_host,
                      double* resid_host, double* bounds_out) {
+    h->yp_src = nullptr;
     if (P.nbb < P.nbands) return eig_step_blocked(X, HX, nb, ld, prm, eig_host, resid_host, bounds_out);
     const int m = prm.degree;
     double bmax = prm.b;
@@ -374,7 +394,7 @@ struct Engine {
     if (m >= 1) {
       const double e = 0.5 * (prm.b - prm.a), c = 0.5 * (prm.b + prm.a);
       const double s1 = e / (prm.a_lo - c), tau = 2.0 / s1;
-      s = hop(X, ld, nb, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0);
+      s = hop(X, ld, nb, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0, true);
       if (s != PW_OK) return s;
       const cplx<T>* prev = X;
       long ldprev = ld;
@@ -383,7 +403,7 @@ struct Engine {
       for (int k = 1; k < m; ++k) {
         const double sn = 1.0 / (tau - sg);
         cplx<T>* dst = (prev == X) ? u0() : const_cast<cplx<T>*>(prev);
-        s = hop(cur, ldw, nb, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev);
+        s = hop(cur, ldw, nb, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev, true);
         if (s != PW_OK) return s;
         prev = cur;
         ldprev = ldw;

@@ -78,6 +78,11 @@ struct EpiH {
   long ldz;
   const void* Yp;  // may be null when beta == 0
   long ldp;
+  // split-precision nn only, optional: bf16 hi/lo planes of out (one (re, im) word per entry,
+  // leading dimension ldpl), for the next projector product
+  void* ph;
+  void* pl;
+  long ldpl;
 };
 
 // Generator of the projector matrix inside the GEMM loaders, for cells whose table would not
@@ -115,10 +120,15 @@ hipError_t launch_gemm_cn_bf16x3(const float2* A, long lda, const float2* B, lon
                                  int ncol1, int M, int N, int K, int nsplit, double2* part, int nterm, hipStream_t s);
 hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, long ldb, int M, int N, int K,
                                  float2* out, long ldo, const EpiH& e, hipStream_t s);
-// The same products with A given as pre-split bf16 planes (launch_beta_planes layout): cn with
-// A = M columns of length K, nn with A = K columns of length M.  lda counts 32-bit words.
-hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda, const float2* B,
-                                        long ldb, int M, int N, int K, int nsplit, double2* part, hipStream_t s);
+// The same products with pre-split bf16 planes (launch_beta_planes layout): cn with A and B given
+// as planes of M and N columns of length K, nn with A = planes of K columns of length M.  Leading
+// dimensions of planes count 32-bit words.
+hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
+                                        const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
+                                        int nsplit, double2* part, hipStream_t s);
+// hi/lo planes (one (re, im) word per entry, leading dimension ldp) of rows x cols fp32 complex.
+hipError_t launch_split_planes(const float2* X, long ldx, int rows, int cols, unsigned int* H, unsigned int* L,
+                               long ldp, hipStream_t s);
 hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda, const float2* B,
                                         long ldb, int M, int N, int K, float2* out, long ldo, const EpiH& e,
                                         hipStream_t s);

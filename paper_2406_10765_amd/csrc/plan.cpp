@@ -269,6 +269,8 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   L.sb = take(per_band_sb * P.fft_batch);
   L.g1 = take(per_band_g1 * P.fft_batch);
   L.pt = take(cb * std::max(1, P.nproj) * P.nbb);
+  // bf16 hi/lo planes of the block entering the projector product (split-precision projectors)
+  L.yp = take((P.flags & PW_FLAG_BF16_KB) ? 8 * (size_t)P.ldw * P.nbb : 0);
   const size_t parts = std::max((size_t)P.nsplit_proj * P.nproj * P.nbb, (size_t)P.nsplit_gram * nb * 2 * nb);
   L.parts = take(16 * parts);
   L.sh = take(16 * nb * 2 * nb);
