@@ -378,6 +378,7 @@ int fft_pick_threads(const FftPlan& p, int nlines, int min_thr) {
 template <typename T>
 hipError_t launch_sticks_inv(const cplx<T>* X, long ldx, cplx<T>* SB, int nbatch, const Stick* st,
                              const GridDesc& g, const cplx<T>* tw3, const FftLaunch& L, hipStream_t s) {
+  if (L.sized_sticks) return launch_sticks_inv_n<T>(X, ldx, SB, nbatch, st, g, tw3, s);
   const size_t lds = (size_t)L.spw * g.n3 * sizeof(cplx<T>) + g.n3 * sizeof(cplx<T>) + 2 * L.spw * sizeof(int);
   dim3 grid(ceil_div(g.nst, L.spw), nbatch);
   hipLaunchKernelGGL(k_sticks_inv<T>, grid, dim3(L.stick_thr), lds, s, X, ldx, SB, st, g, tw3, L.spw);
@@ -387,6 +388,7 @@ hipError_t launch_sticks_inv(const cplx<T>* X, long ldx, cplx<T>* SB, int nbatch
 template <typename T>
 hipError_t launch_sticks_fwd(const cplx<T>* SB, cplx<T>* Z, long ldz, int nbatch, const Stick* st,
                              const GridDesc& g, const cplx<T>* tw3, const FftLaunch& L, hipStream_t s) {
+  if (L.sized_sticks) return launch_sticks_fwd_n<T>(SB, Z, ldz, nbatch, st, g, tw3, s);
   const size_t lds = (size_t)L.spw * g.n3 * sizeof(cplx<T>) + g.n3 * sizeof(cplx<T>) + 2 * L.spw * sizeof(int);
   dim3 grid(ceil_div(g.nst, L.spw), nbatch);
   hipLaunchKernelGGL(k_sticks_fwd<T>, grid, dim3(L.stick_thr), lds, s, SB, Z, ldz, st, g, tw3, L.spw);
@@ -453,6 +455,7 @@ bool fft_plan_launch(const GridDesc& g, int real_bytes, size_t max_lds, FftLaunc
     }
   }
   L->sized = L->fused && plane_n_supported(g.n1, g.n2, real_bytes, max_lds) && std::getenv("PW_GENERIC_PLANE") == nullptr;
+  L->sized_sticks = sticks_n_supported(g.n3) && std::getenv("PW_GENERIC_STICKS") == nullptr;
   L->cx = 16;
   while (L->cx > 1 && L->cx * g.n2 > 4096) L->cx /= 2;
   L->cy = 16;

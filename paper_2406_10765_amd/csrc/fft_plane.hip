@@ -161,9 +161,10 @@ __device__ __forceinline__ void line_fft(cplx<T>* buf, int base, int es, int t, 
 }
 
 // Row pass: inverse FFT, * V, forward FFT, in place on a row held in LDS (element stride 1).
+// vr[j][k2] = V at x = k1 + A k2 with k1 = t + gcd(A, B) j (loaded by the caller ahead of time).
 template <typename T, int A, int B>
 __device__ __forceinline__ void row_ivf(cplx<T>* buf, int base, int t, bool active, const cplx<T>* twN,
-                                        const T* __restrict__ vrow) {
+                                        const T (&vr)[A / cgcd(A, B)][B]) {
   constexpr int N = A * B, TT = cgcd(A, B), I1 = B / TT, J2 = A / TT;
   // inverse stage 1
   cplx<T> r1[I1][A];
@@ -200,7 +201,7 @@ __device__ __forceinline__ void row_ivf(cplx<T>* buf, int base, int t, bool acti
       for (int n2 = 0; n2 < B; ++n2) r2[j][n2] = buf[base + k1 * B + n2];
       SmallDft<T, B, +1>::run(r2[j]);
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) r2[j][k2] = cscale<T>(r2[j][k2], vrow[k1 + A * k2]);
+      for (int k2 = 0; k2 < B; ++k2) r2[j][k2] = cscale<T>(r2[j][k2], vr[j][k2]);
       SmallDft<T, B, -1>::run(r2[j]);  // over m2 = k2, output q2
 #pragma unroll
       for (int q2 = 1; q2 < B; ++q2) r2[j][q2] = cmul<T>(r2[j][q2], twN[(k1 * q2) % N]);
@@ -247,12 +248,24 @@ template <typename T, int A, int B, int NT>
 __global__ __launch_bounds__(NT) void k_plane_n(cplx<T>* __restrict__ SB, const T* __restrict__ V,
                                                 const Stick* __restrict__ st, GridDesc g,
                                                 const cplx<T>* __restrict__ twg, T scale) {
-  constexpr int N = A * B, TT = cgcd(A, B), R = N + 1;
+  constexpr int N = A * B, TT = cgcd(A, B), R = N + 1, J2 = A / TT;
+  static_assert(NT / TT >= N, "one row per thread group");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* plane = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* tw = plane + N * R;
   const int tid = threadIdx.x;
   const int z = blockIdx.x, b = blockIdx.y;
+  // V(r) of this thread's row, fetched first so that its latency hides behind the y pass
+  const int yrow = tid % (NT / TT), trow = min(tid / (NT / TT), TT);
+  const bool row_act = yrow < N && trow < TT;
+  T vr[J2][B];
+  {
+    const T* vz = V + ((long)z * N + (row_act ? yrow : 0)) * N;
+#pragma unroll
+    for (int j = 0; j < J2; ++j)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) vr[j][k2] = row_act ? vz[(trow + TT * j) + A * k2] : (T)0;
+  }
   for (int i = tid; i < N * R; i += NT) plane[i] = mk<T>(0, 0);
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
@@ -272,15 +285,8 @@ __global__ __launch_bounds__(NT) void k_plane_n(cplx<T>* __restrict__ SB, const 
       line_fft<T, A, B, +1>(plane, x, R, t, act, tw);
     }
   }
-  // along x: inverse, * V, forward (lines = y rows)
-  {
-    const T* vz = V + (long)z * N * N;
-    for (int l0 = 0; l0 < N; l0 += NT / TT) {
-      const int y = l0 + tid % (NT / TT), t = min(tid / (NT / TT), TT);
-      const bool act = y < N && t < TT;
-      row_ivf<T, A, B>(plane, (act ? y : 0) * R, t, act, tw, vz + (long)(act ? y : 0) * N);
-    }
-  }
+  // along x: inverse, * V, forward (lines = y rows, one per thread group)
+  row_ivf<T, A, B>(plane, (row_act ? yrow : 0) * R, trow, row_act, tw, vr);
   // forward along y on the active columns
   {
     const int L = g.n1a;
@@ -296,6 +302,201 @@ __global__ __launch_bounds__(NT) void k_plane_n(cplx<T>* __restrict__ SB, const 
     sb[s] = cscale<T>(plane[wrapn(t.n2, N) * R + wrapn(t.n1, N)], scale);
   }
 }
+
+// ---- z transforms of the sticks with compile-time N = A B ---------------------------------
+// gcd(A, B) threads share a stick; a block takes SPW sticks of one band (at most 256 threads and
+// 48 KB of LDS).  Stick element i (0 <= i < len, h = (len - 1) / 2) sits at z = i - h mod N.
+template <typename T, int A, int B>
+struct StickShape {
+  static constexpr int N = A * B, TT = cgcd(A, B);
+  static constexpr int SPW0 = 256 / TT, SPWL = (48 * 1024) / (N * (int)sizeof(cplx<T>));
+  static constexpr int SPW = SPW0 < SPWL ? SPW0 : SPWL;
+  static constexpr int NT = SPW * TT;
+};
+
+__device__ __forceinline__ int stick_index(int z, int h, int N) {
+  return z <= h ? z + h : (z >= N - h ? z - N + h : -1);
+}
+
+// sphere -> sticks, inverse FFT along z.  Grid (ceil(nst / SPW), nbatch).  SB layout [band][z][stick].
+template <typename T, int A, int B>
+__global__ __launch_bounds__(256) void k_sticks_inv_n(const cplx<T>* __restrict__ X, long ldx,
+                                                      cplx<T>* __restrict__ SB, const Stick* __restrict__ st,
+                                                      GridDesc g, const cplx<T>* __restrict__ twg) {
+  using SS = StickShape<T, A, B>;
+  constexpr int N = A * B, TT = SS::TT, SPW = SS::SPW, NT = SS::NT, I1 = B / TT, J2 = A / TT;
+  __shared__ cplx<T> buf[N * SPW];  // [position][stick]
+  __shared__ cplx<T> tw[N];
+  const int tid = threadIdx.x, b = blockIdx.y;
+  const int s = tid / TT, t = tid % TT;  // stick within the block, thread within the stick
+  const int s0 = blockIdx.x * SPW;
+  const bool act = s0 + s < g.nst;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  Stick sk{0, 0, 0, 0};
+  if (act) sk = st[s0 + s];
+  const int h = (sk.len - 1) >> 1;
+  const cplx<T>* xs = X + (long)b * ldx + sk.off;
+  // stage 1 input straight from the sphere: x[B n1 + n2], n2 = t + TT i
+  cplx<T> r1[I1][A];
+#pragma unroll
+  for (int i = 0; i < I1; ++i)
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) {
+      const int e = act ? stick_index(B * n1 + t + TT * i, h, N) : -1;
+      r1[i][n1] = e >= 0 ? xs[e] : mk<T>(0, 0);
+    }
+  __syncthreads();  // twiddles
+#pragma unroll
+  for (int i = 0; i < I1; ++i) {
+    const int n2 = t + TT * i;
+    SmallDft<T, A, +1>::run(r1[i]);
+#pragma unroll
+    for (int k1 = 1; k1 < A; ++k1) {
+      cplx<T> w = tw[(n2 * k1) % N];
+      w.y = -w.y;
+      r1[i][k1] = cmul<T>(r1[i][k1], w);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) buf[(k1 * B + n2) * SPW + s] = r1[i][k1];
+  }
+  __syncthreads();
+  cplx<T> r2[J2][B];
+#pragma unroll
+  for (int j = 0; j < J2; ++j) {
+    const int k1 = t + TT * j;
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) r2[j][n2] = buf[(k1 * B + n2) * SPW + s];
+    SmallDft<T, B, +1>::run(r2[j]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J2; ++j) {
+    const int k1 = t + TT * j;
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) buf[(k1 + A * k2) * SPW + s] = r2[j][k2];
+  }
+  __syncthreads();
+  // rows of SPW consecutive sticks per z
+  const int ns = min(SPW, g.nst - s0);
+  cplx<T>* sb = SB + (long)b * N * g.nst + s0;
+  for (int i = tid; i < N * SPW; i += NT) {
+    const int z = i / SPW, l = i - z * SPW;
+    if (l < ns) sb[(long)z * g.nst + l] = buf[i];
+  }
+}
+
+// sticks -> sphere, forward FFT along z.
+template <typename T, int A, int B>
+__global__ __launch_bounds__(256) void k_sticks_fwd_n(const cplx<T>* __restrict__ SB, cplx<T>* __restrict__ Z,
+                                                      long ldz, const Stick* __restrict__ st, GridDesc g,
+                                                      const cplx<T>* __restrict__ twg) {
+  using SS = StickShape<T, A, B>;
+  constexpr int N = A * B, TT = SS::TT, SPW = SS::SPW, NT = SS::NT, I1 = B / TT, J2 = A / TT;
+  __shared__ cplx<T> buf[N * SPW];
+  __shared__ cplx<T> tw[N];
+  const int tid = threadIdx.x, b = blockIdx.y;
+  const int s = tid / TT, t = tid % TT;
+  const int s0 = blockIdx.x * SPW;
+  const int ns = min(SPW, g.nst - s0);
+  const bool act = s < ns;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  const cplx<T>* sb = SB + (long)b * N * g.nst + s0;
+  for (int i = tid; i < N * SPW; i += NT) {
+    const int z = i / SPW, l = i - z * SPW;
+    buf[i] = l < ns ? sb[(long)z * g.nst + l] : mk<T>(0, 0);
+  }
+  Stick sk{0, 0, 0, 0};
+  if (act) sk = st[s0 + s];
+  __syncthreads();
+  cplx<T> r1[I1][A];
+#pragma unroll
+  for (int i = 0; i < I1; ++i)
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) r1[i][n1] = buf[(B * n1 + t + TT * i) * SPW + s];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < I1; ++i) {
+    const int n2 = t + TT * i;
+    SmallDft<T, A, -1>::run(r1[i]);
+#pragma unroll
+    for (int k1 = 1; k1 < A; ++k1) r1[i][k1] = cmul<T>(r1[i][k1], tw[(n2 * k1) % N]);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) buf[(k1 * B + n2) * SPW + s] = r1[i][k1];
+  }
+  __syncthreads();
+  if (!act) return;
+  const int h = (sk.len - 1) >> 1;
+  cplx<T>* zs = Z + (long)b * ldz + sk.off;
+#pragma unroll
+  for (int j = 0; j < J2; ++j) {
+    const int k1 = t + TT * j;
+    cplx<T> r2[B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) r2[n2] = buf[(k1 * B + n2) * SPW + s];
+    SmallDft<T, B, -1>::run(r2);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) {
+      const int e = stick_index(k1 + A * k2, h, N);
+      if (e >= 0) zs[e] = r2[k2];
+    }
+  }
+}
+
+#define PW_STICK_SIZES(X) \
+  X(24, 4, 6) X(27, 3, 9) X(32, 4, 8) X(48, 4, 12) X(54, 6, 9) X(64, 8, 8) X(81, 9, 9) X(96, 8, 12) X(128, 8, 16) \
+  X(192, 12, 16)
+
+bool sticks_n_supported(int n3) {
+  switch (n3) {
+#define PW_CASE(NN, AA, BB) case NN:
+    PW_STICK_SIZES(PW_CASE)
+#undef PW_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T>
+hipError_t launch_sticks_inv_n(const cplx<T>* X, long ldx, cplx<T>* SB, int nbatch, const Stick* st,
+                               const GridDesc& g, const cplx<T>* tw3, hipStream_t s) {
+  switch (g.n3) {
+#define PW_CASE(NN, AA, BB)                                                                                   \
+  case NN:                                                                                                    \
+    hipLaunchKernelGGL((k_sticks_inv_n<T, AA, BB>), dim3(ceil_div(g.nst, StickShape<T, AA, BB>::SPW), nbatch),  \
+                       dim3(StickShape<T, AA, BB>::NT), 0, s, X, ldx, SB, st, g, tw3);                         \
+    return hipGetLastError();
+    PW_STICK_SIZES(PW_CASE)
+#undef PW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_sticks_fwd_n(const cplx<T>* SB, cplx<T>* Z, long ldz, int nbatch, const Stick* st,
+                               const GridDesc& g, const cplx<T>* tw3, hipStream_t s) {
+  switch (g.n3) {
+#define PW_CASE(NN, AA, BB)                                                                                   \
+  case NN:                                                                                                    \
+    hipLaunchKernelGGL((k_sticks_fwd_n<T, AA, BB>), dim3(ceil_div(g.nst, StickShape<T, AA, BB>::SPW), nbatch),  \
+                       dim3(StickShape<T, AA, BB>::NT), 0, s, SB, Z, ldz, st, g, tw3);                         \
+    return hipGetLastError();
+    PW_STICK_SIZES(PW_CASE)
+#undef PW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_sticks_inv_n<float>(const cplx<float>*, long, cplx<float>*, int, const Stick*,
+                                               const GridDesc&, const cplx<float>*, hipStream_t);
+template hipError_t launch_sticks_inv_n<double>(const cplx<double>*, long, cplx<double>*, int, const Stick*,
+                                                const GridDesc&, const cplx<double>*, hipStream_t);
+template hipError_t launch_sticks_fwd_n<float>(const cplx<float>*, cplx<float>*, long, int, const Stick*,
+                                               const GridDesc&, const cplx<float>*, hipStream_t);
+template hipError_t launch_sticks_fwd_n<double>(const cplx<double>*, cplx<double>*, long, int, const Stick*,
+                                                const GridDesc&, const cplx<double>*, hipStream_t);
 
 // Sizes with a compile-time plane kernel: N = A B and threads per block.
 template <typename T>

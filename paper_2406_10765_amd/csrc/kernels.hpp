@@ -11,6 +11,7 @@ struct FftLaunch {
   int stick_thr;  // threads per workgroup in the z pass
   bool fused;     // whole plane in LDS
   bool sized;     // fused plane with a compile-time size kernel (register FFT stages)
+  bool sized_sticks;  // z transforms with a compile-time size kernel
   int plane_thr;
   int cx, cy;     // columns / rows per workgroup in the pencil form
   int col_thr, row_thr;
@@ -31,6 +32,13 @@ hipError_t launch_plane_fused(cplx<T>* SB, const T* V, int nbatch, const Stick* 
                               const cplx<T>* tw1, const cplx<T>* tw2, T scale, int mode, T* vout, const FftLaunch& L,
                               hipStream_t s);
 // Compile-time-size fused plane (square planes of supported sizes); mode 0 only.
+bool sticks_n_supported(int n3);
+template <typename T>
+hipError_t launch_sticks_inv_n(const cplx<T>* X, long ldx, cplx<T>* SB, int nbatch, const Stick* st,
+                               const GridDesc& g, const cplx<T>* tw3, hipStream_t s);
+template <typename T>
+hipError_t launch_sticks_fwd_n(const cplx<T>* SB, cplx<T>* Z, long ldz, int nbatch, const Stick* st,
+                               const GridDesc& g, const cplx<T>* tw3, hipStream_t s);
 bool plane_n_supported(int n1, int n2, int real_bytes, size_t max_lds);
 template <typename T>
 hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const GridDesc& g,
