@@ -70,6 +70,26 @@ def phase_work(name: str, info, nb: int, m: int, steps: int, real_bytes: int, n1
 EXECUTED_PER_ALGORITHMIC = {"gram": 16.0 / 12.0}
 
 
+def measured_traffic(workload, flags, phase):
+    """HBM bytes per launch of a phase from the committed counter summary (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, scaled by the copy-kernel calibration), or None when the summary does not cover this
+    workload or the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_mixed_hbm_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    src = os.path.join(ROOT, d["source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != d["source_sha256"]:
+            return None
+    if d.get("mixed_flags") != flags or phase not in d["kernels"]:
+        return None
+    k = d["kernels"][phase]
+    return 1024.0 * (k["FETCH_SIZE_KiB"] * d["scale"]["FETCH_SIZE"] + k["WRITE_SIZE_KiB"] * d["scale"]["WRITE_SIZE"])
+
+
 def phase_table(stats, info, nb, m, steps, real_bytes, n1a, nterm, fp64=False):
     """Per-phase rates over the timed steps and the roofline entry of the longest phase."""
     mfma_peak = PEAK_MFMA_TFLOPS["fp64" if fp64 else "fp32"]
@@ -257,6 +277,8 @@ def main():
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--filter-only", action="store_true",
+                    help="set up the workload, run one degree-m filter step and exit (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -282,6 +304,16 @@ def main():
         del src, dst
     cell = synth.make_cell(args.workload)
     nb, m = cell.nbands, args.degree
+    if args.filter_only:
+        mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
+        hm = pw.Handle(cell, pw.PW_MIXED, flags=mflags)
+        b = hm.spectrum_bound(20, 1)
+        X = hm.random_block(nb, synth.SEED_X0 + synth.WORKLOADS[args.workload]["index"])
+        eig, res, bnd = hm.eig_step(X, 0, b=b)
+        eig, res, bnd = hm.eig_step(X, m, bnd[0], bnd[1], b)
+        torch.cuda.synchronize()
+        log(f"filter step done: lowest eigenvalue {eig[0]:.6f}")
+        return
 
     # ---- mixed precision (the headline) --------------------------------------------------
     t0 = time.time()
@@ -331,6 +363,10 @@ def main():
     if mflags & 8:
         nterm["rotate"] = 3
     phases, dom, roofline = phase_table(stats, hm.info, nb, m, args.steps, 4, n1a, nterm)
+    if roofline is not None:
+        roofline["traffic"] = measured_traffic(args.workload, mflags, dom)
+        if roofline["traffic"] is not None:
+            roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     # ---- FP64 form from the same block and bounds -----------------------------------------
     fp64 = None

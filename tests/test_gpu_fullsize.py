@@ -81,3 +81,25 @@ def test_si512_mixed_step_properties(si512, flags):
     say("  resid lib", r1[cols], "oracle", rr)
     assert np.abs(rr - r1[cols]).max() <= 1e-4 * max(1.0, rr.max())
     h.close()
+
+
+def test_random_block_beyond_32bit_dispatch():
+    """Element-wise kernels over more than 2^32 entries (the Si4096 plane-wave count times 5200
+    bands): every column of the seeded block must come out normalised.  One work-item per entry
+    would exceed the 32-bit dispatch size and leave columns unwritten."""
+    import torch
+    cell = synth.make_cell("si4096", nbands=5200)
+    h = pw.Handle(cell, pw.PW_MIXED, flags=pw.PW_FLAG_BETA_OTF)
+    assert h.npw * cell.nbands > 2 ** 32
+    say("random block", h.npw, "x", cell.nbands)
+    X = h.random_block(cell.nbands, 123)
+    norms = []
+    for c0 in range(0, cell.nbands, 256):
+        blk = X[c0:c0 + 256, : h.npw]
+        norms.append(torch.linalg.vector_norm(blk, dim=1).double().cpu())
+    n = torch.cat(norms).numpy()
+    say("  column norms min/max", n.min(), n.max())
+    assert np.all(np.abs(n - 1.0) < 1e-5)
+    del X
+    h.close()
+    torch.cuda.empty_cache()
