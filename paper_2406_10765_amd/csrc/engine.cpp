@@ -78,16 +78,18 @@ struct pw_handle_s {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
   }
-  void tbegin() {
+  void tbegin() { tbegin(stream); }
+  void tend(int ph) { tend(ph, stream); }
+  void tbegin(hipStream_t s) {
     if (!timing) return;
     open_ev = take_event();
-    if (open_ev) hipEventRecord(open_ev, stream);
+    if (open_ev) hipEventRecord(open_ev, s);
   }
-  void tend(int ph) {
+  void tend(int ph, hipStream_t s) {
     if (!timing || !open_ev) return;
     hipEvent_t b = take_event();
     if (!b) return;
-    hipEventRecord(b, stream);
+    hipEventRecord(b, s);
     pending.push_back({ph, open_ev, b});
     open_ev = nullptr;
   }
@@ -104,7 +106,18 @@ struct pw_handle_s {
     }
     pending.clear();
   }
+  // Second stream of the handle (default priority): the FFT part of each H application runs on
+  // it, forked from and joined back into the caller's stream, concurrently with the projection.
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
   ~pw_handle_s() {
+    if (aux) {
+      hipStreamSynchronize(aux);
+      hipStreamDestroy(aux);
+    }
+    if (ev_fork) hipEventDestroy(ev_fork);
+    if (ev_join) hipEventDestroy(ev_join);
     for (const Rec& r : pending) {
       hipEventDestroy(r.a);
       hipEventDestroy(r.b);
@@ -130,6 +143,12 @@ namespace {
     h->tbegin();           \
     PW_HIP(call);          \
     h->tend(ph);           \
+  } while (0)
+#define PW_TIMED_ON(ph, st, call) \
+  do {                            \
+    h->tbegin(st);                \
+    PW_HIP(call);                 \
+    h->tend(ph, st);              \
   } while (0)
 
 pw_status fail(pw_handle_s* h, pw_status s, const std::string& m) {
@@ -191,7 +210,7 @@ struct Engine {
   }
 
   // Local potential part: Z = P_sphere FFT_fwd[V FFT_inv[P_sphere^T Y]] for nb columns.
-  pw_status local_part(const cplx<T>* Y, long ldy, cplx<T>* Z, long ldz, int nb) {
+  pw_status local_part(const cplx<T>* Y, long ldy, cplx<T>* Z, long ldz, int nb, hipStream_t sm) {
     const GridDesc& g = P.g;
     const T scale = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
     cplx<T>* SB = h->at<cplx<T>>(P.lay.sb);
@@ -202,20 +221,22 @@ struct Engine {
     const cplx<T>* tw1 = h->at<cplx<T>>(P.lay.tw1);
     const cplx<T>* tw2 = h->at<cplx<T>>(P.lay.tw2);
     const cplx<T>* tw3 = h->at<cplx<T>>(P.lay.tw3);
-    hipStream_t sm = h->stream;
     for (int b0 = 0; b0 < nb; b0 += P.fft_batch) {
       const int nbt = std::min(P.fft_batch, nb - b0);
-      PW_TIMED(PW_PH_STICKS_INV, launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, sm));
+      PW_TIMED_ON(PW_PH_STICKS_INV, sm,
+                  launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, sm));
       if (P.fl.sized) {
-        PW_TIMED(PW_PH_PLANE, launch_plane_n<T>(SB, V, nbt, st, g, tw1, scale, sm));
+        PW_TIMED_ON(PW_PH_PLANE, sm, launch_plane_n<T>(SB, V, nbt, st, g, tw1, scale, sm));
       } else if (P.fl.fused) {
-        PW_TIMED(PW_PH_PLANE, launch_plane_fused<T>(SB, V, nbt, st, g, tw1, tw2, scale, 0, (T*)nullptr, P.fl, sm));
+        PW_TIMED_ON(PW_PH_PLANE, sm,
+                    launch_plane_fused<T>(SB, V, nbt, st, g, tw1, tw2, scale, 0, (T*)nullptr, P.fl, sm));
       } else {
-        PW_TIMED(PW_PH_PENCIL_YINV, launch_pencil_yinv<T>(SB, G1, nbt, st, cs, g, tw2, P.fl, sm));
-        PW_TIMED(PW_PH_PENCIL_X, launch_pencil_x<T>(G1, V, nbt, g, tw1, 0, (T*)nullptr, P.fl, sm));
-        PW_TIMED(PW_PH_PENCIL_YFWD, launch_pencil_yfwd<T>(SB, G1, nbt, st, cs, g, tw2, scale, P.fl, sm));
+        PW_TIMED_ON(PW_PH_PENCIL_YINV, sm, launch_pencil_yinv<T>(SB, G1, nbt, st, cs, g, tw2, P.fl, sm));
+        PW_TIMED_ON(PW_PH_PENCIL_X, sm, launch_pencil_x<T>(G1, V, nbt, g, tw1, 0, (T*)nullptr, P.fl, sm));
+        PW_TIMED_ON(PW_PH_PENCIL_YFWD, sm, launch_pencil_yfwd<T>(SB, G1, nbt, st, cs, g, tw2, scale, P.fl, sm));
       }
-      PW_TIMED(PW_PH_STICKS_FWD, launch_sticks_fwd<T>(SB, Z + (long)b0 * ldz, ldz, nbt, st, g, tw3, P.fl, sm));
+      PW_TIMED_ON(PW_PH_STICKS_FWD, sm,
+                  launch_sticks_fwd<T>(SB, Z + (long)b0 * ldz, ldz, nbt, st, g, tw3, P.fl, sm));
     }
     return PW_OK;
   }
@@ -226,8 +247,18 @@ struct Engine {
   // hop on out.
   pw_status hop(const cplx<T>* Y, long ldy, int nb, cplx<T>* out, long ldo, cplx<T>* Zl, long ldz, double alpha,
                 double c, double beta_c, const cplx<T>* Yp, long ldp, bool planes_out = false) {
-    pw_status s = local_part(Y, ldy, Zl, ldz, nb);
+    // the local part (FFTs, memory bound) on the second stream, the projection (matrix cores)
+    // on the caller's stream; both only read Y, and the nonlocal GEMM waits for both.  With
+    // phase timing on, everything stays on the caller's stream so that phase times are not
+    // inflated by sharing the device.
+    const bool overlap = !h->timing;
+    if (overlap) {
+      PW_HIP(hipEventRecord(h->ev_fork, h->stream));
+      PW_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+    }
+    pw_status s = local_part(Y, ldy, Zl, ldz, nb, overlap ? h->aux : h->stream);
     if (s != PW_OK) return s;
+    if (overlap) PW_HIP(hipEventRecord(h->ev_join, h->aux));
     cplx<T>* PT = h->at<cplx<T>>(P.lay.pt);
     if (P.nproj > 0) {
       double2* parts = h->at<double2>(P.lay.parts);
@@ -247,6 +278,7 @@ struct Engine {
                                                          h->at<double>(P.lay.dscale), 4, nullptr, 0, PT, P.nproj,
                                                          h->stream));
     }
+    if (overlap) PW_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
     EpiH e;
     e.mode = 1;
     e.alpha = alpha;
@@ -799,6 +831,13 @@ pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes
     return fail(nullptr, PW_EDEVICE, "rocblas_create_handle failed");
   }
   rocblas_set_stream(h->blas, h->stream);
+  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+    rocblas_destroy_handle(h->blas);
+    delete h;
+    return fail(nullptr, PW_EDEVICE, "stream or event creation failed");
+  }
   if (h->plan.fl.fused) {
     // allow large dynamic LDS for the fused plane kernel
     pw_allow_large_lds();
