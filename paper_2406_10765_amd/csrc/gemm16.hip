@@ -89,11 +89,11 @@ __device__ __forceinline__ v8bf frag(const uint4* plane, int row0, int lane) {
 // >= ncol1), split on the fly.  Unit: 2 complex (16 bytes) of one column -> 8 bytes per plane.
 // Lanes: bit 0 half of the chunk, bits 1-4 column within 16, bits 5-6 slot, higher bits column
 // group: a wave writes 512 contiguous bytes per plane.  NEG negates the imaginary parts (nn B).
-template <int NC, bool VEC, bool NEG>
+template <int NC, bool VEC, bool NEG, int NTH = 256>
 struct SplitK {
   static constexpr int UNITS = 8 * NC;
-  static constexpr int PER = UNITS / 256;
-  static_assert(UNITS % 256 == 0, "whole units per thread");
+  static constexpr int PER = UNITS / NTH;
+  static_assert(UNITS % NTH == 0, "whole units per thread");
   float v[PER][4];
   __device__ __forceinline__ static void unit(int idx, int& c, int& half, int& slot) {
     half = idx & 1;
@@ -106,7 +106,7 @@ struct SplitK {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       int c, half, slot;
-      unit(tid + q * 256, c, half, slot);
+      unit(tid + q * NTH, c, half, slot);
       const int gc = c0 + c, gk = k0 + 4 * slot + 2 * half;
       const float2* col = gc < ncol1 ? P + (long)gc * ld : P2 + (long)(gc - ncol1) * ld2;
       if (full) {
@@ -144,7 +144,7 @@ struct SplitK {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       int c, half, slot;
-      unit(tid + q * 256, c, half, slot);
+      unit(tid + q * NTH, c, half, slot);
       const Split2 r0 = split(v[q][0]), i0 = split(NEG ? -v[q][1] : v[q][1]);
       const Split2 r1 = split(v[q][2]), i1 = split(NEG ? -v[q][3] : v[q][3]);
       const int o = chunk_of(c, slot);
@@ -232,18 +232,18 @@ struct SplitM {
 // K-contiguous pre-split planes (cn A = projector planes): unit = 4 complex k (one chunk) of one
 // column per plane.  Lanes: bits 0-3 column within 16, bits 4-5 slot: a wave writes one
 // contiguous kilobyte per plane.
-template <int NC, bool VEC>
+template <int NC, bool VEC, int NTH = 256>
 struct PlanesK {
   static constexpr int UNITS = 4 * NC;
-  static constexpr int PER = UNITS / 256;
-  static_assert(UNITS % 256 == 0, "whole units per thread");
+  static constexpr int PER = UNITS / NTH;
+  static_assert(UNITS % NTH == 0, "whole units per thread");
   uint4 h[PER], l[PER];
   __device__ __forceinline__ void load(const unsigned int* __restrict__ Hp, const unsigned int* __restrict__ Lp,
                                        long lda, int ncols, int c0, int k0, int kend, int tid) {
     const bool full = VEC && c0 + NC <= ncols && k0 + hBK <= kend;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int idx = tid + q * 256;
+      const int idx = tid + q * NTH;
       const int c = ((idx >> 6) << 4) + (idx & 15), slot = (idx >> 4) & 3;
       const int gc = c0 + c, gk = k0 + 4 * slot;
       const long o = (long)gc * lda + gk;
@@ -274,7 +274,7 @@ struct PlanesK {
   __device__ __forceinline__ void store(uint4* H, uint4* L, int tid) const {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int idx = tid + q * 256;
+      const int idx = tid + q * NTH;
       const int c = ((idx >> 6) << 4) + (idx & 15), slot = (idx >> 4) & 3;
       const int o = chunk_of(c, slot);
       H[o] = h[q];
@@ -285,16 +285,16 @@ struct PlanesK {
 
 // M-contiguous pre-split planes (nn A = projector planes): unit = 4 rows x 4 k of one plane,
 // loaded as four 16-byte row quads (one per k) and transposed in registers into four chunks (one
-// per row).  Threads 0-127 take the hi plane, 128-255 the lo plane.  Lanes: bits 0-1 k quad,
+// per row).  The first NR threads take the hi plane, the others the lo plane.  Lanes: bits 0-1 k quad,
 // bits 2-5 row quad; with the chunk swizzle each write instruction covers 16 distinct chunks.
-template <int NR, bool VEC>
+template <int NR, bool VEC, int NTH = 256>
 struct PlanesM {
-  static_assert(NR == 128 && hBK == 16, "one unit per thread");
+  static_assert(NTH == 2 * NR && hBK == 16, "one unit per thread");
   uint4 t[4];
   __device__ __forceinline__ void load(const unsigned int* __restrict__ Hp, const unsigned int* __restrict__ Lp,
                                        long lda, int nrows, int r0, int k0, int kend, int tid) {
-    const unsigned int* Pp = tid < 128 ? Hp : Lp;
-    const int u = tid & 127;
+    const unsigned int* Pp = tid < NR ? Hp : Lp;
+    const int u = tid % NR;
     const int kq = u & 3, gq = u >> 2;
     const int gm = r0 + 4 * gq;
     const bool full = VEC && r0 + NR <= nrows && k0 + hBK <= kend;
@@ -321,8 +321,8 @@ struct PlanesM {
     }
   }
   __device__ __forceinline__ void store(uint4* H, uint4* L, int tid) const {
-    uint4* D = tid < 128 ? H : L;
-    const int u = tid & 127;
+    uint4* D = tid < NR ? H : L;
+    const int u = tid % NR;
     const int kq = u & 3, gq = u >> 2;
     D[chunk_of(4 * gq + 0, kq)] = uint4{t[0].x, t[1].x, t[2].x, t[3].x};
     D[chunk_of(4 * gq + 1, kq)] = uint4{t[0].y, t[1].y, t[2].y, t[3].y};
@@ -342,9 +342,9 @@ struct CnAF32 {
   }
   __device__ __forceinline__ void store(uint4* H, uint4* L, int tid) const { l.store(H, L, tid); }
 };
-template <int NC, bool VEC>
+template <int NC, bool VEC, int NTH = 256>
 struct CnAPlanes {
-  PlanesK<NC, VEC> l;
+  PlanesK<NC, VEC, NTH> l;
   __device__ __forceinline__ void load(const void* A0, const void* A1, long lda, int ncols, int c0, int k0, int kend,
                                        int tid) {
     l.load(static_cast<const unsigned int*>(A0), static_cast<const unsigned int*>(A1), lda, ncols, c0, k0, kend,
@@ -361,9 +361,9 @@ struct NnAF32 {
   }
   __device__ __forceinline__ void store(uint4* H, uint4* L, int tid) const { l.store(H, L, tid); }
 };
-template <int NR, bool VEC>
+template <int NR, bool VEC, int NTH = 256>
 struct NnAPlanes {
-  PlanesM<NR, VEC> l;
+  PlanesM<NR, VEC, NTH> l;
   __device__ __forceinline__ void load(const void* A0, const void* A1, long lda, int nrows, int r0, int k0, int kend,
                                        int tid) {
     l.load(static_cast<const unsigned int*>(A0), static_cast<const unsigned int*>(A1), lda, nrows, r0, k0, kend,
@@ -384,9 +384,9 @@ struct CnBF32 {
   }
   __device__ __forceinline__ void store(uint4* H, uint4* L, int tid) const { l.store(H, L, tid); }
 };
-template <int NC, bool VEC>
+template <int NC, bool VEC, int NTH = 256>
 struct CnBPlanes {
-  PlanesK<NC, VEC> l;
+  PlanesK<NC, VEC, NTH> l;
   __device__ __forceinline__ void load(const void* B0, const void* B1, long ldb, const void*, long, int, int ncols,
                                        int c0, int k0, int kend, int tid) {
     l.load(static_cast<const unsigned int*>(B0), static_cast<const unsigned int*>(B1), ldb, ncols, c0, k0, kend, tid);
@@ -397,21 +397,23 @@ struct CnBPlanes {
 // ------------------------------------------------------------------------------------------
 // cn: part[s] = A^H B over K chunk s (fp32 accumulation per hFlush tiles, fp64 partials).
 // ------------------------------------------------------------------------------------------
-template <int NTERM, class AL, class BL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_cn_bf16x3(
+// Workgroup of NT threads (NT / 64 waves of 64 x 64), tile TM x TN with TM / 64 waves along M.
+template <int NTERM, class AL, class BL, int TM = hTM, int NT = 256>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_cn_bf16x3(
     const void* __restrict__ A0, const void* __restrict__ A1, long lda, const void* __restrict__ B0,
     const void* __restrict__ B1, long ldb, const void* __restrict__ B2, long ldb2, int ncol1, int M, int N, int K,
     int kchunk, int tiles_m, int tiles_n, double2* __restrict__ part) {
-  constexpr int PL = hTM * 4;  // chunks per plane
-  __shared__ uint4 sAh[2][PL], sAl[2][PL], sBh[2][PL], sBl[2][PL];
+  constexpr int WM = TM / 64, TN = 64 * (NT / 64) / WM;
+  constexpr int PA = TM * 4, PB = TN * 4;  // chunks per plane
+  __shared__ uint4 sAh[2][PA], sAl[2][PA], sBh[2][PB], sBl[2][PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int t = xcd_tile16(blockIdx.x, gridDim.x);
   const int sp = t / (tiles_m * tiles_n);
   const int tr = t - sp * tiles_m * tiles_n;
   const int tm = tr / tiles_n, tn = tr - tm * tiles_n;
-  const int i0 = tm * hTM, j0 = tn * hTN;
+  const int i0 = tm * TM, j0 = tn * TN;
   const int kb = sp * kchunk, ke = min(K, kb + kchunk);
-  const int mo = (wave & 1) * 64, no = (wave >> 1) * 64;
+  const int mo = (wave % WM) * 64, no = (wave / WM) * 64;
   v4f16 cr[4][4], ci[4][4];
   AL la;
   BL lb;
@@ -500,24 +502,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // ------------------------------------------------------------------------------------------
 // nn: out = epilogue(A B) (fp32 data, bf16x3 products).
 // ------------------------------------------------------------------------------------------
-template <class AL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nn_bf16x3(const void* __restrict__ A0, const void* __restrict__ A1,
-                                                        long lda, const float2* __restrict__ B, long ldb, int M, int N,
-                                                        int K, int tiles_n, float2* out, long ldo, EpiH e) {
-  constexpr int PL = hTM * 4;
-  __shared__ uint4 sAh[2][PL], sAl[2][PL], sBh[2][PL], sBl[2][PL];
+template <class AL, int TM = hTM, int NT = 256>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nn_bf16x3(
+    const void* __restrict__ A0, const void* __restrict__ A1, long lda, const float2* __restrict__ B, long ldb, int M,
+    int N, int K, int tiles_n, float2* out, long ldo, EpiH e) {
+  constexpr int WM = TM / 64, TN = 64 * (NT / 64) / WM;
+  constexpr int PA = TM * 4, PB = TN * 4;
+  __shared__ uint4 sAh[2][PA], sAl[2][PA], sBh[2][PB], sBl[2][PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int t = xcd_tile16(blockIdx.x, gridDim.x);
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
-  const int i0 = tm * hTM, j0 = tn * hTN;
-  const int mo = (wave & 1) * 64, no = (wave >> 1) * 64;
+  const int i0 = tm * TM, j0 = tn * TN;
+  const int mo = (wave % WM) * 64, no = (wave / WM) * 64;
   v4f16 cr[4][4], ci[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) cr[a][b] = ci[a][b] = v4f16{0, 0, 0, 0};
   AL la;
-  SplitK<hTN, false, true> lb;  // Br = (br, -bi); B rows are small, scalar loads
+  SplitK<TN, false, true, NT> lb;  // Br = (br, -bi); B rows are small, scalar loads
   const int ntiles = (K + hBK - 1) / hBK;
   if (ntiles > 0) {
     la.load(A0, A1, lda, M, i0, 0, K, tid);
@@ -665,10 +668,37 @@ hipError_t launch_gemm_cn_bf16x3(const float2* A, long lda, const float2* B, lon
   return hipGetLastError();
 }
 
+// The projection with pre-split planes uses a 256-row tile with 8 waves when M is large: the block
+// is then re-read by half as many workgroups.  (The nonlocal product, whose K is short, keeps two
+// 128 x 128 workgroups per CU, which overlap one's epilogue with the other's MFMAs.)
+constexpr int hWM = 256, hWT = 512;
+static bool planes_wide(int M) { return M >= 512; }
+
+int gemm_cn_bf16_planes_tiles(int M, int N) {
+  return planes_wide(M) ? ceil_div(M, hWM) * ceil_div(N, hTN) : gemm_cn_bf16_tiles(M, N);
+}
+
 hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
                                         const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
                                         int nsplit, double2* part, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (planes_wide(M)) {
+    const int kchunk = cn_chunk(K, nsplit);
+    const int tm = ceil_div(M, hWM), tn = ceil_div(N, hTN);
+    dim3 grid(tm * tn * nsplit);
+    const void* a0 = Ahi;
+    const void* a1 = Alo;
+    const void* b0 = Bhi;
+    const void* b1 = Blo;
+    const void* nul = nullptr;
+    if (ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb))
+      hipLaunchKernelGGL((k_gemm_cn_bf16x3<3, CnAPlanes<hWM, true, hWT>, CnBPlanes<hTN, true, hWT>, hWM, hWT>), grid,
+                         dim3(hWT), 0, s, a0, a1, lda, b0, b1, ldb, nul, 0L, N, M, N, K, kchunk, tm, tn, part);
+    else
+      hipLaunchKernelGGL((k_gemm_cn_bf16x3<3, CnAPlanes<hWM, false, hWT>, CnBPlanes<hTN, false, hWT>, hWM, hWT>), grid,
+                         dim3(hWT), 0, s, a0, a1, lda, b0, b1, ldb, nul, 0L, N, M, N, K, kchunk, tm, tn, part);
+    return hipGetLastError();
+  }
   const int kchunk = cn_chunk(K, nsplit);
   const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
   const bool vec = ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb);

@@ -123,6 +123,8 @@ hipError_t launch_gemm_nn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb
 
 // Split-precision (bf16x3) forms of the two GEMM shapes, fp32 data.
 int gemm_cn_bf16_tiles(int M, int N);
+// tiles of the projection product with pre-split planes (launch_gemm_cn_bf16x3_planes)
+int gemm_cn_bf16_planes_tiles(int M, int N);
 // nterm = 3: hi*hi' + hi*lo' + lo*hi'; nterm = 4 adds lo*lo'.
 hipError_t launch_gemm_cn_bf16x3(const float2* A, long lda, const float2* B, long ldb, const float2* B2, long ldb2,
                                  int ncol1, int M, int N, int K, int nsplit, double2* part, int nterm, hipStream_t s);

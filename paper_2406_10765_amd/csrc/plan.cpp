@@ -222,7 +222,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   };
   const bool f64 = P.prec == PW_FP64;
   const bool bkb = (P.flags & PW_FLAG_BF16_KB) != 0, bgr = (P.flags & PW_FLAG_BF16_GRAM) != 0;
-  P.nsplit_proj = P.nproj ? pick_split(bkb ? gemm_cn_bf16_tiles(P.nproj, P.nbb) : gemm_cn_tiles(P.nproj, P.nbb, f64),
+  P.nsplit_proj = P.nproj ? pick_split(bkb ? gemm_cn_bf16_planes_tiles(P.nproj, P.nbb) : gemm_cn_tiles(P.nproj, P.nbb, f64),
                                        P.npw)
                           : 1;
   P.nsplit_gram = pick_split(bgr ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands) : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
