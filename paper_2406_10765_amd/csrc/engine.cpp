@@ -251,7 +251,8 @@ struct Engine {
     // on the caller's stream; both only read Y, and the nonlocal GEMM waits for both.  With
     // phase timing on, everything stays on the caller's stream so that phase times are not
     // inflated by sharing the device.
-    const bool overlap = !h->timing;
+    // Small blocks (serving-size cells) gain nothing from it and would only add streams.
+    const bool overlap = !h->timing && (double)P.npw * nb >= (double)(1 << 26);
     if (overlap) {
       PW_HIP(hipEventRecord(h->ev_fork, h->stream));
       PW_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
