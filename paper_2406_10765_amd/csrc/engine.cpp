@@ -44,8 +44,12 @@ struct pw_handle_s {
   // PW_PROGRESS=1 in the environment: report each completed filter block of a band-blocked
   // step on stderr (the stream is synchronised at each report).
   bool progress = false;
-  // Block whose bf16 planes the planes buffer holds (split-precision projectors), or null.
+  // Block whose bf16 planes the planes buffer holds (split-precision projectors), or null, and
+  // the number of its leading columns they cover.
   const void* yp_src = nullptr;
+  int yp_n = 0;
+  // Block whose planes follow those of yp_src (the Gram product's second operand), or null.
+  const void* wp_src = nullptr;
   std::chrono::steady_clock::time_point t_step;
   void report(const char* what, int i, int n) {
     if (!progress) return;
@@ -159,6 +163,7 @@ pw_status fail(pw_handle_s* h, pw_status s, const std::string& m) {
 
 template <typename T>
 struct Engine {
+  enum { PLANES_NONE = 0, PLANES_NEXT = 1, PLANES_GRAM = 2, PLANES_KEEP = 3 };
   pw_handle_s* h;
   const Plan& P;
   explicit Engine(pw_handle_s* hh) : h(hh), P(hh->plan) {}
@@ -191,7 +196,58 @@ struct Engine {
   unsigned int* beta_hi() const { return h->at<unsigned int>(P.lay.beta); }
   unsigned int* beta_lo() const { return beta_hi() + (size_t)P.ldw * P.nproj; }
   unsigned int* yp_hi() const { return h->at<unsigned int>(P.lay.yp); }
-  unsigned int* yp_lo() const { return yp_hi() + (size_t)P.ldw * P.nbb; }
+  unsigned int* yp_lo() const { return yp_hi() + (size_t)P.ldw * P.yp_cols; }
+  // the unblocked step keeps the planes of W = H Y beside those of Y for the Gram product
+  bool gram_planes() const { return beta_planes() && P.yp_cols >= 2 * P.nbb; }
+  // with projector planes, D B^H Y is kept as the nonlocal product's B planes in the bytes of PT
+  unsigned int* pt_hi() const { return h->at<unsigned int>(P.lay.pt); }
+  unsigned int* pt_lo() const { return pt_hi() + (size_t)P.nproj * P.nbb; }
+  bool planes_of(const void* Y, int nb) const { return Y && h->yp_src == Y && nb <= h->yp_n; }
+  void set_planes(const void* Y, int nb) {
+    h->yp_src = Y;
+    h->yp_n = Y ? nb : 0;
+    h->wp_src = nullptr;
+  }
+  // Rotation coefficients (n x n, leading dimension n) as the nn product's B operand: with
+  // split-precision rotation, bf16 planes (hi, then lo) in the bytes of the fp32 table at off;
+  // otherwise the table in the compute precision.  Column j is scaled by sc * lambda_j when lam is
+  // given.
+  const cplx<T>* coef_table(size_t off, int n, const double* lam, double sc) {
+    double2* Hs = h->at<double2>(P.lay.sh) + (size_t)n * n;
+    if constexpr (std::is_same<T, float>::value) {
+      if (flag(PW_FLAG_BF16_ROT)) {
+        unsigned int* hi = h->at<unsigned int>(off);
+        h->tbegin();
+        (void)launch_coef_planes(Hs, n, n, lam, sc, hi, hi + (size_t)n * n, n, h->stream);
+        h->tend(PW_PH_OTHER);
+        return h->at<cplx<T>>(off);
+      }
+    }
+    if (lam) {
+      cplx<T>* t = h->at<cplx<T>>(off);
+      h->tbegin();
+      (void)launch_scale_cols_lam<T>(Hs, n, t, n, n, lam, sc, h->stream);
+      h->tend(PW_PH_OTHER);
+      return t;
+    }
+    return coeffs(n);
+  }
+  // out = epilogue(A C[:, c0 : c0 + w]), C from coef_table (n x n).
+  hipError_t rot(const cplx<T>* A, long lda, const cplx<T>* C, int n, int c0, int w, cplx<T>* out, long ldo,
+                 const EpiH& e) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (flag(PW_FLAG_BF16_ROT)) {
+        const unsigned int* hi = reinterpret_cast<const unsigned int*>(C);
+        const unsigned int* ch = hi + (size_t)c0 * n;
+        const unsigned int* cl = hi + (size_t)n * n + (size_t)c0 * n;
+        if (beta_planes() && planes_of(A, n))
+          return launch_gemm_nn_bf16x3_planes(yp_hi(), yp_lo(), P.ldw, ch, cl, n, P.npw, w, n, out, ldo, e,
+                                              h->stream);
+        return launch_gemm_nn_bf16x3_bplanes(A, lda, ch, cl, n, P.npw, w, n, out, ldo, e, h->stream);
+      }
+    }
+    return launch_gemm_nn<T>(A, lda, C + (long)c0 * n, n, P.npw, w, n, out, ldo, e, h->stream);
+  }
 
   hipError_t cn(bool split16, const cplx<T>* A, long lda, const cplx<T>* B, long ldb, const cplx<T>* B2, long ldb2,
                 int ncol1, int M, int N, int K, int nsplit, double2* part, int nterm = 3) {
@@ -243,10 +299,12 @@ struct Engine {
 
   // out = alpha ((kin - c) Y + Zl + B D B^H Y) - beta Yp, where Zl is first filled with the
   // local potential part.  Zl may equal out (apply_h); Yp may equal out (in-place update).
-  // planes_out: also write the bf16 planes of out (split-precision projectors), for a following
-  // hop on out.
+  // planes_out (split-precision projectors): PLANES_NEXT writes the bf16 planes of out for a
+  // following hop on out; PLANES_GRAM writes them beside those of Y for the Gram product and keeps
+  // Y's; PLANES_KEEP keeps Y's (the caller leaves Y unchanged while it uses them); PLANES_NONE
+  // drops them.
   pw_status hop(const cplx<T>* Y, long ldy, int nb, cplx<T>* out, long ldo, cplx<T>* Zl, long ldz, double alpha,
-                double c, double beta_c, const cplx<T>* Yp, long ldp, bool planes_out = false) {
+                double c, double beta_c, const cplx<T>* Yp, long ldp, int planes_out = PLANES_NONE) {
     // the local part (FFTs, memory bound) on the second stream, the projection (matrix cores)
     // on the caller's stream; both only read Y, and the nonlocal GEMM waits for both.  With
     // phase timing on, everything stays on the caller's stream so that phase times are not
@@ -265,8 +323,10 @@ struct Engine {
       double2* parts = h->at<double2>(P.lay.parts);
       if constexpr (std::is_same<T, float>::value) {
         if (beta_planes()) {
-          if (h->yp_src != static_cast<const void*>(Y))
+          if (!planes_of(Y, nb)) {
             PW_TIMED(PW_PH_OTHER, launch_split_planes(Y, ldy, P.npw, nb, yp_hi(), yp_lo(), P.ldw, h->stream));
+            set_planes(Y, nb);
+          }
           PW_TIMED(PW_PH_PROJ, launch_gemm_cn_bf16x3_planes(beta_hi(), beta_lo(), P.ldw, yp_hi(), yp_lo(), P.ldw,
                                                             P.nproj, nb, P.npw, P.nsplit_proj, parts, h->stream));
         }
@@ -275,9 +335,14 @@ struct Engine {
         PW_TIMED(PW_PH_PROJ, launch_gemm_cn_beta<T>(beta_gen(), Y, ldy, nb, P.nsplit_proj, parts, h->stream));
       else if (!beta_planes())
         PW_TIMED(PW_PH_PROJ, cn(false, beta(), P.ldw, Y, ldy, nullptr, 0, nb, P.nproj, nb, P.npw, P.nsplit_proj, parts));
-      PW_TIMED(PW_PH_PROJ_REDUCE, launch_reduce_parts<T>(parts, P.nsplit_proj, P.nproj, nb,
-                                                         h->at<double>(P.lay.dscale), 4, nullptr, 0, PT, P.nproj,
+      if (beta_planes())
+        PW_TIMED(PW_PH_PROJ_REDUCE, launch_reduce_planes(parts, P.nsplit_proj, P.nproj, nb,
+                                                         h->at<double>(P.lay.dscale), 4, pt_hi(), pt_lo(), P.nproj,
                                                          h->stream));
+      else
+        PW_TIMED(PW_PH_PROJ_REDUCE, launch_reduce_parts<T>(parts, P.nsplit_proj, P.nproj, nb,
+                                                           h->at<double>(P.lay.dscale), 4, nullptr, 0, PT, P.nproj,
+                                                           h->stream));
     }
     if (overlap) PW_HIP(hipStreamWaitEvent(h->stream, h->ev_join, 0));
     EpiH e;
@@ -294,17 +359,24 @@ struct Engine {
     e.ldp = ldp;
     e.ph = e.pl = nullptr;
     e.ldpl = 0;
-    h->yp_src = nullptr;
+    const bool keep_y = (planes_out == PLANES_GRAM || planes_out == PLANES_KEEP) && planes_of(Y, nb) &&
+                        static_cast<const void*>(out) != static_cast<const void*>(Y) &&
+                        static_cast<const void*>(Zl) != static_cast<const void*>(Y);
+    const void* ysrc = h->yp_src;
+    set_planes(keep_y ? ysrc : nullptr, keep_y ? nb : 0);
     if constexpr (std::is_same<T, float>::value) {
       if (beta_planes()) {
-        if (planes_out) {
-          e.ph = yp_hi();
-          e.pl = yp_lo();
+        const bool w_gram = planes_out == PLANES_GRAM && keep_y && gram_planes();
+        if (planes_out == PLANES_NEXT || w_gram) {
+          const size_t pc = w_gram ? (size_t)P.ldw * nb : 0;  // W's columns follow Y's
+          e.ph = yp_hi() + pc;
+          e.pl = yp_lo() + pc;
           e.ldpl = P.ldw;
         }
-        PW_TIMED(PW_PH_NL, launch_gemm_nn_bf16x3_planes(beta_hi(), beta_lo(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj,
-                                                        out, ldo, e, h->stream));
-        if (planes_out) h->yp_src = out;
+        PW_TIMED(PW_PH_NL, launch_gemm_nn_bf16x3_planes(beta_hi(), beta_lo(), P.ldw, pt_hi(), pt_lo(), P.nproj,
+                                                        P.npw, nb, P.nproj, out, ldo, e, h->stream));
+        if (planes_out == PLANES_NEXT) set_planes(out, nb);
+        if (w_gram) h->wp_src = out;
         return PW_OK;
       }
     }
@@ -317,7 +389,7 @@ struct Engine {
   }
 
   pw_status apply_h(const cplx<T>* X, cplx<T>* HX, int nb, int ld) {
-    h->yp_src = nullptr;
+    set_planes(nullptr, 0);
     for (int c0 = 0; c0 < nb; c0 += P.nbb) {
       const int w = std::min(P.nbb, nb - c0);
       pw_status s = hop(X + (long)c0 * ld, ld, w, HX + (long)c0 * ld, ld, HX + (long)c0 * ld, ld, 1.0, 0.0, 0.0,
@@ -335,7 +407,7 @@ struct Engine {
     if (m < 1) return PW_OK;
     const double e = 0.5 * (prm.b - prm.a), c = 0.5 * (prm.b + prm.a);
     const double s1 = e / (prm.a_lo - c), tau = 2.0 / s1;
-    pw_status s = hop(Y0, ld0, w, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0, true);
+    pw_status s = hop(Y0, ld0, w, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0, PLANES_NEXT);
     if (s != PW_OK) return s;
     const cplx<T>* prev = Y0;
     long ldprev = ld0;
@@ -344,7 +416,7 @@ struct Engine {
     for (int k = 1; k < m; ++k) {
       const double sn = 1.0 / (tau - sg);
       cplx<T>* dst = (prev == Y0) ? u0() : const_cast<cplx<T>*>(prev);
-      s = hop(cur, ldw, w, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev, true);
+      s = hop(cur, ldw, w, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev, PLANES_NEXT);
       if (s != PW_OK) return s;
       prev = cur;
       ldprev = ldw;
@@ -352,7 +424,7 @@ struct Engine {
       sg = sn;
     }
     PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(cur, ldw, Y0, ld0, P.npw, w, h->stream));
-    if (h->yp_src == static_cast<const void*>(cur)) h->yp_src = Y0;  // same values
+    if (h->yp_src == static_cast<const void*>(cur)) h->yp_src = Y0;  // same values, same columns
     return PW_OK;
   }
 
@@ -375,24 +447,22 @@ struct Engine {
     s = project_solve(X, ld, W, ldw, nb);
     if (s != PW_OK) return s;
     h->report("Gram and eigensolve", 1, 1);
-    const cplx<T>* C = coeffs(nb);
     double* eig_d = h->at<double>(P.lay.eig);
     double* resid_d = h->at<double>(P.lay.resid);
+    const cplx<T>* C = coef_table(P.lay.ct, nb, nullptr, 1.0);
     // CL = -C diag(lambda)
-    cplx<T>* CL = h->at<cplx<T>>(P.lay.ct2);
-    double2* Hs = h->at<double2>(P.lay.sh) + (size_t)nb * nb;
-    PW_TIMED(PW_PH_OTHER, launch_scale_cols_lam<T>(Hs, nb, CL, nb, nb, eig_d, -1.0, h->stream));
+    const cplx<T>* CL = coef_table(P.lay.ct2, nb, eig_d, -1.0);
     EpiH st;
     std::memset(&st, 0, sizeof(st));
     for (int c0 = 0; c0 < nb; c0 += P.nbb) {
       const int w = std::min(P.nbb, nb - c0);
       // zb = W C[:, blk];  u0 = X CL[:, blk] + zb;  resid = ||u0 columns||
-      PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), W, ldw, C + (long)c0 * nb, nb, P.npw, w, nb, zb(), ldw, st));
+      PW_TIMED(PW_PH_ROTATE, rot(W, ldw, C, nb, c0, w, zb(), ldw, st));
       EpiH ad = st;
       ad.mode = 2;
       ad.Zl = zb();
       ad.ldz = ldw;
-      PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), X, ld, CL + (long)c0 * nb, nb, P.npw, w, nb, u0(), ldw, ad));
+      PW_TIMED(PW_PH_ROTATE, rot(X, ld, CL, nb, c0, w, u0(), ldw, ad));
       PW_TIMED(PW_PH_RESID, launch_resid<T>(u0(), ldw, u0(), ldw, (const double*)nullptr, P.npw, w, resid_d + c0,
                                             h->stream));
       if (prm.want_hx && HX) {
@@ -400,8 +470,9 @@ struct Engine {
       }
     }
     // X' = X C into W's storage, then back into X
-    PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), X, ld, C, nb, P.npw, nb, nb, W, ldw, st));
+    PW_TIMED(PW_PH_ROTATE, rot(X, ld, C, nb, 0, nb, W, ldw, st));
     PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(W, ldw, X, ld, P.npw, nb, h->stream));
+    set_planes(nullptr, 0);
     return finish(nb, eig_host, resid_host, bounds_out, prm.b);
   }
 
@@ -409,13 +480,14 @@ struct Engine {
     EpiH e;
     std::memset(&e, 0, sizeof(e));
     e.mode = 0;
-    PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), A, lda, C, nb, P.npw, nb, nb, out, ldo, e));
+    PW_TIMED(PW_PH_ROTATE, rot(A, lda, C, nb, 0, nb, out, ldo, e));
+    if (h->yp_src == static_cast<const void*>(out)) set_planes(nullptr, 0);
     return PW_OK;
   }
 
   pw_status eig_step(cplx<T>* X, cplx<T>* HX, int nb, int ld, const pw_step_params& prm, double* eig_host,
                      double* resid_host, double* bounds_out) {
-    h->yp_src = nullptr;
+    set_planes(nullptr, 0);
     if (P.nbb < P.nbands) return eig_step_blocked(X, HX, nb, ld, prm, eig_host, resid_host, bounds_out);
     const int m = prm.degree;
     double bmax = prm.b;
@@ -427,7 +499,7 @@ struct Engine {
     if (m >= 1) {
       const double e = 0.5 * (prm.b - prm.a), c = 0.5 * (prm.b + prm.a);
       const double s1 = e / (prm.a_lo - c), tau = 2.0 / s1;
-      s = hop(X, ld, nb, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0, true);
+      s = hop(X, ld, nb, u1(), ldw, zb(), ldw, s1 / e, c, 0.0, nullptr, 0, PLANES_NEXT);
       if (s != PW_OK) return s;
       const cplx<T>* prev = X;
       long ldprev = ld;
@@ -436,7 +508,7 @@ struct Engine {
       for (int k = 1; k < m; ++k) {
         const double sn = 1.0 / (tau - sg);
         cplx<T>* dst = (prev == X) ? u0() : const_cast<cplx<T>*>(prev);
-        s = hop(cur, ldw, nb, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev, true);
+        s = hop(cur, ldw, nb, dst, ldw, zb(), ldw, 2.0 * sn / e, c, sg * sn, prev, ldprev, PLANES_NEXT);
         if (s != PW_OK) return s;
         prev = cur;
         ldprev = ldw;
@@ -449,11 +521,11 @@ struct Engine {
     }
     // W = H Y
     cplx<T>* W = dead;
-    s = hop(Y, ldy, nb, W, ldw, zb(), ldw, 1.0, 0.0, 0.0, nullptr, 0);
+    s = hop(Y, ldy, nb, W, ldw, zb(), ldw, 1.0, 0.0, 0.0, nullptr, 0, gram_planes() ? PLANES_GRAM : PLANES_KEEP);
     if (s != PW_OK) return s;
     s = project_solve(Y, ldy, W, ldw, nb);
     if (s != PW_OK) return s;
-    const cplx<T>* C = coeffs(nb);
+    const cplx<T>* C = coef_table(P.lay.ct, nb, nullptr, 1.0);
     double* eig_d = h->at<double>(P.lay.eig);
     // X' = Y C (never in place), W' = W C
     cplx<T>* Wr = (prm.want_hx && HX) ? HX : zb();
@@ -462,6 +534,7 @@ struct Engine {
       s = rotate(Y, ldy, C, nb, u1(), ldw);
       if (s != PW_OK) return s;
       PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(u1(), ldw, X, ld, P.npw, nb, h->stream));
+      if (h->yp_src == static_cast<const void*>(X)) set_planes(nullptr, 0);
     } else {
       s = rotate(Y, ldy, C, nb, X, ld);
       if (s != PW_OK) return s;
@@ -470,6 +543,7 @@ struct Engine {
     if (s != PW_OK) return s;
     double* resid_d = h->at<double>(P.lay.resid);
     PW_TIMED(PW_PH_RESID, launch_resid<T>(Wr, ldwr, X, ld, eig_d, P.npw, nb, resid_d, h->stream));
+    set_planes(nullptr, 0);
     return finish(nb, eig_host, resid_host, bounds_out, bmax);
   }
 
@@ -477,8 +551,12 @@ struct Engine {
   pw_status project_solve(const cplx<T>* Y, long ldy, const cplx<T>* W, long ldw, int nb) {
     double2* parts = h->at<double2>(P.lay.parts);
     double2* SH = h->at<double2>(P.lay.sh);
-    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
-                            parts, 4));
+    if (gram_planes() && planes_of(Y, nb) && h->wp_src == static_cast<const void*>(W))
+      PW_TIMED(PW_PH_GRAM, launch_gemm_cn_bf16x3_planes(yp_hi(), yp_lo(), P.ldw, yp_hi(), yp_lo(), P.ldw, nb, 2 * nb,
+                                                        P.npw, P.nsplit_gram, parts, h->stream, 4));
+    else
+      PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
+                              parts, 4));
     double2* S = SH;
     double2* Hs = SH + (size_t)nb * nb;
     h->tbegin();

@@ -394,6 +394,28 @@ struct CnBPlanes {
   __device__ __forceinline__ void store(uint4* H, uint4* L, int tid) const { l.store(H, L, tid); }
 };
 
+// nn B-operand adapters: the K-contiguous columns of B as Br = (br, -bi) words, either fp32 split on
+// the fly or planes already holding those words (launch_reduce_planes).
+template <int NC, int NTH = 256>
+struct NnBF32 {
+  SplitK<NC, false, true, NTH> l;  // B rows are small, scalar loads
+  __device__ __forceinline__ void load(const void* B0, const void*, long ldb, int ncols, int c0, int k0, int kend,
+                                       int tid) {
+    const float2* P = static_cast<const float2*>(B0);
+    l.load(P, ldb, P, ldb, ncols, ncols, c0, k0, kend, tid);
+  }
+  __device__ __forceinline__ void store(uint4* H, uint4* L, int tid) const { l.store(H, L, tid); }
+};
+template <int NC, bool VEC, int NTH = 256>
+struct NnBPlanes {
+  PlanesK<NC, VEC, NTH> l;
+  __device__ __forceinline__ void load(const void* B0, const void* B1, long ldb, int ncols, int c0, int k0, int kend,
+                                       int tid) {
+    l.load(static_cast<const unsigned int*>(B0), static_cast<const unsigned int*>(B1), ldb, ncols, c0, k0, kend, tid);
+  }
+  __device__ __forceinline__ void store(uint4* H, uint4* L, int tid) const { l.store(H, L, tid); }
+};
+
 // ------------------------------------------------------------------------------------------
 // cn: part[s] = A^H B over K chunk s (fp32 accumulation per hFlush tiles, fp64 partials).
 // ------------------------------------------------------------------------------------------
@@ -502,10 +524,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 // ------------------------------------------------------------------------------------------
 // nn: out = epilogue(A B) (fp32 data, bf16x3 products).
 // ------------------------------------------------------------------------------------------
-template <class AL, int TM = hTM, int NT = 256>
+template <class AL, class BL, int TM = hTM, int NT = 256>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nn_bf16x3(
-    const void* __restrict__ A0, const void* __restrict__ A1, long lda, const float2* __restrict__ B, long ldb, int M,
-    int N, int K, int tiles_n, float2* out, long ldo, EpiH e) {
+    const void* __restrict__ A0, const void* __restrict__ A1, long lda, const void* __restrict__ B0,
+    const void* __restrict__ B1, long ldb, int M, int N, int K, int tiles_n, float2* out, long ldo, EpiH e) {
   constexpr int WM = TM / 64, TN = 64 * (NT / 64) / WM;
   constexpr int PA = TM * 4, PB = TN * 4;
   __shared__ uint4 sAh[2][PA], sAl[2][PA], sBh[2][PB], sBl[2][PB];
@@ -520,11 +542,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
     for (int b = 0; b < 4; ++b) cr[a][b] = ci[a][b] = v4f16{0, 0, 0, 0};
   AL la;
-  SplitK<TN, false, true, NT> lb;  // Br = (br, -bi); B rows are small, scalar loads
+  BL lb;  // Br = (br, -bi)
   const int ntiles = (K + hBK - 1) / hBK;
   if (ntiles > 0) {
     la.load(A0, A1, lda, M, i0, 0, K, tid);
-    lb.load(B, ldb, B, ldb, N, N, j0, 0, K, tid);
+    lb.load(B0, B1, ldb, N, j0, 0, K, tid);
     la.store(sAh[0], sAl[0], tid);
     lb.store(sBh[0], sBl[0], tid);
   }
@@ -535,7 +557,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     if (more) {
       const int kn = (it + 1) * hBK;
       la.load(A0, A1, lda, M, i0, kn, K, tid);
-      lb.load(B, ldb, B, ldb, N, N, j0, kn, K, tid);
+      lb.load(B0, B1, ldb, N, j0, kn, K, tid);
     }
     v8bf ah[4], al[4];
 #pragma unroll
@@ -628,6 +650,63 @@ hipError_t launch_split_planes(const float2* X, long ldx, int rows, int cols, un
   return hipGetLastError();
 }
 
+// Sum of the split-K partials, scaled per row by dscale[i % dper], rounded to fp32 and stored as the
+// nn B operand's planes: words (re, -im) of bf16(x) and of bf16(x - hi), k = row contiguous.
+__global__ void k_reduce_planes(const double2* __restrict__ part, int nsplit, int M, int N,
+                                const double* __restrict__ dscale, int dper, unsigned int* __restrict__ H,
+                                unsigned int* __restrict__ L, long ldp) {
+  PW_GRID_STRIDE(idx, (long)M * N) {
+    const int j = (int)(idx / M), i = (int)(idx - (long)j * M);
+    double2 s = part[idx];
+    for (int p = 1; p < nsplit; ++p) {
+      const double2 v = part[(long)p * M * N + idx];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    if (dscale) {
+      const double d = dscale[i % dper];
+      s.x *= d;
+      s.y *= d;
+    }
+    const float re = (float)s.x, im = (float)s.y;
+    const Split2 sr = split(re), si = split(-im);
+    H[(long)j * ldp + i] = pack(sr.h, si.h);
+    L[(long)j * ldp + i] = pack(sr.l, si.l);
+  }
+}
+
+hipError_t launch_reduce_planes(const double2* part, int nsplit, int M, int N, const double* dscale, int dper,
+                                unsigned int* H, unsigned int* L, long ldp, hipStream_t s) {
+  const long n = (long)M * N;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_planes, dim3(stride_blocks(n)), dim3(256), 0, s, part, nsplit, M, N, dscale,
+                     dper > 0 ? dper : 1, H, L, ldp);
+  return hipGetLastError();
+}
+
+// n x n FP64 coefficients (columns optionally scaled by sc * lam[j]) as the nn B planes: rounded to
+// fp32, then words (re, -im) of bf16(x) and bf16(x - hi).
+__global__ void k_coef_planes(const double2* __restrict__ C, long ldc, int n, const double* __restrict__ lam,
+                              double sc, unsigned int* __restrict__ H, unsigned int* __restrict__ L, long ldp) {
+  PW_GRID_STRIDE(idx, (long)n * n) {
+    const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
+    const double2 v = C[(long)j * ldc + i];
+    const double f = lam ? sc * lam[j] : 1.0;
+    const float re = (float)(f * v.x), im = (float)(f * v.y);
+    const Split2 sr = split(re), si = split(-im);
+    H[(long)j * ldp + i] = pack(sr.h, si.h);
+    L[(long)j * ldp + i] = pack(sr.l, si.l);
+  }
+}
+
+hipError_t launch_coef_planes(const double2* C, long ldc, int n, const double* lam, double sc, unsigned int* H,
+                              unsigned int* L, long ldp, hipStream_t s) {
+  const long m = (long)n * n;
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coef_planes, dim3(stride_blocks(m)), dim3(256), 0, s, C, ldc, n, lam, sc, H, L, ldp);
+  return hipGetLastError();
+}
+
 static inline bool ok16(const void* p, long ld) {
   return (reinterpret_cast<uintptr_t>(p) & 15) == 0 && (ld % 2) == 0;
 }
@@ -680,40 +759,36 @@ int gemm_cn_bf16_planes_tiles(int M, int N) {
 
 hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
                                         const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
-                                        int nsplit, double2* part, hipStream_t s) {
+                                        int nsplit, double2* part, hipStream_t s, int nterm) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if (planes_wide(M)) {
-    const int kchunk = cn_chunk(K, nsplit);
-    const int tm = ceil_div(M, hWM), tn = ceil_div(N, hTN);
-    dim3 grid(tm * tn * nsplit);
-    const void* a0 = Ahi;
-    const void* a1 = Alo;
-    const void* b0 = Bhi;
-    const void* b1 = Blo;
-    const void* nul = nullptr;
-    if (ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb))
-      hipLaunchKernelGGL((k_gemm_cn_bf16x3<3, CnAPlanes<hWM, true, hWT>, CnBPlanes<hTN, true, hWT>, hWM, hWT>), grid,
-                         dim3(hWT), 0, s, a0, a1, lda, b0, b1, ldb, nul, 0L, N, M, N, K, kchunk, tm, tn, part);
-    else
-      hipLaunchKernelGGL((k_gemm_cn_bf16x3<3, CnAPlanes<hWM, false, hWT>, CnBPlanes<hTN, false, hWT>, hWM, hWT>), grid,
-                         dim3(hWT), 0, s, a0, a1, lda, b0, b1, ldb, nul, 0L, N, M, N, K, kchunk, tm, tn, part);
-    return hipGetLastError();
-  }
   const int kchunk = cn_chunk(K, nsplit);
-  const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
   const bool vec = ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb);
-  dim3 grid(tm * tn * nsplit);
   const void* a0 = Ahi;
   const void* a1 = Alo;
   const void* b0 = Bhi;
   const void* b1 = Blo;
   const void* nul = nullptr;
-  if (vec)
-    hipLaunchKernelGGL((k_gemm_cn_bf16x3<3, CnAPlanes<hTM, true>, CnBPlanes<hTN, true>>), grid, dim3(256), 0, s, a0,
-                       a1, lda, b0, b1, ldb, nul, 0L, N, M, N, K, kchunk, tm, tn, part);
-  else
-    hipLaunchKernelGGL((k_gemm_cn_bf16x3<3, CnAPlanes<hTM, false>, CnBPlanes<hTN, false>>), grid, dim3(256), 0, s, a0,
-                       a1, lda, b0, b1, ldb, nul, 0L, N, M, N, K, kchunk, tm, tn, part);
+#define PW_CNP(NTERM, V, TM, NT)                                                                                  \
+  hipLaunchKernelGGL((k_gemm_cn_bf16x3<NTERM, CnAPlanes<TM, V, NT>, CnBPlanes<hTN, V, NT>, TM, NT>), grid, dim3(NT), \
+                     0, s, a0, a1, lda, b0, b1, ldb, nul, 0L, N, M, N, K, kchunk, tm, tn, part)
+  if (planes_wide(M)) {
+    const int tm = ceil_div(M, hWM), tn = ceil_div(N, hTN);
+    dim3 grid(tm * tn * nsplit);
+    if (nterm == 4) {
+      if (vec) PW_CNP(4, true, hWM, hWT); else PW_CNP(4, false, hWM, hWT);
+    } else {
+      if (vec) PW_CNP(3, true, hWM, hWT); else PW_CNP(3, false, hWM, hWT);
+    }
+    return hipGetLastError();
+  }
+  const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
+  dim3 grid(tm * tn * nsplit);
+  if (nterm == 4) {
+    if (vec) PW_CNP(4, true, hTM, 256); else PW_CNP(4, false, hTM, 256);
+  } else {
+    if (vec) PW_CNP(3, true, hTM, 256); else PW_CNP(3, false, hTM, 256);
+  }
+#undef PW_CNP
   return hipGetLastError();
 }
 
@@ -725,30 +800,53 @@ hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, lon
   dim3 grid(tm * tn);
   const void* a0 = A;
   const void* a1 = nullptr;
+  const void* b0 = B;
   if (vec)
-    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, true>>), grid, dim3(256), 0, s, a0, a1, lda, B, ldb, M, N, K,
-                       tn, out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, true>, NnBF32<hTN>>), grid, dim3(256), 0, s, a0, a1, lda, b0,
+                       a1, ldb, M, N, K, tn, out, ldo, e);
   else
-    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, false>>), grid, dim3(256), 0, s, a0, a1, lda, B, ldb, M, N, K,
-                       tn, out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, false>, NnBF32<hTN>>), grid, dim3(256), 0, s, a0, a1, lda, b0,
+                       a1, ldb, M, N, K, tn, out, ldo, e);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda, const float2* B,
-                                        long ldb, int M, int N, int K, float2* out, long ldo, const EpiH& e,
-                                        hipStream_t s) {
+hipError_t launch_gemm_nn_bf16x3_bplanes(const float2* A, long lda, const unsigned int* Bhi, const unsigned int* Blo,
+                                         long ldb, int M, int N, int K, float2* out, long ldo, const EpiH& e,
+                                         hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
-  const bool vec = ok_planes(Ahi, Alo, lda);
+  const bool vec = ok16(A, lda) && ok_planes(Bhi, Blo, ldb);
+  dim3 grid(tm * tn);
+  const void* a0 = A;
+  const void* a1 = nullptr;
+  const void* b0 = Bhi;
+  const void* b1 = Blo;
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, true>, NnBPlanes<hTN, true>>), grid, dim3(256), 0, s, a0, a1,
+                       lda, b0, b1, ldb, M, N, K, tn, out, ldo, e);
+  else
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, false>, NnBPlanes<hTN, false>>), grid, dim3(256), 0, s, a0, a1,
+                       lda, b0, b1, ldb, M, N, K, tn, out, ldo, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
+                                        const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
+                                        float2* out, long ldo, const EpiH& e, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
+  const bool vec = ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb);
   dim3 grid(tm * tn);
   const void* a0 = Ahi;
   const void* a1 = Alo;
+  const void* b0 = Bhi;
+  const void* b1 = Blo;
   if (vec)
-    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAPlanes<hTM, true>>), grid, dim3(256), 0, s, a0, a1, lda, B, ldb, M, N, K,
-                       tn, out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAPlanes<hTM, true>, NnBPlanes<hTN, true>>), grid, dim3(256), 0, s, a0, a1,
+                       lda, b0, b1, ldb, M, N, K, tn, out, ldo, e);
   else
-    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAPlanes<hTM, false>>), grid, dim3(256), 0, s, a0, a1, lda, B, ldb, M, N,
-                       K, tn, out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAPlanes<hTM, false>, NnBPlanes<hTN, false>>), grid, dim3(256), 0, s, a0,
+                       a1, lda, b0, b1, ldb, M, N, K, tn, out, ldo, e);
   return hipGetLastError();
 }
 

@@ -135,13 +135,27 @@ hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, lon
 // dimensions of planes count 32-bit words.
 hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
                                         const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
-                                        int nsplit, double2* part, hipStream_t s);
+                                        int nsplit, double2* part, hipStream_t s, int nterm = 3);
 // hi/lo planes (one (re, im) word per entry, leading dimension ldp) of rows x cols fp32 complex.
 hipError_t launch_split_planes(const float2* X, long ldx, int rows, int cols, unsigned int* H, unsigned int* L,
                                long ldp, hipStream_t s);
-hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda, const float2* B,
-                                        long ldb, int M, int N, int K, float2* out, long ldo, const EpiH& e,
-                                        hipStream_t s);
+// nn with A = planes of K columns of length M and B = planes of N columns of length K holding
+// (re, -im) words (launch_reduce_planes).
+hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
+                                        const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
+                                        float2* out, long ldo, const EpiH& e, hipStream_t s);
+// nn with fp32 A (M contiguous) and B planes as above.
+hipError_t launch_gemm_nn_bf16x3_bplanes(const float2* A, long lda, const unsigned int* Bhi, const unsigned int* Blo,
+                                         long ldb, int M, int N, int K, float2* out, long ldo, const EpiH& e,
+                                         hipStream_t s);
+// n x n FP64 matrix C (ldc), column j scaled by sc * lam[j] when lam is given, as nn B planes (ldp).
+hipError_t launch_coef_planes(const double2* C, long ldc, int n, const double* lam, double sc, unsigned int* H,
+                              unsigned int* L, long ldp, hipStream_t s);
+// launch_reduce_parts into the nn B planes: the M x N sum over nsplit partials, row i scaled by
+// dscale[i % dper], rounded to fp32 and split into words (re, -im) of hi and lo (leading dimension
+// ldp, a multiple of 4 words).
+hipError_t launch_reduce_planes(const double2* part, int nsplit, int M, int N, const double* dscale, int dper,
+                                unsigned int* H, unsigned int* L, long ldp, hipStream_t s);
 
 // --------------------------------------------------------------- misc ------
 template <typename T>

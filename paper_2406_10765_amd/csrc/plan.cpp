@@ -225,7 +225,11 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   P.nsplit_proj = P.nproj ? pick_split(bkb ? gemm_cn_bf16_planes_tiles(P.nproj, P.nbb) : gemm_cn_tiles(P.nproj, P.nbb, f64),
                                        P.npw)
                           : 1;
-  P.nsplit_gram = pick_split(bgr ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands) : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
+  const bool gram_planes = bkb && bgr && P.nbb >= P.nbands;
+  P.yp_cols = bkb ? P.nbb * (gram_planes ? 2 : 1) : 0;
+  P.nsplit_gram = pick_split(gram_planes ? gemm_cn_bf16_planes_tiles(P.nbands, 2 * P.nbands)
+                             : bgr       ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands)
+                                         : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
                              P.npw);
 
   // --- arena layout --------------------------------------------------------------
@@ -270,7 +274,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   L.g1 = take(per_band_g1 * P.fft_batch);
   L.pt = take(cb * std::max(1, P.nproj) * P.nbb);
   // bf16 hi/lo planes of the block entering the projector product (split-precision projectors)
-  L.yp = take((P.flags & PW_FLAG_BF16_KB) ? 8 * (size_t)P.ldw * P.nbb : 0);
+  L.yp = take(8 * (size_t)P.ldw * P.yp_cols);
   const size_t parts = std::max((size_t)P.nsplit_proj * P.nproj * P.nbb, (size_t)P.nsplit_gram * nb * 2 * nb);
   L.parts = take(16 * parts);
   L.sh = take(16 * nb * 2 * nb);

@@ -47,6 +47,9 @@ struct Plan {
   int fft_batch;               // bands per FFT launch group
   int nbb;                     // bands per filter block (== nbands: unblocked step)
   int nsplit_proj, nsplit_gram;
+  // bf16 plane columns held per plane: nbb, or 2 nbb when the unblocked step also keeps the
+  // planes of H Y beside those of Y (split-precision projectors and Gram product)
+  int yp_cols;
   int hmax[3];                 // max |n_d| over the sphere (projector generator tables)
   int bwidth;                  // per-atom axis-factor table length
   ArenaLayout lay;
