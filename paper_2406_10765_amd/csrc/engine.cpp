@@ -359,6 +359,7 @@ struct Engine {
     e.ldp = ldp;
     e.ph = e.pl = nullptr;
     e.ldpl = 0;
+    e.vec4 = 0;
     const bool keep_y = (planes_out == PLANES_GRAM || planes_out == PLANES_KEEP) && planes_of(Y, nb) &&
                         static_cast<const void*>(out) != static_cast<const void*>(Y) &&
                         static_cast<const void*>(Zl) != static_cast<const void*>(Y);

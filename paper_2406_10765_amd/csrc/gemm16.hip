@@ -524,23 +524,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 // ------------------------------------------------------------------------------------------
 // nn: out = epilogue(A B) (fp32 data, bf16x3 products).
 // ------------------------------------------------------------------------------------------
-template <class AL, class BL, int TM = hTM, int NT = 256>
+// Each wave owns a WR x (4096 / WR) block of the tile: WR = 64 holds the A fragments and streams
+// the B ones; WR = 128 (one wave per 32 columns) holds the B fragments and their (bi, br) forms
+// and streams A, so that no two waves of a workgroup form the same (bi, br) words.
+template <class AL, class BL, int TM = hTM, int NT = 256, int WR = 64>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nn_bf16x3(
     const void* __restrict__ A0, const void* __restrict__ A1, long lda, const void* __restrict__ B0,
     const void* __restrict__ B1, long ldb, int M, int N, int K, int tiles_n, float2* out, long ldo, EpiH e) {
-  constexpr int WM = TM / 64, TN = 64 * (NT / 64) / WM;
+  constexpr int WC = 4096 / WR, AT = WR / 16, BT = WC / 16;
+  constexpr int WM = TM / WR, TN = WC * (NT / 64) / WM;
   constexpr int PA = TM * 4, PB = TN * 4;
   __shared__ uint4 sAh[2][PA], sAl[2][PA], sBh[2][PB], sBl[2][PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int t = xcd_tile16(blockIdx.x, gridDim.x);
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
   const int i0 = tm * TM, j0 = tn * TN;
-  const int mo = (wave % WM) * 64, no = (wave / WM) * 64;
-  v4f16 cr[4][4], ci[4][4];
+  const int mo = (wave % WM) * WR, no = (wave / WM) * WC;
+  v4f16 cr[AT][BT], ci[AT][BT];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < AT; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) cr[a][b] = ci[a][b] = v4f16{0, 0, 0, 0};
+    for (int b = 0; b < BT; ++b) cr[a][b] = ci[a][b] = v4f16{0, 0, 0, 0};
   AL la;
   BL lb;  // Br = (br, -bi)
   const int ntiles = (K + hBK - 1) / hBK;
@@ -559,25 +563,50 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       la.load(A0, A1, lda, M, i0, kn, K, tid);
       lb.load(B0, B1, ldb, N, j0, kn, K, tid);
     }
-    v8bf ah[4], al[4];
+    if constexpr (WR == 64) {
+      v8bf ah[AT], al[AT];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      ah[a] = frag(sAh[cur], mo + a * 16, lane);
-      al[a] = frag(sAl[cur], mo + a * 16, lane);
-    }
+      for (int a = 0; a < AT; ++a) {
+        ah[a] = frag(sAh[cur], mo + a * 16, lane);
+        al[a] = frag(sAl[cur], mo + a * 16, lane);
+      }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const v8bf rh = frag(sBh[cur], no + b * 16, lane);
-      const v8bf rl = frag(sBl[cur], no + b * 16, lane);
-      const v8bf ih = swapneg_lo(rh), il = swapneg_lo(rl);
+      for (int b = 0; b < BT; ++b) {
+        const v8bf rh = frag(sBh[cur], no + b * 16, lane);
+        const v8bf rl = frag(sBl[cur], no + b * 16, lane);
+        const v8bf ih = swapneg_lo(rh), il = swapneg_lo(rl);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        cr[a][b] = mma16(ah[a], rh, cr[a][b]);
-        ci[a][b] = mma16(ah[a], ih, ci[a][b]);
-        cr[a][b] = mma16(ah[a], rl, cr[a][b]);
-        ci[a][b] = mma16(ah[a], il, ci[a][b]);
-        cr[a][b] = mma16(al[a], rh, cr[a][b]);
-        ci[a][b] = mma16(al[a], ih, ci[a][b]);
+        for (int a = 0; a < AT; ++a) {
+          cr[a][b] = mma16(ah[a], rh, cr[a][b]);
+          ci[a][b] = mma16(ah[a], ih, ci[a][b]);
+          cr[a][b] = mma16(ah[a], rl, cr[a][b]);
+          ci[a][b] = mma16(ah[a], il, ci[a][b]);
+          cr[a][b] = mma16(al[a], rh, cr[a][b]);
+          ci[a][b] = mma16(al[a], ih, ci[a][b]);
+        }
+      }
+    } else {
+      v8bf rh[BT], rl[BT], ih[BT], il[BT];
+#pragma unroll
+      for (int b = 0; b < BT; ++b) {
+        rh[b] = frag(sBh[cur], no + b * 16, lane);
+        rl[b] = frag(sBl[cur], no + b * 16, lane);
+        ih[b] = swapneg_lo(rh[b]);
+        il[b] = swapneg_lo(rl[b]);
+      }
+#pragma unroll
+      for (int a = 0; a < AT; ++a) {
+        const v8bf ah = frag(sAh[cur], mo + a * 16, lane);
+        const v8bf al = frag(sAl[cur], mo + a * 16, lane);
+#pragma unroll
+        for (int b = 0; b < BT; ++b) {
+          cr[a][b] = mma16(ah, rh[b], cr[a][b]);
+          ci[a][b] = mma16(ah, ih[b], ci[a][b]);
+          cr[a][b] = mma16(ah, rl[b], cr[a][b]);
+          ci[a][b] = mma16(ah, il[b], ci[a][b]);
+          cr[a][b] = mma16(al, rh[b], cr[a][b]);
+          ci[a][b] = mma16(al, ih[b], ci[a][b]);
+        }
       }
     }
     if (more) {
@@ -591,33 +620,90 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const float2* Zl = static_cast<const float2*>(e.Zl);
   const float2* Yp = static_cast<const float2*>(e.Yp);
   const float alpha = (float)e.alpha, cc = (float)e.c, beta = (float)e.beta;
+  const float2 zero2 = make_float2(0.f, 0.f);
+  // one entry: v = accumulator, kr = kin[row], y, z, p = Y, Zl, Yp at (row, col)
+  auto update = [&](float2 v, float kr, float2 y, float2 z, float2 p) {
+    if (e.mode == 1) {
+      const float kc = kr - cc;
+      v.x = alpha * (kc * y.x + z.x + v.x);
+      v.y = alpha * (kc * y.y + z.y + v.y);
+      if (Yp) {
+        v.x -= beta * p.x;
+        v.y -= beta * p.y;
+      }
+    }
+    if (e.mode == 2) {
+      v.x += z.x;
+      v.y += z.y;
+    }
+    return v;
+  };
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < AT; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < BT; ++b) {
       const int col = j0 + no + b * 16 + (lane & 15);
+      const int row0 = i0 + mo + a * 16 + 4 * (lane >> 4);
+      if (e.vec4 && col < N && row0 + 4 <= M) {
+        // the lane's four consecutive rows of one column: 16-byte accesses
+        float2 v[4], y[4], z[4], q[4];
+        float kr[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = i0 + mo + a * 16 + 4 * (lane >> 4) + r;
-        if (row < M && col < N) {
-          float2 v = make_float2(cr[a][b][r], ci[a][b][r]);
-          if (e.mode == 1) {
-            const float2 y = Y[(long)col * e.ldy + row];
-            const float2 z = Zl[(long)col * e.ldz + row];
-            const float kc = kin[row] - cc;
-            v.x = alpha * (kc * y.x + z.x + v.x);
-            v.y = alpha * (kc * y.y + z.y + v.y);
+        for (int r = 0; r < 4; ++r) y[r] = z[r] = q[r] = zero2;
+        if (e.mode == 1) {
+          const float4 k4 = *reinterpret_cast<const float4*>(kin + row0);
+          kr[0] = k4.x;
+          kr[1] = k4.y;
+          kr[2] = k4.z;
+          kr[3] = k4.w;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float4 yy = reinterpret_cast<const float4*>(Y + (long)col * e.ldy + row0)[h];
+            y[2 * h] = make_float2(yy.x, yy.y);
+            y[2 * h + 1] = make_float2(yy.z, yy.w);
             if (Yp) {
-              const float2 p = Yp[(long)col * e.ldp + row];
-              v.x -= beta * p.x;
-              v.y -= beta * p.y;
+              const float4 pp = reinterpret_cast<const float4*>(Yp + (long)col * e.ldp + row0)[h];
+              q[2 * h] = make_float2(pp.x, pp.y);
+              q[2 * h + 1] = make_float2(pp.z, pp.w);
             }
           }
-          if (e.mode == 2) {
-            const auto z = Zl[(long)col * e.ldz + row];
-            v.x += z.x;
-            v.y += z.y;
+        }
+        if (e.mode >= 1) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float4 zz = reinterpret_cast<const float4*>(Zl + (long)col * e.ldz + row0)[h];
+            z[2 * h] = make_float2(zz.x, zz.y);
+            z[2 * h + 1] = make_float2(zz.z, zz.w);
           }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = update(make_float2(cr[a][b][r], ci[a][b][r]), kr[r], y[r], z[r], q[r]);
+        float4* oq = reinterpret_cast<float4*>(out + (long)col * ldo + row0);
+        oq[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+        oq[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+        if (e.ph) {
+          unsigned int wh[4], wl[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const Split2 sr = split(v[r].x), si = split(v[r].y);
+            wh[r] = pack(sr.h, si.h);
+            wl[r] = pack(sr.l, si.l);
+          }
+          const long o = (long)col * e.ldpl + row0;
+          *reinterpret_cast<uint4*>(static_cast<unsigned int*>(e.ph) + o) = uint4{wh[0], wh[1], wh[2], wh[3]};
+          *reinterpret_cast<uint4*>(static_cast<unsigned int*>(e.pl) + o) = uint4{wl[0], wl[1], wl[2], wl[3]};
+        }
+        continue;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + r;
+        if (row < M && col < N) {
+          const bool m1 = e.mode == 1;
+          const float2 y = m1 ? Y[(long)col * e.ldy + row] : zero2;
+          const float2 z = e.mode >= 1 ? Zl[(long)col * e.ldz + row] : zero2;
+          const float2 q = m1 && Yp ? Yp[(long)col * e.ldp + row] : zero2;
+          const float2 v = update(make_float2(cr[a][b][r], ci[a][b][r]), m1 ? kin[row] : 0.f, y, z, q);
           out[(long)col * ldo + row] = v;
           if (e.ph) {
             const Split2 sr = split(v.x), si = split(v.y);
@@ -707,6 +793,19 @@ hipError_t launch_coef_planes(const double2* C, long ldc, int n, const double* l
   return hipGetLastError();
 }
 
+// Whether every array of the nn epilogue allows 16-byte accesses of a lane's four rows (row0 a
+// multiple of 4): 16-byte aligned bases, even complex leading dimensions, planes' a multiple of 4.
+static EpiH epi_vec4(const EpiH& e, const void* out, long ldo) {
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  bool ok = al(out) && ldo % 2 == 0;
+  if (e.mode >= 1) ok = ok && al(e.Zl) && e.ldz % 2 == 0;
+  if (e.mode == 1) ok = ok && al(e.kin) && al(e.Y) && e.ldy % 2 == 0 && (!e.Yp || (al(e.Yp) && e.ldp % 2 == 0));
+  if (e.ph) ok = ok && al(e.ph) && al(e.pl) && e.ldpl % 4 == 0;
+  EpiH r = e;
+  r.vec4 = ok ? 1 : 0;
+  return r;
+}
+
 static inline bool ok16(const void* p, long ld) {
   return (reinterpret_cast<uintptr_t>(p) & 15) == 0 && (ld % 2) == 0;
 }
@@ -751,6 +850,8 @@ hipError_t launch_gemm_cn_bf16x3(const float2* A, long lda, const float2* B, lon
 // is then re-read by half as many workgroups.  (The nonlocal product, whose K is short, keeps two
 // 128 x 128 workgroups per CU, which overlap one's epilogue with the other's MFMAs.)
 constexpr int hWM = 256, hWT = 512;
+// wave tile rows of the nonlocal product on planes
+constexpr int hNnWR = 128;
 static bool planes_wide(int M) { return M >= 512; }
 
 int gemm_cn_bf16_planes_tiles(int M, int N) {
@@ -795,6 +896,7 @@ hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned 
 hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, long ldb, int M, int N, int K,
                                  float2* out, long ldo, const EpiH& e, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  const EpiH ev = epi_vec4(e, out, ldo);
   const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
   const bool vec = ok16(A, lda);
   dim3 grid(tm * tn);
@@ -803,10 +905,10 @@ hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, lon
   const void* b0 = B;
   if (vec)
     hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, true>, NnBF32<hTN>>), grid, dim3(256), 0, s, a0, a1, lda, b0,
-                       a1, ldb, M, N, K, tn, out, ldo, e);
+                       a1, ldb, M, N, K, tn, out, ldo, ev);
   else
     hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, false>, NnBF32<hTN>>), grid, dim3(256), 0, s, a0, a1, lda, b0,
-                       a1, ldb, M, N, K, tn, out, ldo, e);
+                       a1, ldb, M, N, K, tn, out, ldo, ev);
   return hipGetLastError();
 }
 
@@ -814,6 +916,7 @@ hipError_t launch_gemm_nn_bf16x3_bplanes(const float2* A, long lda, const unsign
                                          long ldb, int M, int N, int K, float2* out, long ldo, const EpiH& e,
                                          hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  const EpiH ev = epi_vec4(e, out, ldo);
   const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
   const bool vec = ok16(A, lda) && ok_planes(Bhi, Blo, ldb);
   dim3 grid(tm * tn);
@@ -823,10 +926,10 @@ hipError_t launch_gemm_nn_bf16x3_bplanes(const float2* A, long lda, const unsign
   const void* b1 = Blo;
   if (vec)
     hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, true>, NnBPlanes<hTN, true>>), grid, dim3(256), 0, s, a0, a1,
-                       lda, b0, b1, ldb, M, N, K, tn, out, ldo, e);
+                       lda, b0, b1, ldb, M, N, K, tn, out, ldo, ev);
   else
     hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAF32<hTM, false>, NnBPlanes<hTN, false>>), grid, dim3(256), 0, s, a0, a1,
-                       lda, b0, b1, ldb, M, N, K, tn, out, ldo, e);
+                       lda, b0, b1, ldb, M, N, K, tn, out, ldo, ev);
   return hipGetLastError();
 }
 
@@ -834,6 +937,7 @@ hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned 
                                         const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
                                         float2* out, long ldo, const EpiH& e, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  const EpiH ev = epi_vec4(e, out, ldo);
   const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
   const bool vec = ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb);
   dim3 grid(tm * tn);
@@ -842,11 +946,11 @@ hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned 
   const void* b0 = Bhi;
   const void* b1 = Blo;
   if (vec)
-    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAPlanes<hTM, true>, NnBPlanes<hTN, true>>), grid, dim3(256), 0, s, a0, a1,
-                       lda, b0, b1, ldb, M, N, K, tn, out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAPlanes<hTM, true>, NnBPlanes<hTN, true>, hTM, 256, hNnWR>), grid, dim3(256),
+                       0, s, a0, a1, lda, b0, b1, ldb, M, N, K, tn, out, ldo, ev);
   else
-    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAPlanes<hTM, false>, NnBPlanes<hTN, false>>), grid, dim3(256), 0, s, a0,
-                       a1, lda, b0, b1, ldb, M, N, K, tn, out, ldo, e);
+    hipLaunchKernelGGL((k_gemm_nn_bf16x3<NnAPlanes<hTM, false>, NnBPlanes<hTN, false>, hTM, 256, hNnWR>), grid,
+                       dim3(256), 0, s, a0, a1, lda, b0, b1, ldb, M, N, K, tn, out, ldo, ev);
   return hipGetLastError();
 }
 

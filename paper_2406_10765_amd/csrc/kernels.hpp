@@ -91,6 +91,8 @@ struct EpiH {
   void* ph;
   void* pl;
   long ldpl;
+  // split-precision nn: set by the launcher when every epilogue array allows 16-byte accesses
+  int vec4;
 };
 
 // Generator of the projector matrix inside the GEMM loaders, for cells whose table would not
