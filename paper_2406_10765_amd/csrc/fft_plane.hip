@@ -312,6 +312,21 @@ struct StickShape {
   static constexpr int SPW0 = 256 / TT, SPWL = (48 * 1024) / (N * (int)sizeof(cplx<T>));
   static constexpr int SPW = SPW0 < SPWL ? SPW0 : SPWL;
   static constexpr int NT = SPW * TT;
+  // LDS swizzle.  A wave holds G = 64 / TT sticks (lane = TT s + t); the TT threads of one stick
+  // touch TT positions at once, 1 or B apart, which in a plain [position][stick] layout all fall
+  // in the same banks.  Position p goes to row p ^ ((p / B) & 1) (neighbouring rows swapped in
+  // every other block of B) and its stick s to column s ^ (G h(p)), h(p) = (p / 2 + p / 2B) mod
+  // (SPW / G): the TT positions of one access then occupy distinct G-stick slices of a bank row,
+  // whether the LDS has 32, 64 or 128 four-byte banks.  Used where the shapes allow it (64 % TT
+  // == 0, SPW a multiple of the elements per 256 bytes, B even).
+  static constexpr int E = 256 / (int)sizeof(cplx<T>);
+  static constexpr int G = 64 % TT == 0 ? 64 / TT : 0;
+  static constexpr bool SWZ = G > 0 && E > G && SPW % E == 0 && B % 2 == 0;
+  static constexpr int H = G > 0 ? SPW / G : 1;
+  __device__ __forceinline__ static int at(int p, int s) {
+    if constexpr (SWZ) return (p ^ ((p / B) & 1)) * SPW + (s ^ (G * (((p >> 1) + p / (2 * B)) % H)));
+    else return p * SPW + s;
+  }
 };
 
 __device__ __forceinline__ int stick_index(int z, int h, int N) {
@@ -357,7 +372,7 @@ __global__ __launch_bounds__(256) void k_sticks_inv_n(const cplx<T>* __restrict_
       r1[i][k1] = cmul<T>(r1[i][k1], w);
     }
 #pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) buf[(k1 * B + n2) * SPW + s] = r1[i][k1];
+    for (int k1 = 0; k1 < A; ++k1) buf[SS::at(k1 * B + n2, s)] = r1[i][k1];
   }
   __syncthreads();
   cplx<T> r2[J2][B];
@@ -365,7 +380,7 @@ __global__ __launch_bounds__(256) void k_sticks_inv_n(const cplx<T>* __restrict_
   for (int j = 0; j < J2; ++j) {
     const int k1 = t + TT * j;
 #pragma unroll
-    for (int n2 = 0; n2 < B; ++n2) r2[j][n2] = buf[(k1 * B + n2) * SPW + s];
+    for (int n2 = 0; n2 < B; ++n2) r2[j][n2] = buf[SS::at(k1 * B + n2, s)];
     SmallDft<T, B, +1>::run(r2[j]);
   }
   __syncthreads();
@@ -373,7 +388,7 @@ __global__ __launch_bounds__(256) void k_sticks_inv_n(const cplx<T>* __restrict_
   for (int j = 0; j < J2; ++j) {
     const int k1 = t + TT * j;
 #pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) buf[(k1 + A * k2) * SPW + s] = r2[j][k2];
+    for (int k2 = 0; k2 < B; ++k2) buf[SS::at(k1 + A * k2, s)] = r2[j][k2];
   }
   __syncthreads();
   // rows of SPW consecutive sticks per z
@@ -381,7 +396,7 @@ __global__ __launch_bounds__(256) void k_sticks_inv_n(const cplx<T>* __restrict_
   cplx<T>* sb = SB + (long)b * N * g.nst + s0;
   for (int i = tid; i < N * SPW; i += NT) {
     const int z = i / SPW, l = i - z * SPW;
-    if (l < ns) sb[(long)z * g.nst + l] = buf[i];
+    if (l < ns) sb[(long)z * g.nst + l] = buf[SS::at(z, l)];
   }
 }
 
@@ -403,7 +418,7 @@ __global__ __launch_bounds__(256) void k_sticks_fwd_n(const cplx<T>* __restrict_
   const cplx<T>* sb = SB + (long)b * N * g.nst + s0;
   for (int i = tid; i < N * SPW; i += NT) {
     const int z = i / SPW, l = i - z * SPW;
-    buf[i] = l < ns ? sb[(long)z * g.nst + l] : mk<T>(0, 0);
+    buf[SS::at(z, l)] = l < ns ? sb[(long)z * g.nst + l] : mk<T>(0, 0);
   }
   Stick sk{0, 0, 0, 0};
   if (act) sk = st[s0 + s];
@@ -412,7 +427,7 @@ __global__ __launch_bounds__(256) void k_sticks_fwd_n(const cplx<T>* __restrict_
 #pragma unroll
   for (int i = 0; i < I1; ++i)
 #pragma unroll
-    for (int n1 = 0; n1 < A; ++n1) r1[i][n1] = buf[(B * n1 + t + TT * i) * SPW + s];
+    for (int n1 = 0; n1 < A; ++n1) r1[i][n1] = buf[SS::at(B * n1 + t + TT * i, s)];
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < I1; ++i) {
@@ -421,7 +436,7 @@ __global__ __launch_bounds__(256) void k_sticks_fwd_n(const cplx<T>* __restrict_
 #pragma unroll
     for (int k1 = 1; k1 < A; ++k1) r1[i][k1] = cmul<T>(r1[i][k1], tw[(n2 * k1) % N]);
 #pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) buf[(k1 * B + n2) * SPW + s] = r1[i][k1];
+    for (int k1 = 0; k1 < A; ++k1) buf[SS::at(k1 * B + n2, s)] = r1[i][k1];
   }
   __syncthreads();
   if (!act) return;
@@ -432,7 +447,7 @@ __global__ __launch_bounds__(256) void k_sticks_fwd_n(const cplx<T>* __restrict_
     const int k1 = t + TT * j;
     cplx<T> r2[B];
 #pragma unroll
-    for (int n2 = 0; n2 < B; ++n2) r2[n2] = buf[(k1 * B + n2) * SPW + s];
+    for (int n2 = 0; n2 < B; ++n2) r2[n2] = buf[SS::at(k1 * B + n2, s)];
     SmallDft<T, B, -1>::run(r2);
 #pragma unroll
     for (int k2 = 0; k2 < B; ++k2) {
