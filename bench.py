@@ -252,6 +252,9 @@ def serving_leg(n, rate, slots, flags, degree):
         "throughput_req_s": n / (t1 - t0), "band_apps_per_sec": band_apps / (t1 - t0),
         "makespan_s": t1 - t0,
         "converged": int(sum(r["status"] == 0 for r in res)),
+        "not_converged": [{"cell": m["name"], "ecut_ha": float(m["cell"].ecut), "seed": int(m["seed"]),
+                           "status": int(r["status"]), "steps": int(r["steps"])}
+                          for r, m in zip(res, mix) if r["status"] != 0],
         "mean_steps": float(np.mean([r["steps"] for r in res])),
         "p50_latency_by_cell_s": {k: float(np.percentile(v, 50)) for k, v in sorted(by.items())},
         "mean_service_by_cell_s": {k: float(np.mean(v)) for k, v in sorted(svc.items())},
