@@ -19,6 +19,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -919,9 +920,13 @@ pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes
     return fail(nullptr, PW_EDEVICE, "stream or event creation failed");
   }
   if (h->plan.fl.fused) {
-    // allow large dynamic LDS for the fused plane kernel
-    pw_allow_large_lds();
-    pw_allow_large_lds_plane_n();
+    // allow large dynamic LDS for the fused plane kernels: once per process, so that no thread
+    // changes a kernel's attributes while another (request loop worker) launches it
+    static std::once_flag lds_once;
+    std::call_once(lds_once, [] {
+      pw_allow_large_lds();
+      pw_allow_large_lds_plane_n();
+    });
   }
   s = h->plan.prec == PW_FP64 ? Engine<double>(h).setup() : Engine<float>(h).setup();
   if (s != PW_OK) {

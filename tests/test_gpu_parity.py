@@ -226,7 +226,8 @@ def test_bf16_flags_need_mixed():
     assert ei.value.status == pw.PW_EINVAL
 
 
-@pytest.mark.parametrize("flags", [pw.PW_FLAG_BF16_GRAM, pw.PW_FLAG_BF16_ALL])
+@pytest.mark.parametrize("flags", [pw.PW_FLAG_BF16_GRAM, pw.PW_FLAG_BF16_KB | pw.PW_FLAG_BF16_ROT,
+                                   pw.PW_FLAG_BF16_ALL])
 def test_step_parity_si64_bf16(flags):
     cell = synth.make_cell("si64")
     model = O.model_from_cell(cell)
