@@ -136,6 +136,25 @@ def phase_table(stats, info, nb, m, steps, real_bytes, n1a, nterm, fp64=False):
     return phases, dom, roofline
 
 
+def occupied_angle(Xa, Xb, nocc, npw):
+    """Largest principal angle (radians) between the spans of the first nocc columns of two
+    blocks (rows of the (nb, ld) tensors), each orthonormal."""
+    import torch
+
+    A = Xa[:nocc, :npw].to(torch.complex128)
+    B = Xb[:nocc, :npw].to(torch.complex128).t().contiguous()
+    M = torch.mm(A.conj(), B)
+    s = torch.linalg.svdvals(M.cpu()).numpy()
+    return float(np.arccos(min(1.0, float(s.min()))))
+
+
+def device_info(torch, minfo):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "hbm_gib": round(p.total_memory / 2**30, 1),
+            "hip": torch.version.hip, "cus": p.multi_processor_count,
+            "arena_gib_mixed": round(minfo.footprint_bytes / 2**30, 2)}
+
+
 def run_steps(h, X, m, steps, bounds, b, keep_first=False):
     import torch
 
@@ -205,6 +224,15 @@ def cpu_baseline(cell, nb: int, m: int, sample_bands: int = 32):
     }
 
 
+def peak_in_flight(intervals):
+    ev = sorted([(a, 1) for a, _ in intervals] + [(d, -1) for _, d in intervals], key=lambda e: (e[0], e[1]))
+    cur = peak = 0
+    for _, dlt in ev:
+        cur += dlt
+        peak = max(peak, cur)
+    return peak
+
+
 def serving_leg(n, rate, slots, flags, degree):
     """Poisson stream of eigen-solves (mixed precision) through the request loop."""
     import threading
@@ -251,6 +279,7 @@ def serving_leg(n, rate, slots, flags, degree):
         "mean_queue_wait_s": float(wait.mean()),
         "throughput_req_s": n / (t1 - t0), "band_apps_per_sec": band_apps / (t1 - t0),
         "makespan_s": t1 - t0,
+        "peak_in_flight": peak_in_flight([(r["t_admit"], r["t_done"]) for r in res]),
         "converged": int(sum(r["status"] == 0 for r in res)),
         "not_converged": [{"cell": m["name"], "ecut_ha": float(m["cell"].ecut), "seed": int(m["seed"]),
                            "status": int(r["status"]), "steps": int(r["steps"])}
@@ -359,6 +388,24 @@ def main():
     value = 1000.0 / ms_step
     band_apps = (m + 1) * nb / (ms_step / 1000.0)
     log(f"mixed: {ms_step:.1f} ms/step, max resid(occ) {res[:cell.nocc].max():.2e}")
+    # H applications alone (N_b / pw_apply_h time), and the mixed block after one step from the
+    # snapshot (for the subspace angle against the FP64 form)
+    apply_rate = None
+    x1_mixed = None
+    if not big:
+        HX = torch.empty_like(X)
+        hm.apply_h(X, HX)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            hm.apply_h(X, HX)
+        torch.cuda.synchronize()
+        apply_rate = nb * reps / (time.perf_counter() - t0)
+        del HX
+        if snap is not None:
+            x1_mixed = snap.clone()
+            hm.eig_step(x1_mixed, m, bounds_m[0], bounds_m[1], b)
 
     # bf16 split terms executed per real product, by phase
     nterm = {}
@@ -398,10 +445,20 @@ def main():
             Xd[c0:c0 + chunk].copy_(snap[c0:c0 + chunk].to("cuda", non_blocking=False))
         del snap
         steps64 = 1 if big else args.fp64_steps
+        angle = None
         if not big:
-            # warm the FP64 handle (solver workspace) on a copy, untimed
+            # warm the FP64 handle (solver workspace) on a copy, untimed; this is also one FP64
+            # step from the snapshot, compared with the mixed one by principal angles
             Xw = Xd.clone()
-            hd.eig_step(Xw, m, bounds_m[0], bounds_m[1], b)
+            ew, _, _ = hd.eig_step(Xw, m, bounds_m[0], bounds_m[1], b)
+            if x1_mixed is not None:
+                # the occupied bands, extended to the end of the cluster (gaps < 1e-3 Ha) that
+                # holds the last of them, so that the span is well defined
+                n_eff = cell.nocc
+                while n_eff < nb and ew[n_eff] - ew[n_eff - 1] < 1e-3:
+                    n_eff += 1
+                angle = {"rad": occupied_angle(x1_mixed, Xw, n_eff, hd.npw), "bands": n_eff}
+                del x1_mixed
             del Xw
         # the largest cells take minutes per FP64 step: one step, timed per phase as it runs
         hd.reset_stats()
@@ -426,6 +483,7 @@ def main():
                 "roofline": roof64, "phases": ph64}
         nocc = cell.nocc
         accuracy = {"max_abs_deig_occ_mixed_vs_fp64_Ha": float(np.abs(eig_first[:nocc] - e64_first[:nocc]).max()),
+                    "max_principal_angle_occ": angle,
                     "bands_compared": nocc, "what": "first timed degree-%d step of each form, same block and bounds" % m}
         del hd, Xd
         torch.cuda.empty_cache()
@@ -462,6 +520,8 @@ def main():
                    "fft_grid": list(int(x) for x in pw.plan(cell, pw.PW_MIXED).fft_n), "precision": "mixed",
                    "mixed_flags": mflags},
         "band_apps_per_sec": band_apps,
+        "apply_h_band_apps_per_sec": apply_rate,
+        "device": device_info(torch, minfo),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64": fp64,
