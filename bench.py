@@ -391,6 +391,7 @@ def main():
     # H applications alone (N_b / pw_apply_h time), and the mixed block after one step from the
     # snapshot (for the subspace angle against the FP64 form)
     apply_rate = None
+    density = None
     x1_mixed = None
     if not big:
         HX = torch.empty_like(X)
@@ -403,6 +404,21 @@ def main():
         torch.cuda.synchronize()
         apply_rate = nb * reps / (time.perf_counter() - t0)
         del HX
+        # charge density of the block (doubly occupied lowest bands), timed alone
+        occ = np.where(np.arange(nb) < cell.nocc, 2.0, 0.0)
+        rho = hm.density(X, occ)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            hm.density(X, occ, rho)
+        torch.cuda.synchronize()
+        t_rho = (time.perf_counter() - t0) / reps
+        density = {"ms_per_call": round(1000.0 * t_rho, 3), "bands": nb, "band_per_sec": nb / t_rho,
+                   "x_read_gbs": nb * hm.npw * 8 / t_rho / 1e9,
+                   "electrons": float(rho.sum().item()) / float(np.prod(hm.info.fft_n)),
+                   "what": "rho(r) = sum_n f_n |psi_n(r)|^2 on the FFT grid, f = 2 for the lowest %d bands "
+                           "(electrons = sum_r rho / N_r for the unnormalised transform)" % cell.nocc}
+        del rho
         if snap is not None:
             x1_mixed = snap.clone()
             hm.eig_step(x1_mixed, m, bounds_m[0], bounds_m[1], b)
@@ -521,6 +537,7 @@ def main():
                    "mixed_flags": mflags},
         "band_apps_per_sec": band_apps,
         "apply_h_band_apps_per_sec": apply_rate,
+        "density": density,
         "device": device_info(torch, minfo),
         "roofline": roofline,
         "cpu_baseline": cpu,

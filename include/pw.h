@@ -157,6 +157,19 @@ pw_status pw_get_gvectors(const pw_handle *h, int *miller_host);
 pw_status pw_apply_h(pw_handle *h, const void *X_dev, void *HX_dev, int nb, int ld);
 
 /*
+ * Charge density of nb bands (1 <= nb <= nbands; X as for pw_apply_h), the quantity the SCF
+ * loop forms from the eigenfunctions (Section II-A): rho(r_j) = sum_n occ[n] |psi_n(r_j)|^2 at
+ * the FFT grid points r_j = (j1 L1/N1, j2 L2/N2, j3 L3/N3), psi_n(r) = sum_G X[G, n] exp(+i G.r)
+ * (unnormalised inverse transform, no volume factor; the caller scales).  occ_host: nb finite
+ * band weights on the host (e.g. 2 for each doubly occupied band), copied during the call.
+ * rho_dev: N1 N2 N3 doubles on the device, layout [j3][j2][j1] (j1 fastest), overwritten.
+ * Accumulated in FP64 over bands in index order (deterministic).  Uses the handle's work
+ * buffers; returns after rho is complete.  PW_EINVAL for bad sizes, null pointers or
+ * non-finite weights.
+ */
+pw_status pw_density(pw_handle *h, const void *X_dev, int nb, int ld, const double *occ_host, void *rho_dev);
+
+/*
  * One block-eigensolver step on X (in/out, nb columns, ld >= npw):
  *   Y = T_m((H - c)/e) X / T_m((a_lo - c)/e), e = (b - a)/2, c = (b + a)/2 (m = degree;
  *       three-term recurrence, one H application per degree);

@@ -253,6 +253,19 @@ def to_g_space(f: np.ndarray, miller: np.ndarray) -> np.ndarray:
     return gather_from_grid(F, miller)
 
 
+def density(X: np.ndarray, occ: np.ndarray, miller: np.ndarray, grid: Sequence[int]) -> np.ndarray:
+    """Charge density from the eigenfunctions (Section II-A, the SCF part): the weighted sum of
+    |psi_n(r_j)|^2 over the bands, psi_n the unnormalised inverse DFT of column n of X (npw x nb).
+    occ holds one weight per band (the paper sums |psi_j|^2 over its occupied index range; here
+    the caller states the weights, e.g. 2 for a doubly occupied band).  Grid shape (N1, N2, N3)."""
+    rho = np.zeros(tuple(grid))
+    for n in range(X.shape[1]):
+        if occ[n] != 0.0:
+            psi = to_real_space(X[:, n], miller, grid)
+            rho += occ[n] * (psi.real ** 2 + psi.imag ** 2)
+    return rho
+
+
 def build_model(L: Sequence[float], tau: np.ndarray, ecut: float, zval: float = 4.0,
                 rc: float = 1.0, gauss_c: float = 2.0, sigma: float = 0.8, d0: float = 1.5,
                 d1: float = -0.7, mode_miller: Optional[np.ndarray] = None,

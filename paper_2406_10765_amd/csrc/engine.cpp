@@ -390,6 +390,39 @@ struct Engine {
     return PW_OK;
   }
 
+  // rho(r) = sum_j occ_j |psi_j(r)|^2 on the FFT grid ([z][y][x], FP64), psi_j the unnormalised
+  // inverse transform of column j: sticks -> inverse plane (or pencil) pass writing |psi|^2 per band
+  // into u0, then a band-ordered weighted sum.  occ is on the device.
+  pw_status density(const cplx<T>* X, int nb, long ld, const double* occ, double* rho) {
+    const GridDesc& g = P.g;
+    const long nr = (long)g.n1 * g.n2 * g.n3;
+    cplx<T>* SB = h->at<cplx<T>>(P.lay.sb);
+    cplx<T>* G1 = h->at<cplx<T>>(P.lay.g1);
+    const Stick* st = h->at<Stick>(P.lay.sticks);
+    const int* cs = h->at<int>(P.lay.colstart);
+    const cplx<T>* tw1 = h->at<cplx<T>>(P.lay.tw1);
+    const cplx<T>* tw2 = h->at<cplx<T>>(P.lay.tw2);
+    const cplx<T>* tw3 = h->at<cplx<T>>(P.lay.tw3);
+    T* psq = h->at<T>(P.lay.u0);
+    // bands per pass: the stick batch, and as many |psi|^2 grids as u0 holds
+    const long u0_elems = 2L * P.ldw * P.nbb;
+    const int per = (int)std::min<long>(P.fft_batch, u0_elems / nr);
+    if (per < 1) return fail(h, PW_EINVAL, "density: the work buffer cannot hold one real-space grid");
+    for (int b0 = 0; b0 < nb; b0 += per) {
+      const int nbt = std::min(per, nb - b0);
+      PW_TIMED(PW_PH_STICKS_INV, launch_sticks_inv<T>(X + (long)b0 * ld, ld, SB, nbt, st, g, tw3, P.fl, h->stream));
+      if (P.fl.fused) {
+        PW_TIMED(PW_PH_PLANE, launch_plane_fused<T>(SB, (const T*)nullptr, nbt, st, g, tw1, tw2, (T)1, 2, psq, P.fl,
+                                                    h->stream));
+      } else {
+        PW_TIMED(PW_PH_PENCIL_YINV, launch_pencil_yinv<T>(SB, G1, nbt, st, cs, g, tw2, P.fl, h->stream));
+        PW_TIMED(PW_PH_PENCIL_X, launch_pencil_x<T>(G1, (const T*)nullptr, nbt, g, tw1, 2, psq, P.fl, h->stream));
+      }
+      PW_TIMED(PW_PH_OTHER, launch_density_acc<T>(psq, nbt, nr, occ + b0, rho, b0 == 0, h->stream));
+    }
+    return PW_OK;
+  }
+
   pw_status apply_h(const cplx<T>* X, cplx<T>* HX, int nb, int ld) {
     set_planes(nullptr, 0);
     for (int c0 = 0; c0 < nb; c0 += P.nbb) {
@@ -971,6 +1004,24 @@ pw_status pw_apply_h(pw_handle* h, const void* X, void* HX, int nb, int ld) {
   if (h->plan.prec == PW_FP64)
     return Engine<double>(h).apply_h(static_cast<const double2*>(X), static_cast<double2*>(HX), nb, ld);
   return Engine<float>(h).apply_h(static_cast<const float2*>(X), static_cast<float2*>(HX), nb, ld);
+}
+
+pw_status pw_density(pw_handle* h, const void* X, int nb, int ld, const double* occ_host, void* rho_dev) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  pw_status s = check_block(h, X, nb, ld);
+  if (s != PW_OK) return s;
+  if (!occ_host || !rho_dev) return fail(h, PW_EINVAL, "null occupations or output");
+  for (int i = 0; i < nb; ++i)
+    if (!std::isfinite(occ_host[i])) return fail(h, PW_EINVAL, "non-finite occupation");
+  double* occ = h->at<double>(h->plan.lay.occ);
+  if (hipMemcpyAsync(occ, occ_host, sizeof(double) * nb, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return fail(h, PW_EDEVICE, "occupation upload failed");
+  s = h->plan.prec == PW_FP64
+          ? Engine<double>(h).density(static_cast<const double2*>(X), nb, ld, occ, static_cast<double*>(rho_dev))
+          : Engine<float>(h).density(static_cast<const float2*>(X), nb, ld, occ, static_cast<double*>(rho_dev));
+  if (s != PW_OK) return s;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, PW_EDEVICE, "stream synchronise failed");
+  return PW_OK;
 }
 
 pw_status pw_eig_step(pw_handle* h, void* X, void* HX, int nb, int ld, const pw_step_params* p, double* eig,

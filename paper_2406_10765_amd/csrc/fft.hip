@@ -218,6 +218,7 @@ __global__ __launch_bounds__(256) void k_sticks_fwd(const cplx<T>* __restrict__ 
 // Stage 2, fused: one workgroup per (z plane, band); the whole N1 x N2 plane
 // sits in LDS, layout [y][x].  mode 0: inverse, * V, forward, gather * scale.
 // mode 1: inverse only, write the real part to vout[z][y][x] (potential setup).
+// mode 2: inverse only, write |psi|^2 to vout[band][z][y][x] (charge density).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(1024) void k_plane(cplx<T>* __restrict__ SB, const T* __restrict__ V, const Stick* __restrict__ st,
@@ -248,6 +249,11 @@ __global__ __launch_bounds__(1024) void k_plane(cplx<T>* __restrict__ SB, const 
   const long zoff = (long)z * np;
   if (mode == 1) {
     for (int i = tid; i < np; i += nthr) vout[zoff + i] = plane[i].x;
+    return;
+  }
+  if (mode == 2) {
+    T* vb = vout + (long)b * n3 * np + zoff;
+    for (int i = tid; i < np; i += nthr) vb[i] = plane[i].x * plane[i].x + plane[i].y * plane[i].y;
     return;
   }
   for (int i = tid; i < np; i += nthr) plane[i] = cscale<T>(plane[i], V[zoff + i]);
@@ -316,6 +322,11 @@ __global__ __launch_bounds__(256) void k_xrows(cplx<T>* __restrict__ G1, const T
   const long voff = ((long)z * n2 + y0) * n1;
   if (mode == 1) {
     for (int i = tid; i < ny * n1; i += nthr) vout[voff + i] = buf[i].x;
+    return;
+  }
+  if (mode == 2) {
+    T* vb = vout + (long)b * n3 * n2 * n1 + voff;
+    for (int i = tid; i < ny * n1; i += nthr) vb[i] = buf[i].x * buf[i].x + buf[i].y * buf[i].y;
     return;
   }
   for (int i = tid; i < ny * n1; i += nthr) buf[i] = cscale<T>(buf[i], V[voff + i]);

@@ -160,6 +160,10 @@ hipError_t launch_reduce_planes(const double2* part, int nsplit, int M, int N, c
                                 unsigned int* H, unsigned int* L, long ldp, hipStream_t s);
 
 // --------------------------------------------------------------- misc ------
+// Charge density: rho[r] = (first ? 0 : rho[r]) + sum_b occ[b] psq[b * nr + r], bands in order.
+template <typename T>
+hipError_t launch_density_acc(const T* psq, int nbt, long nr, const double* occ, double* rho, bool first,
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_fill_zero(cplx<T>* p, long n, hipStream_t s);
 

@@ -415,6 +415,28 @@ hipError_t launch_scale_cols_lam(const double2* in, long ldi, cplx<T>* out, long
   return hipGetLastError();
 }
 
+// rho[r] (+)= sum over the nbt bands of occ[b] psq[b][r], bands in order (deterministic)
+template <typename T>
+__global__ void k_density_acc(const T* __restrict__ psq, int nbt, long nr, const double* __restrict__ occ,
+                              double* __restrict__ rho, int first) {
+  PW_GRID_STRIDE(r, nr) {
+    double acc = first ? 0.0 : rho[r];
+    for (int b = 0; b < nbt; ++b) acc += occ[b] * (double)psq[(long)b * nr + r];
+    rho[r] = acc;
+  }
+}
+
+template <typename T>
+hipError_t launch_density_acc(const T* psq, int nbt, long nr, const double* occ, double* rho, bool first,
+                              hipStream_t s) {
+  if (nr <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_density_acc<T>, dim3(stride_blocks(nr)), dim3(256), 0, s, psq, nbt, nr, occ, rho,
+                     first ? 1 : 0);
+  return hipGetLastError();
+}
+template hipError_t launch_density_acc<float>(const float*, int, long, const double*, double*, bool, hipStream_t);
+template hipError_t launch_density_acc<double>(const double*, int, long, const double*, double*, bool, hipStream_t);
+
 hipError_t launch_hermitize(double2* A, long lda, int n, hipStream_t s) {
   const long m = (long)n * n;
   if (m <= 0) return hipSuccess;

@@ -286,6 +286,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   L.info = take(sizeof(int) * 4);
   L.scal = take(sizeof(double) * 8);
   L.lanc = take(cb * P.ldw * 3);
+  L.occ = take(sizeof(double) * nb);  // band weights of the charge density
   L.total = off;
   return PW_OK;
 }

@@ -15,7 +15,8 @@ constexpr size_t kDefaultMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 struct ArenaLayout {
   size_t miller, sticks, colstart, kin, tw1, tw2, tw3, vr, frac, mmil, mamp, mpha, vg, dscale;
-  size_t beta, brad, bph, yp, u0, u1, zb, wf, sb, g1, pt, parts, sh, ct, ct2, eig, ework, resid, info, scal, lanc;
+  size_t beta, brad, bph, yp, u0, u1, zb, wf, sb, g1, pt, parts, sh, ct, ct2, eig, ework, resid, info, scal, lanc,
+      occ;
   size_t total;
 };
 

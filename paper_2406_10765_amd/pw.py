@@ -135,6 +135,7 @@ def lib() -> ctypes.CDLL:
         "pw_query": ([vp, P(Info)]),
         "pw_get_gvectors": ([vp, P(ctypes.c_int)]),
         "pw_apply_h": ([vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "pw_density": ([vp, vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_double), vp]),
         "pw_eig_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, P(StepParams), P(ctypes.c_double),
                          P(ctypes.c_double), P(ctypes.c_double)]),
         "pw_spectrum_bound": ([vp, ctypes.c_int, ctypes.c_ulonglong, P(ctypes.c_double)]),
@@ -296,6 +297,23 @@ class Handle:
         _check(lib().pw_apply_h(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(HX.data_ptr()), nb, ld),
                self._h)
         return HX
+
+    def density(self, X, occ, rho=None):
+        """rho(r) = sum_n occ[n] |psi_n(r)|^2 on the FFT grid: float64 device tensor (N3, N2, N1)."""
+        nb, ld = self._check_block(X)
+        w = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
+        if w.shape != (nb,):
+            raise ValueError("occ must hold one weight per band")
+        n1, n2, n3 = (int(v) for v in self.info.fft_n)
+        if rho is None:
+            rho = self._torch.empty((n3, n2, n1), dtype=self._torch.float64, device=self.device)
+        if rho.dtype != self._torch.float64 or rho.device != self.device or not rho.is_contiguous() \
+                or rho.numel() != n1 * n2 * n3:
+            raise ValueError("rho must be a contiguous float64 device tensor of N1 N2 N3 entries")
+        _check(lib().pw_density(self._h, ctypes.c_void_p(X.data_ptr()), nb, ld,
+                                w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_void_p(rho.data_ptr())),
+               self._h)
+        return rho
 
     def eig_step(self, X, degree: int, a_lo: float = float("nan"), a: float = float("nan"),
                  b: float = float("nan"), HX=None):

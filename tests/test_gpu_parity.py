@@ -344,3 +344,44 @@ def test_blocked_step_generated_projectors_si64(prec, etol):
     if prec == pw.PW_FP64:
         assert np.abs(r2 - s2.resid).max() < 1e-9
     h.close()
+
+
+# --- charge density (pw_density) --------------------------------------------------------------
+# Tolerances relative to max rho: FP64 1e-12 (double FFTs of length <= 128, sums over <= 40
+# bands); mixed 1e-5 (fp32 transforms: unit roundoff times the log2 N depth, squared magnitude).
+@pytest.mark.parametrize("name,prec,flags,nb,tol", [
+    ("si8", pw.PW_FP64, 0, 20, 1e-12),
+    ("si8", pw.PW_MIXED, 0, 20, 1e-5),
+    ("si8", pw.PW_MIXED, pw.PW_FLAG_PENCIL_FFT, 9, 1e-5),
+    ("si64", pw.PW_FP64, pw.PW_FLAG_PENCIL_FFT, 13, 1e-12),
+    ("si64", pw.PW_MIXED, 0, 37, 1e-5),
+])
+def test_density_matches_oracle(name, prec, flags, nb, tol):
+    cell = synth.make_cell(name, modes=True)
+    model = O.model_from_cell(cell)
+    h = pw.Handle(cell, prec, nbands=max(nb, cell.nbands), flags=flags)
+    p = to_gpu_order(h, model)
+    X = synth.random_block(model.npw, nb, 700 + nb)
+    if prec == pw.PW_MIXED:
+        X = X.astype(np.complex64).astype(np.complex128)
+    occ = np.where(np.arange(nb) % 5 == 4, 0.0, 2.0) - 0.01 * np.arange(nb)
+    say("density", name, prec, flags, nb, "grid", tuple(h.info.fft_n))
+    ref = O.density(X, occ, model.miller, model.grid).transpose(2, 1, 0)
+    rho = h.density(h.to_device(X[p]), occ).cpu().numpy()
+    err = float(np.abs(rho - ref).max() / np.abs(ref).max())
+    say("  rel err", err)
+    assert err < tol
+    # bands enter in index order and one at a time: a single band alone is its own density
+    one = h.density(h.to_device(X[p][:, :1]), occ[:1]).cpu().numpy()
+    ref1 = O.density(X[:, :1], occ[:1], model.miller, model.grid).transpose(2, 1, 0)
+    assert float(np.abs(one - ref1).max() / np.abs(ref1).max()) < tol
+
+
+def test_density_argument_errors():
+    cell = synth.make_cell("si8")
+    h = pw.Handle(cell, pw.PW_MIXED)
+    X = h.to_device(synth.random_block(h.npw, 4, 3))
+    with pytest.raises(Exception):
+        h.density(X, np.array([1.0, 1.0, 1.0]))  # one weight short
+    with pytest.raises(Exception):
+        h.density(X, np.array([1.0, np.nan, 1.0, 1.0]))

@@ -356,3 +356,57 @@ def test_atomwise_nonlocal_equals_matrix_form(si8):
     a = O.apply_h(model, X)
     b = O.apply_h(lite, X)
     assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+
+
+# --- charge density -----------------------------------------------------------------------
+def _grid_points(L, grid, idx):
+    """Cartesian r_j = (j1 L1/N1, j2 L2/N2, j3 L3/N3) for integer index triples."""
+    idx = np.asarray(idx, float)
+    return idx * (np.asarray(L, float) / np.asarray(grid, float))
+
+
+def test_density_parseval(si8):
+    """sum_r rho(r) = N_r sum_n f_n sum_G |c_nG|^2 for the unnormalised inverse transform."""
+    cell, model = si8[0], si8[1]
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((model.npw, 5)) + 1j * rng.standard_normal((model.npw, 5))
+    occ = np.array([2.0, 2.0, 1.0, 0.5, 0.0])
+    rho = O.density(X, occ, model.miller, model.grid)
+    nr = float(np.prod(model.grid))
+    want = nr * float(np.sum(occ * np.sum(np.abs(X) ** 2, axis=0)))
+    assert abs(rho.sum() - want) <= 1e-12 * want
+    assert rho.min() >= 0.0
+
+
+def test_density_two_plane_waves_closed_form(si8):
+    """Two plane waves a e^{iG1.r} + b e^{iG2.r}: |psi|^2 = |a|^2 + |b|^2 + 2 Re(a b* e^{i(G1-G2).r}),
+    evaluated from the formula at every grid point (pins axis order and the transform sign)."""
+    cell, model = si8[0], si8[1]
+    m = model.miller
+    i1 = int(np.flatnonzero((m == [1, 2, -1]).all(axis=1))[0])
+    i2 = int(np.flatnonzero((m == [-2, 0, 1]).all(axis=1))[0])
+    a, b = 0.7 - 0.2j, -0.3 + 0.9j
+    X = np.zeros((model.npw, 1), complex)
+    X[i1, 0], X[i2, 0] = a, b
+    rho = O.density(X, np.array([1.0]), m, model.grid)
+    N = model.grid
+    j = np.stack(np.meshgrid(*[np.arange(n) for n in N], indexing="ij"), axis=-1).reshape(-1, 3)
+    r = _grid_points(model.L, N, j)
+    dG = 2 * np.pi * (np.array([1, 2, -1]) - np.array([-2, 0, 1])) / np.asarray(model.L, float)
+    want = abs(a) ** 2 + abs(b) ** 2 + 2 * np.real(a * np.conj(b) * np.exp(1j * r @ dG))
+    assert np.abs(rho.reshape(-1) - want).max() < 1e-12
+
+
+def test_density_direct_sum_at_points(si8):
+    """rho at a few grid points equals the weighted |sum_G c_G e^{iG.r}|^2 summed by brute force."""
+    cell, model = si8[0], si8[1]
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((model.npw, 3)) + 1j * rng.standard_normal((model.npw, 3))
+    occ = np.array([2.0, 1.0, 0.5])
+    rho = O.density(X, occ, model.miller, model.grid)
+    G = 2 * np.pi * model.miller / np.asarray(model.L, float)
+    for idx in [(0, 0, 0), (3, 5, 7), (model.grid[0] - 1, 1, model.grid[2] // 2)]:
+        r = _grid_points(model.L, model.grid, idx)
+        psi = np.exp(1j * (G @ r)) @ X
+        want = float(np.sum(occ * np.abs(psi) ** 2))
+        assert abs(rho[idx] - want) < 1e-10 * want
