@@ -313,7 +313,7 @@ def main():
                     help="set up the workload, run one degree-m filter step and exit (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

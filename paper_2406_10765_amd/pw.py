@@ -124,7 +124,7 @@ def lib() -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: run paper_2406_10765_amd/build.py (or __graft_entry__.build())")
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2406_10765_amd/build.py")
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp = ctypes.c_void_p
