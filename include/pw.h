@@ -57,7 +57,8 @@ typedef enum {
 #define PW_FLAG_PENCIL_FFT 1u
 /* PW_MIXED only: form the products with fp32 data split into two bf16 terms each
    (hi*hi' + hi*lo' + lo*hi' on the bf16 matrix cores, fp32 accumulation; the Gram/projected
-   products also add lo*lo' and move their partial sums to fp64 every 256 plane waves):
+   products also add lo*lo'; the long sums over plane waves move their fp32 partial sums to
+   fp64 every 4096 plane waves):
    GRAM = [S | H_s] = Y^H [Y | W];  KB = projector products beta^H Y and beta (D P);
    ROT = rotations Y C and W C. */
 #define PW_FLAG_BF16_GRAM 2u
@@ -69,6 +70,9 @@ typedef enum {
    O(N_pw N_atoms).  For cells whose table does not fit (Si4096 in FP64: 219 GB).
    Not combinable with PW_FLAG_BF16_KB. */
 #define PW_FLAG_BETA_OTF 16u
+/* Plan the buffers of pw_lobpcg_step (the three-block basis and its Gram matrix); unblocked
+   plans only (PW_EINVAL when the bands would be filtered in blocks). */
+#define PW_FLAG_LOBPCG 32u
 
 typedef enum {
   PW_FP64 = 0,  /* every product and FFT in double precision */
@@ -168,6 +172,24 @@ pw_status pw_apply_h(pw_handle *h, const void *X_dev, void *HX_dev, int nb, int 
  * non-finite weights.
  */
 pw_status pw_density(pw_handle *h, const void *X_dev, int nb, int ld, const double *occ_host, void *rho_dev);
+
+/*
+ * One LOBPCG step (locally optimal block preconditioned conjugate gradient, one of the inner
+ * eigensolvers the paper names in Section II-A) on X (in/out, nb columns) with search
+ * directions P (in/out, nb columns, same ld; its input is ignored when have_p == 0):
+ *   W = H X, theta_i = Re(x_i^H w_i) / (x_i^H x_i),
+ *   R = T (W - X diag(theta)), T = diag(1 / (1 + |G|^2/2)) (diagonal preconditioner),
+ *   the columns of R and P scaled to unit norm,
+ *   Rayleigh-Ritz of H on Z = [X R P] (or [X R]): [S | H_s] = Z^H [Z | HZ] and the FP64
+ *   generalised eigensolve H_s C = S C Lambda of size 3 nb (2 nb),
+ *   X' = Z C_1 (C_1: the nb lowest Ritz vectors), P' = [R P] times the R and P rows of C_1.
+ * eig (host, nb): the nb lowest Ritz values; resid (host, nb): ||w_i - theta_i x_i|| of the
+ * input block.  Three H applications per step (X, R, P).  Needs a handle planned with
+ * PW_FLAG_LOBPCG (PW_EINVAL otherwise); PW_ENOTPD when the basis Gram matrix is not positive
+ * definite (restart with have_p = 0).  Synchronises before returning.
+ */
+pw_status pw_lobpcg_step(pw_handle *h, void *X_dev, void *P_dev, int nb, int ld, int have_p, double *eig,
+                         double *resid);
 
 /*
  * One block-eigensolver step on X (in/out, nb columns, ld >= npw):

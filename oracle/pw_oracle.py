@@ -439,6 +439,43 @@ def eig_step(hop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, m: int, a_l
     return StepResult(eig=lam, X=Xn, HX=Wn, resid=resid, a_lo=float(lam[0]), a=float(lam[-1]))
 
 
+@dataclasses.dataclass
+class LobpcgResult:
+    X: np.ndarray  # the nb lowest Ritz vectors
+    P: np.ndarray  # their components along [R, P] (the next search directions)
+    eig: np.ndarray  # the nb lowest Ritz values
+    resid: np.ndarray  # ||H x_i - theta_i x_i|| of the input block
+
+
+def lobpcg_step(hop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, P: Optional[np.ndarray],
+                kin: np.ndarray) -> LobpcgResult:
+    """One step of the locally optimal block preconditioned conjugate gradient method, one of
+    the inner eigensolvers of Section II-A (Knyazev's block form).  The Rayleigh quotients of the
+    columns of X give the residuals W - X theta; the diagonal preconditioner 1 / (1 + |G|^2/2)
+    acts on them; R and P are scaled to unit columns; Rayleigh-Ritz of H on span[X, R, P] (or
+    span[X, R] without P) keeps the nb lowest Ritz pairs; the new P is the part of the new X
+    along [R, P]."""
+    nb = X.shape[1]
+    W = hop(X)
+    theta = np.real(np.sum(X.conj() * W, axis=0)) / np.real(np.sum(X.conj() * X, axis=0))
+    Rraw = W - X * theta
+    resid = np.linalg.norm(Rraw, axis=0)
+    R = Rraw / (1.0 + kin)[:, None]
+    R = R / np.linalg.norm(R, axis=0)
+    blocks = [X, R]
+    if P is not None:
+        blocks.append(P / np.linalg.norm(P, axis=0))
+    Z = np.hstack(blocks)
+    HZ = hop(Z)
+    S = Z.conj().T @ Z
+    Hs = Z.conj().T @ HZ
+    S = 0.5 * (S + S.conj().T)
+    Hs = 0.5 * (Hs + Hs.conj().T)
+    lam, C = scipy.linalg.eigh(Hs, S)
+    C1 = C[:, :nb]
+    return LobpcgResult(X=Z @ C1, P=Z[:, nb:] @ C1[nb:], eig=lam[:nb], resid=resid)
+
+
 def lanczos_max(hop: Callable[[np.ndarray], np.ndarray], npw: int, steps: int = 20,
                 seed: int = 7) -> float:
     """Largest Ritz value of a `steps`-step Lanczos run from a seeded random vector."""

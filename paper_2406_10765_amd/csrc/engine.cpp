@@ -592,10 +592,18 @@ struct Engine {
     else
       PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
                               parts, 4));
+    return dense_solve(nb, P.nsplit_gram);
+  }
+
+  // Sum the split-K partials of [S | H_s] (n x 2n), take Hermitian parts, and solve
+  // H_s C = S C diag(lambda), C^H S C = I in FP64 (C in the H_s storage, lambda ascending).
+  pw_status dense_solve(int nb, int nsplit) {
+    double2* parts = h->at<double2>(P.lay.parts);
+    double2* SH = h->at<double2>(P.lay.sh);
     double2* S = SH;
     double2* Hs = SH + (size_t)nb * nb;
     h->tbegin();
-    PW_HIP(launch_reduce_parts<T>(parts, P.nsplit_gram, nb, 2 * nb, nullptr, 0, SH, nb, (cplx<T>*)nullptr, 0,
+    PW_HIP(launch_reduce_parts<T>(parts, nsplit, nb, 2 * nb, nullptr, 0, SH, nb, (cplx<T>*)nullptr, 0,
                                   h->stream));
     PW_HIP(launch_hermitize(S, nb, nb, h->stream));
     PW_HIP(launch_hermitize(Hs, nb, nb, h->stream));
@@ -616,6 +624,62 @@ struct Engine {
     PW_HIP(hipStreamSynchronize(h->stream));
     if (info > nb) return fail(h, PW_ENOTPD, "Cholesky of the Gram matrix failed (rank-deficient block)");
     if (info > 0) return fail(h, PW_ENUMERIC, "dense eigensolver did not converge");
+    return PW_OK;
+  }
+
+  // One LOBPCG step (the C ABI's pw_lobpcg_step): Z = [X R P], HZ = [HX HR HP] in the arena,
+  // Rayleigh-Ritz on span Z, X' = Z C_1 into X, P' = [R P] C_1(R and P rows) into Pd.
+  pw_status lobpcg_step(cplx<T>* X, cplx<T>* Pd, int nb, long ld, bool have_p, double* eig_host,
+                        double* resid_host) {
+    set_planes(nullptr, 0);
+    const long ldw = P.ldw;
+    const int k = (have_p ? 3 : 2) * nb;
+    cplx<T>* Z = h->at<cplx<T>>(P.lay.lz);
+    cplx<T>* HZ = Z + (size_t)3 * P.nbands * ldw;
+    double* theta = h->at<double>(P.lay.eig);  // Rayleigh quotients of X (before the eigensolve)
+    double* resid_d = h->at<double>(P.lay.resid);
+    double* nrm = h->at<double>(P.lay.ework);
+    const T* kin = h->at<T>(P.lay.kin);
+    // X and W = H X
+    PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(X, ld, Z, ldw, P.npw, nb, h->stream));
+    pw_status s = hop(Z, ldw, nb, HZ, ldw, HZ, ldw, 1.0, 0.0, 0.0, nullptr, 0);
+    if (s != PW_OK) return s;
+    // theta, residual norms of X, preconditioned residuals R (unit columns) and H R
+    cplx<T>* R = Z + (size_t)nb * ldw;
+    PW_TIMED(PW_PH_OTHER, launch_rayleigh<T>(HZ, ldw, Z, ldw, P.npw, nb, theta, h->stream));
+    PW_TIMED(PW_PH_RESID, launch_resid<T>(HZ, ldw, Z, ldw, theta, P.npw, nb, resid_d, h->stream));
+    PW_HIP(hipMemcpyAsync(resid_host, resid_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
+    PW_TIMED(PW_PH_OTHER, launch_precond_resid<T>(HZ, ldw, Z, ldw, theta, kin, P.npw, nb, R, ldw, h->stream));
+    PW_TIMED(PW_PH_OTHER, launch_resid<T>(R, ldw, R, ldw, (const double*)nullptr, P.npw, nb, nrm, h->stream));
+    PW_TIMED(PW_PH_OTHER, launch_scale_cols_inv<T>(R, ldw, P.npw, nb, nrm, h->stream));
+    s = hop(R, ldw, nb, HZ + (size_t)nb * ldw, ldw, HZ + (size_t)nb * ldw, ldw, 1.0, 0.0, 0.0, nullptr, 0);
+    if (s != PW_OK) return s;
+    if (have_p) {
+      cplx<T>* Pz = Z + (size_t)2 * nb * ldw;
+      PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(Pd, ld, Pz, ldw, P.npw, nb, h->stream));
+      PW_TIMED(PW_PH_OTHER, launch_resid<T>(Pz, ldw, Pz, ldw, (const double*)nullptr, P.npw, nb, nrm, h->stream));
+      PW_TIMED(PW_PH_OTHER, launch_scale_cols_inv<T>(Pz, ldw, P.npw, nb, nrm, h->stream));
+      s = hop(Pz, ldw, nb, HZ + (size_t)2 * nb * ldw, ldw, HZ + (size_t)2 * nb * ldw, ldw, 1.0, 0.0, 0.0, nullptr, 0);
+      if (s != PW_OK) return s;
+    }
+    // Rayleigh-Ritz on span Z
+    double2* parts = h->at<double2>(P.lay.parts);
+    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Z, ldw, Z, ldw, HZ, ldw, k, k, 2 * k, P.npw, P.nsplit_lob,
+                            parts, 4));
+    s = dense_solve(k, P.nsplit_lob);
+    if (s != PW_OK) return s;
+    const cplx<T>* C = coeffs(k);
+    EpiH e;
+    std::memset(&e, 0, sizeof(e));
+    e.mode = 0;
+    PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), Z, ldw, C, k, P.npw, nb, k, X, ld, e));
+    PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), R, ldw, C + nb, k, P.npw, nb, k - nb, Pd, ld, e));
+    PW_HIP(hipMemcpyAsync(eig_host, h->at<double>(P.lay.eig), sizeof(double) * nb, hipMemcpyDeviceToHost,
+                          h->stream));
+    PW_HIP(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < nb; ++i)
+      if (!std::isfinite(eig_host[i]) || !std::isfinite(resid_host[i]))
+        return fail(h, PW_ENUMERIC, "non-finite Ritz value or residual");
     return PW_OK;
   }
 
@@ -1022,6 +1086,24 @@ pw_status pw_density(pw_handle* h, const void* X, int nb, int ld, const double* 
   if (s != PW_OK) return s;
   if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, PW_EDEVICE, "stream synchronise failed");
   return PW_OK;
+}
+
+pw_status pw_lobpcg_step(pw_handle* h, void* X, void* Pd, int nb, int ld, int have_p, double* eig, double* resid) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  pw_status s = check_block(h, X, nb, ld);
+  if (s != PW_OK) return s;
+  if (!Pd || !eig || !resid) return fail(h, PW_EINVAL, "null directions or output");
+  if (!(h->plan.flags & PW_FLAG_LOBPCG)) return fail(h, PW_EINVAL, "handle not planned with PW_FLAG_LOBPCG");
+  const size_t cb = 2 * (size_t)h->plan.real_bytes;
+  const char* x0 = static_cast<const char*>(X);
+  const char* p0 = static_cast<const char*>(Pd);
+  const size_t span = ((size_t)(nb - 1) * ld + h->plan.npw) * cb;
+  if (x0 < p0 + span && p0 < x0 + span) return fail(h, PW_EINVAL, "X and P overlap");
+  if (h->plan.prec == PW_FP64)
+    return Engine<double>(h).lobpcg_step(static_cast<double2*>(X), static_cast<double2*>(Pd), nb, ld, have_p != 0,
+                                         eig, resid);
+  return Engine<float>(h).lobpcg_step(static_cast<float2*>(X), static_cast<float2*>(Pd), nb, ld, have_p != 0, eig,
+                                      resid);
 }
 
 pw_status pw_eig_step(pw_handle* h, void* X, void* HX, int nb, int ld, const pw_step_params* p, double* eig,

@@ -160,6 +160,14 @@ hipError_t launch_reduce_planes(const double2* part, int nsplit, int M, int N, c
                                 unsigned int* H, unsigned int* L, long ldp, hipStream_t s);
 
 // --------------------------------------------------------------- misc ------
+// LOBPCG pieces: per-column Rayleigh quotients theta_j = Re(x_j^H w_j) / |x_j|^2 (FP64), and the
+// preconditioned residual block R = (W - X diag(theta)) / (1 + kin) (rows: plane waves).
+template <typename T>
+hipError_t launch_rayleigh(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, int rows, int cols, double* theta,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_precond_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, const double* theta,
+                                const T* kin, int rows, int cols, cplx<T>* R, long ldr, hipStream_t s);
 // Charge density: rho[r] = (first ? 0 : rho[r]) + sum_b occ[b] psq[b * nr + r], bands in order.
 template <typename T>
 hipError_t launch_density_acc(const T* psq, int nbt, long nr, const double* occ, double* rho, bool first,

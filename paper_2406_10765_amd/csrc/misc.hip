@@ -415,6 +415,77 @@ hipError_t launch_scale_cols_lam(const double2* in, long ldi, cplx<T>* out, long
   return hipGetLastError();
 }
 
+// theta[j] = Re(x_j^H w_j) / (x_j^H x_j) per column (FP64 accumulation), one block per column
+template <typename T>
+__global__ __launch_bounds__(256) void k_rayleigh(const cplx<T>* __restrict__ W, long ldw, const cplx<T>* __restrict__ X,
+                                                  long ldx, int rows, double* __restrict__ theta) {
+  __shared__ double red[2][4];
+  const int j = blockIdx.x;
+  const cplx<T>* w = W + (long)j * ldw;
+  const cplx<T>* x = X + (long)j * ldx;
+  double d = 0.0, n = 0.0;
+  for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+    const cplx<T> a = w[i], b = x[i];
+    d += (double)b.x * a.x + (double)b.y * a.y;
+    n += (double)b.x * b.x + (double)b.y * b.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    d += __shfl_down(d, off, 64);
+    n += __shfl_down(n, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = d;
+    red[1][threadIdx.x >> 6] = n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double td = 0.0, tn = 0.0;
+    for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) {
+      td += red[0][w2];
+      tn += red[1][w2];
+    }
+    theta[j] = td / tn;
+  }
+}
+
+template <typename T>
+hipError_t launch_rayleigh(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, int rows, int cols, double* theta,
+                           hipStream_t s) {
+  if (cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rayleigh<T>, dim3(cols), dim3(256), 0, s, W, ldw, X, ldx, rows, theta);
+  return hipGetLastError();
+}
+
+// R[g, j] = (W[g, j] - theta_j X[g, j]) / (1 + kin[g]): preconditioned residual block
+template <typename T>
+__global__ void k_precond_resid(const cplx<T>* __restrict__ W, long ldw, const cplx<T>* __restrict__ X, long ldx,
+                                const double* __restrict__ theta, const T* __restrict__ kin, int rows, int cols,
+                                cplx<T>* __restrict__ R, long ldr) {
+  PW_GRID_STRIDE(idx, (long)rows * cols) {
+    const int j = (int)(idx / rows), g = (int)(idx - (long)j * rows);
+    const double t = theta[j], p = 1.0 / (1.0 + (double)kin[g]);
+    const cplx<T> w = W[(long)j * ldw + g], x = X[(long)j * ldx + g];
+    R[(long)j * ldr + g] = mk<T>((T)(((double)w.x - t * x.x) * p), (T)(((double)w.y - t * x.y) * p));
+  }
+}
+
+template <typename T>
+hipError_t launch_precond_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, const double* theta,
+                                const T* kin, int rows, int cols, cplx<T>* R, long ldr, hipStream_t s) {
+  const long n = (long)rows * cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_precond_resid<T>, dim3(stride_blocks(n)), dim3(256), 0, s, W, ldw, X, ldx, theta, kin, rows,
+                     cols, R, ldr);
+  return hipGetLastError();
+}
+template hipError_t launch_rayleigh<float>(const float2*, long, const float2*, long, int, int, double*, hipStream_t);
+template hipError_t launch_rayleigh<double>(const double2*, long, const double2*, long, int, int, double*,
+                                            hipStream_t);
+template hipError_t launch_precond_resid<float>(const float2*, long, const float2*, long, const double*,
+                                                const float*, int, int, float2*, long, hipStream_t);
+template hipError_t launch_precond_resid<double>(const double2*, long, const double2*, long, const double*,
+                                                 const double*, int, int, double2*, long, hipStream_t);
+
 // rho[r] (+)= sum over the nbt bands of occ[b] psq[b][r], bands in order (deterministic)
 template <typename T>
 __global__ void k_density_acc(const T* __restrict__ psq, int nbt, long nr, const double* __restrict__ occ,

@@ -5,6 +5,7 @@
 // same sphere equals the textbook matrix element V(G - G') exactly.
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -52,7 +53,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   if (d->nbands < 1) { *err = "nbands must be >= 1"; return PW_EINVAL; }
   if (d->prec != PW_FP64 && d->prec != PW_MIXED) { *err = "unknown precision"; return PW_EINVAL; }
   const unsigned known =
-      PW_FLAG_PENCIL_FFT | PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT | PW_FLAG_BETA_OTF;
+      PW_FLAG_PENCIL_FFT | PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT | PW_FLAG_BETA_OTF | PW_FLAG_LOBPCG;
   if (d->flags & ~known) { *err = "unknown flag bits"; return PW_EINVAL; }
   if ((d->flags & PW_FLAG_BETA_OTF) && (d->flags & PW_FLAG_BF16_KB)) {
     *err = "PW_FLAG_BETA_OTF cannot be combined with PW_FLAG_BF16_KB";
@@ -231,6 +232,16 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
                              : bgr       ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands)
                                          : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
                              P.npw);
+  const bool lob = (P.flags & PW_FLAG_LOBPCG) != 0;
+  if (lob && P.nbb < P.nbands) {
+    *err = "PW_FLAG_LOBPCG needs every band in one block (the plan would filter in blocks)";
+    return PW_EINVAL;
+  }
+  P.nsplit_lob = lob ? pick_split(bgr ? gemm_cn_bf16_tiles(3 * P.nbands, 6 * P.nbands)
+                                      : gemm_cn_tiles(3 * P.nbands, 6 * P.nbands, f64),
+                                  P.npw)
+                     : 0;
+  const size_t kb = lob ? 3 * (size_t)P.nbands : (size_t)P.nbands;  // largest dense problem
 
   // --- arena layout --------------------------------------------------------------
   ArenaLayout& L = P.lay;
@@ -275,18 +286,21 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   L.pt = take(cb * std::max(1, P.nproj) * P.nbb);
   // bf16 hi/lo planes of the block entering the projector product (split-precision projectors)
   L.yp = take(8 * (size_t)P.ldw * P.yp_cols);
-  const size_t parts = std::max((size_t)P.nsplit_proj * P.nproj * P.nbb, (size_t)P.nsplit_gram * nb * 2 * nb);
+  const size_t parts = std::max({(size_t)P.nsplit_proj * P.nproj * P.nbb, (size_t)P.nsplit_gram * nb * 2 * nb,
+                                  (size_t)P.nsplit_lob * kb * 2 * kb});
   L.parts = take(16 * parts);
-  L.sh = take(16 * nb * 2 * nb);
-  L.ct = take(cb * nb * nb);
+  L.sh = take(16 * kb * 2 * kb);
+  L.ct = take(cb * kb * kb);
   L.ct2 = take(blocked ? cb * nb * nb : 0);
-  L.eig = take(sizeof(double) * nb);
-  L.ework = take(sizeof(double) * nb);
+  L.eig = take(sizeof(double) * kb);
+  L.ework = take(sizeof(double) * kb);
   L.resid = take(sizeof(double) * nb);
   L.info = take(sizeof(int) * 4);
   L.scal = take(sizeof(double) * 8);
   L.lanc = take(cb * P.ldw * 3);
   L.occ = take(sizeof(double) * nb);  // band weights of the charge density
+  // LOBPCG basis Z = [X R P] and HZ = [HX HR HP] (3 nbands columns each)
+  L.lz = take(lob ? 2 * cb * P.ldw * 3 * nb : 0);
   L.total = off;
   return PW_OK;
 }

@@ -16,7 +16,7 @@ constexpr size_t kDefaultMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 struct ArenaLayout {
   size_t miller, sticks, colstart, kin, tw1, tw2, tw3, vr, frac, mmil, mamp, mpha, vg, dscale;
   size_t beta, brad, bph, yp, u0, u1, zb, wf, sb, g1, pt, parts, sh, ct, ct2, eig, ework, resid, info, scal, lanc,
-      occ;
+      occ, lz;
   size_t total;
 };
 
@@ -48,6 +48,7 @@ struct Plan {
   int fft_batch;               // bands per FFT launch group
   int nbb;                     // bands per filter block (== nbands: unblocked step)
   int nsplit_proj, nsplit_gram;
+  int nsplit_lob;  // K splits of the LOBPCG basis Gram product (PW_FLAG_LOBPCG), else 0
   // bf16 plane columns held per plane: nbb, or 2 nbb when the unblocked step also keeps the
   // planes of H Y beside those of Y (split-precision projectors and Gram product)
   int yp_cols;

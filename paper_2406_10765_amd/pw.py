@@ -136,6 +136,8 @@ def lib() -> ctypes.CDLL:
         "pw_get_gvectors": ([vp, P(ctypes.c_int)]),
         "pw_apply_h": ([vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "pw_density": ([vp, vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_double), vp]),
+        "pw_lobpcg_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
+                            P(ctypes.c_double)]),
         "pw_eig_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, P(StepParams), P(ctypes.c_double),
                          P(ctypes.c_double), P(ctypes.c_double)]),
         "pw_spectrum_bound": ([vp, ctypes.c_int, ctypes.c_ulonglong, P(ctypes.c_double)]),
@@ -175,6 +177,7 @@ PW_FLAG_BF16_KB = 4
 PW_FLAG_BF16_ROT = 8
 PW_FLAG_BF16_ALL = PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT
 PW_FLAG_BETA_OTF = 16
+PW_FLAG_LOBPCG = 32
 
 
 def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,
@@ -314,6 +317,20 @@ class Handle:
                                 w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.c_void_p(rho.data_ptr())),
                self._h)
         return rho
+
+    def lobpcg_step(self, X, P, have_p: bool):
+        """One LOBPCG step on X and the directions P (both in place; P's input ignored when
+        not have_p).  Returns (Ritz values, residual norms of the input X) as numpy arrays."""
+        nb, ld = self._check_block(X)
+        nb2, ld2 = self._check_block(P)
+        if nb2 != nb or ld2 != ld:
+            raise ValueError("X and P must have the same shape and stride")
+        eig = np.empty(nb)
+        res = np.empty(nb)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().pw_lobpcg_step(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(P.data_ptr()), nb, ld,
+                                    1 if have_p else 0, eig.ctypes.data_as(dp), res.ctypes.data_as(dp)), self._h)
+        return eig, res
 
     def eig_step(self, X, degree: int, a_lo: float = float("nan"), a: float = float("nan"),
                  b: float = float("nan"), HX=None):

@@ -125,3 +125,12 @@ def test_generated_projector_plan():
     d, keep = _desc(si64, prec=pw.PW_MIXED, flags=pw.PW_FLAG_BETA_OTF | pw.PW_FLAG_BF16_KB)
     info = pw.Info()
     assert pw.lib().pw_plan(ctypes.byref(d), ctypes.byref(info)) == pw.PW_EINVAL
+
+
+def test_lobpcg_plan_needs_one_block():
+    cell = synth.make_cell("si64")
+    ok = pw.plan(cell, pw.PW_MIXED, flags=pw.PW_FLAG_LOBPCG)
+    base = pw.plan(cell, pw.PW_MIXED)
+    assert ok.footprint_bytes > base.footprint_bytes
+    with pytest.raises(Exception):
+        pw.plan(cell, pw.PW_MIXED, flags=pw.PW_FLAG_LOBPCG, filter_block=64)

@@ -385,3 +385,72 @@ def test_density_argument_errors():
         h.density(X, np.array([1.0, 1.0, 1.0]))  # one weight short
     with pytest.raises(Exception):
         h.density(X, np.array([1.0, np.nan, 1.0, 1.0]))
+
+
+# --- LOBPCG step (pw_lobpcg_step) -------------------------------------------------------------
+@pytest.mark.parametrize("name,prec,flags,nb,etol", [
+    ("si8", pw.PW_FP64, 0, 12, 1e-10),
+    ("si8", pw.PW_MIXED, 0, 12, 1e-5),
+    ("si64", pw.PW_MIXED, pw.PW_FLAG_BF16_ALL, 24, 1e-5),
+])
+def test_lobpcg_steps_match_oracle(name, prec, flags, nb, etol):
+    """Two steps (without, then with search directions) from the same orthonormal block."""
+    cell = synth.make_cell(name, modes=True)
+    model = O.model_from_cell(cell)
+    hop = lambda Y: O.apply_h(model, Y)
+    h = pw.Handle(cell, prec, nbands=nb, flags=flags | pw.PW_FLAG_LOBPCG)
+    p = to_gpu_order(h, model)
+    inv = np.argsort(p)
+    X0 = synth.random_block(model.npw, nb, 900 + nb)
+    X0, _ = np.linalg.qr(X0)
+    if prec == pw.PW_MIXED:
+        X0 = X0.astype(np.complex64).astype(np.complex128)
+    r1 = O.lobpcg_step(hop, X0, None, model.kin)
+    r2 = O.lobpcg_step(hop, r1.X, r1.P, model.kin)
+    Xd = h.to_device(X0[p])
+    Pd = h.empty_block(nb)
+    Pd.zero_()
+    e1, s1 = h.lobpcg_step(Xd, Pd, False)
+    e2, s2 = h.lobpcg_step(Xd, Pd, True)
+    say("lobpcg", name, prec, flags, "eig", np.abs(e1 - r1.eig).max(), np.abs(e2 - r2.eig).max(),
+        "resid", np.abs(s1 - r1.resid).max() / r1.resid.max(), np.abs(s2 - r2.resid).max() / r2.resid.max())
+    assert np.abs(e1 - r1.eig).max() < etol and np.abs(e2 - r2.eig).max() < etol
+    # residual norms: of the same input block at step 1; at step 2 of each side's own first
+    # iterate, which differ to first order in the compute precision
+    rtol1, rtol2 = (1e-9, 1e-9) if prec == pw.PW_FP64 else (1e-3, 1e-2)
+    assert np.abs(s1 - r1.resid).max() < rtol1 * r1.resid.max()
+    assert np.abs(s2 - r2.resid).max() < rtol2 * r2.resid.max()
+    if prec == pw.PW_FP64:
+        # the new block spans the oracle's (principal angles per eigenvalue cluster)
+        Xg = h.to_host(Xd)[inv]
+        for a, b in O.clusters(r2.eig):
+            if b == nb:
+                continue  # the top cluster may continue past the block
+            assert O.subspace_sin(r2.X[:, a:b], Xg[:, a:b]) < 1e-7
+
+
+def test_lobpcg_converges_to_dense_gpu(si8_dense):
+    cell, model, lam, V = si8_dense
+    nb = cell.nbands  # 20 bands for the 16 occupied ones
+    h = pw.Handle(cell, pw.PW_FP64, nbands=nb, flags=pw.PW_FLAG_LOBPCG)
+    X0, _ = np.linalg.qr(synth.random_block(model.npw, nb, 77))
+    p = to_gpu_order(h, model)
+    Xd = h.to_device(X0[p])
+    Pd = h.empty_block(nb)
+    have_p = False
+    for it in range(80):
+        eig, res = h.lobpcg_step(Xd, Pd, have_p)
+        have_p = True
+        if res[: cell.nocc].max() < 1e-8:
+            break
+    say("lobpcg gpu steps", it + 1, "max |de| occ", np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max())
+    assert np.abs(eig[: cell.nocc] - lam[: cell.nocc]).max() < 1e-8
+
+
+def test_lobpcg_needs_its_plan():
+    cell = synth.make_cell("si8")
+    h = pw.Handle(cell, pw.PW_FP64)
+    X = h.to_device(np.linalg.qr(synth.random_block(h.npw, 4, 1))[0])
+    P = h.empty_block(4)
+    with pytest.raises(Exception):
+        h.lobpcg_step(X, P, False)

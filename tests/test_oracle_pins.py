@@ -410,3 +410,39 @@ def test_density_direct_sum_at_points(si8):
         psi = np.exp(1j * (G @ r)) @ X
         want = float(np.sum(occ * np.abs(psi) ** 2))
         assert abs(rho[idx] - want) < 1e-10 * want
+
+
+# --- LOBPCG step ------------------------------------------------------------------------------
+def test_lobpcg_ritz_values_bounded(si8):
+    """Ritz values on span[X, R] lie above the exact eigenvalues (Courant-Fischer) and below the
+    Rayleigh-Ritz values of span X alone, which the larger space contains."""
+    cell, model, H, lam, V = si8
+    hop = lambda Y: H @ Y
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((model.npw, 6)) + 1j * rng.standard_normal((model.npw, 6))
+    X, _ = np.linalg.qr(X)
+    r = O.lobpcg_step(hop, X, None, model.kin)
+    rr = np.linalg.eigvalsh(X.conj().T @ H @ X)
+    assert np.all(r.eig >= lam[:6] - 1e-10)
+    assert np.all(r.eig <= rr + 1e-10)
+    assert np.abs(r.X.conj().T @ r.X - np.eye(6)).max() < 1e-10
+    # residual norms of the input block, from their definition
+    th = np.real(np.diag(X.conj().T @ H @ X))
+    assert np.allclose(r.resid, np.linalg.norm(H @ X - X * th, axis=0), rtol=1e-12)
+
+
+def test_lobpcg_converges_to_dense(si8):
+    """Repeated steps from a random orthonormal block reach the dense spectrum."""
+    cell, model, H, lam, V = si8
+    hop = lambda Y: H @ Y
+    nb = 10
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((model.npw, nb)) + 1j * rng.standard_normal((model.npw, nb))
+    X, _ = np.linalg.qr(X)
+    P = None
+    for _ in range(60):
+        r = O.lobpcg_step(hop, X, P, model.kin)
+        X, P = r.X, r.P
+        if r.resid[:8].max() < 1e-9:
+            break
+    assert np.abs(r.eig[:8] - lam[:8]).max() < 1e-8
