@@ -150,22 +150,38 @@ def occupied_angle(Xa, Xb, nocc, npw):
 
 def device_info(torch, minfo):
     p = torch.cuda.get_device_properties(0)
-    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "hbm_gib": round(p.total_memory / 2**30, 1),
-            "hip": torch.version.hip, "cus": p.multi_processor_count,
-            "arena_gib_mixed": round(minfo.footprint_bytes / 2**30, 2)}
+    out = {"name": p.name, "arch": getattr(p, "gcnArchName", None), "hbm_gib": round(p.total_memory / 2**30, 1),
+           "hip": torch.version.hip, "cus": p.multi_processor_count,
+           "arena_gib_mixed": round(minfo.footprint_bytes / 2**30, 2)}
+    try:  # current clocks as the SMI tool reports them (a child process; absent tools are skipped)
+        import subprocess
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        card = next(iter(json.loads(r.stdout).values()))
+        out["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception:
+        out["clocks"] = None
+    return out
 
 
-def run_steps(h, X, m, steps, bounds, b, keep_first=False):
+def run_steps(h, X, m, steps, bounds, b, keep_first=False, times=None):
+    """steps eig-steps on X; each returns after its host outputs are written, so the wall time
+    between returns is the step time (appended to times when given)."""
     import torch
 
     eig = res = first = None
+    t_prev = time.perf_counter()
     for i in range(steps):
         eig, res, bnd = h.eig_step(X, m, bounds[0], bounds[1], b)
+        if times is not None:
+            t_now = time.perf_counter()
+            times.append(t_now - t_prev)
+            t_prev = t_now
         bounds = (bnd[0], bnd[1])
         if i == 0:
             first = eig.copy()
         if steps > 1:
             log(f"  step {i + 1}/{steps} done")
+            t_prev = time.perf_counter()
     torch.cuda.synchronize()
     if keep_first:
         return eig, res, bounds, first
@@ -300,6 +316,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-lobpcg", action="store_true", help="skip the LOBPCG step timing")
     ap.add_argument("--flags", type=int, default=None,
                     help="mixed-precision product flags (bit 2: bf16 Gram, 4: bf16 projectors, 8: bf16 rotation)")
     ap.add_argument("--serving-requests", type=int, default=64,
@@ -374,7 +391,8 @@ def main():
     bounds_m = bounds
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    eig, res, bounds, eig_first = run_steps(hm, X, m, args.steps, bounds, b, keep_first=True)
+    step_times = []
+    eig, res, bounds, eig_first = run_steps(hm, X, m, args.steps, bounds, b, keep_first=True, times=step_times)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # phase times from further steps with per-launch events (the FFT part then runs on the
@@ -436,6 +454,40 @@ def main():
         roofline["traffic"] = measured_traffic(args.workload, mflags, dom)
         if roofline["traffic"] is not None:
             roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+
+    # ---- LOBPCG step on the same cell (three H applications and a 3 N_b Rayleigh-Ritz) ------
+    lobpcg = None
+    if not big and not args.no_lobpcg and snap is not None:
+        hl = pw.Handle(cell, pw.PW_MIXED, flags=mflags | pw.PW_FLAG_LOBPCG)
+        Xl = snap.clone()
+        Pl = hl.empty_block(nb)
+        hl.lobpcg_step(Xl, Pl, False)
+        # steps with search directions; when the three-block Gram matrix is numerically singular
+        # (PW_ENOTPD) the step is redone without them, as the entry point prescribes
+        times, sizes, restarts = [], [], 0
+        have_p = True
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                el, rl = hl.lobpcg_step(Xl, Pl, have_p)
+            except pw.PWError:
+                restarts += 1
+                have_p = False
+                continue
+            times.append(time.perf_counter() - t0)
+            sizes.append(3 * nb if have_p else 2 * nb)
+            have_p = True
+        if times:
+            lobpcg = {"ms_per_step": [round(1000.0 * t, 2) for t in times], "rayleigh_ritz_sizes": sizes,
+                      "restarts_without_directions": restarts,
+                      "h_applications_per_step": [3 if k == 3 * nb else 2 for k in sizes],
+                      "max_resid_occ_input": float(rl[: cell.nocc].max()),
+                      "what": "mixed-precision LOBPCG steps from the filter's starting block"}
+        del hl, Xl, Pl
+        torch.cuda.empty_cache()
+        if lobpcg:
+            log(f"lobpcg: ms/step {lobpcg['ms_per_step']}, Rayleigh-Ritz sizes {sizes}, restarts {restarts}")
 
     # ---- FP64 form from the same block and bounds -----------------------------------------
     fp64 = None
@@ -524,6 +576,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": round(1000.0 * float(np.median(step_times)), 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -538,6 +591,7 @@ def main():
         "band_apps_per_sec": band_apps,
         "apply_h_band_apps_per_sec": apply_rate,
         "density": density,
+        "lobpcg": lobpcg,
         "device": device_info(torch, minfo),
         "roofline": roofline,
         "cpu_baseline": cpu,
