@@ -184,12 +184,14 @@ pw_status pw_density(pw_handle *h, const void *X_dev, int nb, int ld, const doub
  *   generalised eigensolve H_s C = S C Lambda of size 3 nb (2 nb),
  *   X' = Z C_1 (C_1: the nb lowest Ritz vectors), P' = [R P] times the R and P rows of C_1.
  * eig (host, nb): the nb lowest Ritz values; resid (host, nb): ||w_i - theta_i x_i|| of the
- * input block.  Three H applications per step (X, R, P).  Needs a handle planned with
- * PW_FLAG_LOBPCG (PW_EINVAL otherwise); PW_ENOTPD when the basis Gram matrix is not positive
- * definite (restart with have_p = 0).  Synchronises before returning.
+ * input block.  Three H applications per step (X, R, P).  When the basis Gram matrix with P
+ * fails the Cholesky test (the directions have become numerically dependent), the step is redone
+ * on [X R] alone and *restarted (optional, may be NULL) is set to 1, else 0.  Needs a handle
+ * planned with PW_FLAG_LOBPCG (PW_EINVAL otherwise); PW_ENOTPD when even [X R] is dependent.
+ * Synchronises before returning.
  */
 pw_status pw_lobpcg_step(pw_handle *h, void *X_dev, void *P_dev, int nb, int ld, int have_p, double *eig,
-                         double *resid);
+                         double *resid, int *restarted);
 
 /*
  * One block-eigensolver step on X (in/out, nb columns, ld >= npw):

@@ -653,10 +653,10 @@ struct Engine {
   // One LOBPCG step (the C ABI's pw_lobpcg_step): Z = [X R P], HZ = [HX HR HP] in the arena,
   // Rayleigh-Ritz on span Z, X' = Z C_1 into X, P' = [R P] C_1(R and P rows) into Pd.
   pw_status lobpcg_step(cplx<T>* X, cplx<T>* Pd, int nb, long ld, bool have_p, double* eig_host,
-                        double* resid_host) {
+                        double* resid_host, int* restarted) {
+    if (restarted) *restarted = 0;
     set_planes(nullptr, 0);
     const long ldw = P.ldw;
-    const int k = (have_p ? 3 : 2) * nb;
     cplx<T>* Z = h->at<cplx<T>>(P.lay.lz);
     cplx<T>* HZ = Z + (size_t)3 * P.nbands * ldw;
     double* theta = h->at<double>(P.lay.eig);  // Rayleigh quotients of X (before the eigensolve)
@@ -685,11 +685,21 @@ struct Engine {
       s = hop(Pz, ldw, nb, HZ + (size_t)2 * nb * ldw, ldw, HZ + (size_t)2 * nb * ldw, ldw, 1.0, 0.0, 0.0, nullptr, 0);
       if (s != PW_OK) return s;
     }
-    // Rayleigh-Ritz on span Z
+    // Rayleigh-Ritz on span Z; when the basis with P is numerically dependent (its Gram matrix
+    // fails the Cholesky test), again on span [X R] alone
     double2* parts = h->at<double2>(P.lay.parts);
-    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Z, ldw, Z, ldw, HZ, ldw, k, k, 2 * k, P.npw, P.nsplit_lob,
-                            parts, 4));
-    s = dense_solve(k, P.nsplit_lob);
+    int k = (have_p ? 3 : 2) * nb;
+    for (;;) {
+      PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Z, ldw, Z, ldw, HZ, ldw, k, k, 2 * k, P.npw, P.nsplit_lob,
+                              parts, 4));
+      s = dense_solve(k, P.nsplit_lob);
+      if (s == PW_ENOTPD && k == 3 * nb) {
+        k = 2 * nb;
+        if (restarted) *restarted = 1;
+        continue;
+      }
+      break;
+    }
     if (s != PW_OK) return s;
     const cplx<T>* C = coeffs(k);
     EpiH e;
@@ -1111,7 +1121,8 @@ pw_status pw_density(pw_handle* h, const void* X, int nb, int ld, const double* 
   return PW_OK;
 }
 
-pw_status pw_lobpcg_step(pw_handle* h, void* X, void* Pd, int nb, int ld, int have_p, double* eig, double* resid) {
+pw_status pw_lobpcg_step(pw_handle* h, void* X, void* Pd, int nb, int ld, int have_p, double* eig, double* resid,
+                         int* restarted) {
   if (!h) return fail(nullptr, PW_EINVAL, "null handle");
   pw_status s = check_block(h, X, nb, ld);
   if (s != PW_OK) return s;
@@ -1124,9 +1135,9 @@ pw_status pw_lobpcg_step(pw_handle* h, void* X, void* Pd, int nb, int ld, int ha
   if (x0 < p0 + span && p0 < x0 + span) return fail(h, PW_EINVAL, "X and P overlap");
   if (h->plan.prec == PW_FP64)
     return Engine<double>(h).lobpcg_step(static_cast<double2*>(X), static_cast<double2*>(Pd), nb, ld, have_p != 0,
-                                         eig, resid);
+                                         eig, resid, restarted);
   return Engine<float>(h).lobpcg_step(static_cast<float2*>(X), static_cast<float2*>(Pd), nb, ld, have_p != 0, eig,
-                                      resid);
+                                      resid, restarted);
 }
 
 pw_status pw_eig_step(pw_handle* h, void* X, void* HX, int nb, int ld, const pw_step_params* p, double* eig,

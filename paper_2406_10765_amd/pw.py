@@ -137,7 +137,7 @@ def lib() -> ctypes.CDLL:
         "pw_apply_h": ([vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "pw_density": ([vp, vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_double), vp]),
         "pw_lobpcg_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
-                            P(ctypes.c_double)]),
+                            P(ctypes.c_double), P(ctypes.c_int)]),
         "pw_eig_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, P(StepParams), P(ctypes.c_double),
                          P(ctypes.c_double), P(ctypes.c_double)]),
         "pw_spectrum_bound": ([vp, ctypes.c_int, ctypes.c_ulonglong, P(ctypes.c_double)]),
@@ -318,9 +318,10 @@ class Handle:
                self._h)
         return rho
 
-    def lobpcg_step(self, X, P, have_p: bool):
+    def lobpcg_step(self, X, P, have_p: bool, info: Optional[dict] = None):
         """One LOBPCG step on X and the directions P (both in place; P's input ignored when
-        not have_p).  Returns (Ritz values, residual norms of the input X) as numpy arrays."""
+        not have_p).  Returns (Ritz values, residual norms of the input X) as numpy arrays;
+        info["restarted"] tells whether the step fell back to the basis without P."""
         nb, ld = self._check_block(X)
         nb2, ld2 = self._check_block(P)
         if nb2 != nb or ld2 != ld:
@@ -328,8 +329,12 @@ class Handle:
         eig = np.empty(nb)
         res = np.empty(nb)
         dp = ctypes.POINTER(ctypes.c_double)
+        rs = ctypes.c_int(0)
         _check(lib().pw_lobpcg_step(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(P.data_ptr()), nb, ld,
-                                    1 if have_p else 0, eig.ctypes.data_as(dp), res.ctypes.data_as(dp)), self._h)
+                                    1 if have_p else 0, eig.ctypes.data_as(dp), res.ctypes.data_as(dp),
+                                    ctypes.byref(rs)), self._h)
+        if info is not None:
+            info["restarted"] = bool(rs.value)
         return eig, res
 
     def eig_step(self, X, degree: int, a_lo: float = float("nan"), a: float = float("nan"),

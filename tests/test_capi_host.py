@@ -90,7 +90,7 @@ def test_setup_argument_errors_without_device():
     assert L.pw_apply_h(None, None, None, 1, 1) == pw.PW_EINVAL
     assert L.pw_eig_step(None, None, None, 1, 1, None, None, None, None) == pw.PW_EINVAL
     assert L.pw_density(None, None, 1, 1, None, None) == pw.PW_EINVAL
-    assert L.pw_lobpcg_step(None, None, None, 1, 1, 0, None, None) == pw.PW_EINVAL
+    assert L.pw_lobpcg_step(None, None, None, 1, 1, 0, None, None, None) == pw.PW_EINVAL
     assert L.pw_destroy(None) == pw.PW_OK
 
 
