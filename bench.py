@@ -458,39 +458,43 @@ def main():
     # ---- LOBPCG step on the same cell (three H applications and a 3 N_b Rayleigh-Ritz) ------
     lobpcg = None
     if not big and not args.no_lobpcg and snap is not None:
-        hl = pw.Handle(cell, pw.PW_MIXED, flags=mflags | pw.PW_FLAG_LOBPCG)
-        Xl = snap.clone()
-        Pl = hl.empty_block(nb)
-        hl.lobpcg_step(Xl, Pl, False)
-        # steps with search directions; when the three-block Gram matrix is numerically singular
-        # the entry point redoes the step on [X R] (counted as a restart)
-        times, sizes, restarts = [], [], 0
-        have_p = True
-        for _ in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            info = {}
-            try:
-                el, rl = hl.lobpcg_step(Xl, Pl, have_p, info)
-            except pw.PWError:
-                restarts += 1
-                have_p = False
-                continue
-            times.append(time.perf_counter() - t0)
-            redone = bool(info.get("restarted"))
-            restarts += int(redone)
-            sizes.append(3 * nb if have_p and not redone else 2 * nb)
+        try:
+            hl = pw.Handle(cell, pw.PW_MIXED, flags=mflags | pw.PW_FLAG_LOBPCG)
+            Xl = snap.clone()
+            Pl = hl.empty_block(nb)
+            hl.lobpcg_step(Xl, Pl, False)
+            # steps with search directions; when the three-block Gram matrix is numerically singular
+            # the entry point redoes the step on [X R] (counted as a restart)
+            times, sizes, restarts = [], [], 0
             have_p = True
-        if times:
-            lobpcg = {"ms_per_step": [round(1000.0 * t, 2) for t in times], "rayleigh_ritz_sizes": sizes,
-                      "restarts_without_directions": restarts,
-                      "rayleigh_ritz_note": "a restarted step applied H three times but solved on [X R]",
-                      "max_resid_occ_input": float(rl[: cell.nocc].max()),
-                      "what": "mixed-precision LOBPCG steps from the filter's starting block"}
-        del hl, Xl, Pl
-        torch.cuda.empty_cache()
-        if lobpcg:
-            log(f"lobpcg: ms/step {lobpcg['ms_per_step']}, Rayleigh-Ritz sizes {sizes}, restarts {restarts}")
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = {}
+                try:
+                    el, rl = hl.lobpcg_step(Xl, Pl, have_p, info)
+                except pw.PWError:
+                    restarts += 1
+                    have_p = False
+                    continue
+                times.append(time.perf_counter() - t0)
+                redone = bool(info.get("restarted"))
+                restarts += int(redone)
+                sizes.append(3 * nb if have_p and not redone else 2 * nb)
+                have_p = True
+            if times:
+                lobpcg = {"ms_per_step": [round(1000.0 * t, 2) for t in times], "rayleigh_ritz_sizes": sizes,
+                          "restarts_without_directions": restarts,
+                          "rayleigh_ritz_note": "a restarted step applied H three times but solved on [X R]",
+                          "max_resid_occ_input": float(rl[: cell.nocc].max()),
+                          "what": "mixed-precision LOBPCG steps from the filter's starting block"}
+            del hl, Xl, Pl
+            torch.cuda.empty_cache()
+            if lobpcg:
+                log(f"lobpcg: ms/step {lobpcg['ms_per_step']}, Rayleigh-Ritz sizes {sizes}, restarts {restarts}")
+        except Exception as exc:  # a failed side measurement must not lose the headline line
+            lobpcg = {"error": str(exc)}
+            log(f"lobpcg measurement failed: {exc}")
 
     # ---- FP64 form from the same block and bounds -----------------------------------------
     fp64 = None
