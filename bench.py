@@ -457,10 +457,10 @@ def main():
 
     # ---- LOBPCG step on the same cell (three H applications and a 3 N_b Rayleigh-Ritz) ------
     lobpcg = None
-    if not big and not args.no_lobpcg and snap is not None:
+    if not big and not args.no_lobpcg:
         try:
             hl = pw.Handle(cell, pw.PW_MIXED, flags=mflags | pw.PW_FLAG_LOBPCG)
-            Xl = snap.clone()
+            Xl = (snap if snap is not None else X).clone()
             Pl = hl.empty_block(nb)
             hl.lobpcg_step(Xl, Pl, False)
             # steps with search directions; when the three-block Gram matrix is numerically singular
