@@ -9,6 +9,8 @@
  * and projected matrices S = Y^H Y and H_s = Y^H W (Section II-B, S = Psi^*(H Psi)),
  * the FP64 dense generalised eigensolve of (H_s, S) (Sections II-B and III-D,
  * "Syevd"), the rotation X' = Y C and the residual norms ||H x_i - lambda_i x_i||.
+ * Beside the step: the charge density of a block (pw_density) and a LOBPCG step
+ * (pw_lobpcg_step) on the same machinery, and a request loop for many small solves.
  *
  * Units: Hartree atomic units (bohr, Ha).  Gamma point only; the basis is every
  * reciprocal lattice vector G = 2 pi (n1/L1, n2/L2, n3/L3) with |G|^2/2 <= ecut
@@ -25,7 +27,8 @@
  * small workspace.
  *
  * Streams.  Work is enqueued on the caller's HIP stream.  pw_apply_h returns
- * without synchronising; pw_eig_step returns after its host outputs are written.
+ * without synchronising; pw_eig_step, pw_density and pw_lobpcg_step return after
+ * their outputs are written.
  *
  * Errors.  Every call returns a pw_status.  PW_EINVAL leaves no side effects.
  * pw_last_error gives a text message for the last failing call on a handle.
