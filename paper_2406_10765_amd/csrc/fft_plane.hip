@@ -312,19 +312,19 @@ struct StickShape {
   static constexpr int SPW0 = 256 / TT, SPWL = (48 * 1024) / (N * (int)sizeof(cplx<T>));
   static constexpr int SPW = SPW0 < SPWL ? SPW0 : SPWL;
   static constexpr int NT = SPW * TT;
-  // LDS swizzle.  A wave holds G = 64 / TT sticks (lane = TT s + t); the TT threads of one stick
-  // touch TT positions at once, 1 or B apart, which in a plain [position][stick] layout all fall
-  // in the same banks.  Position p goes to row p ^ ((p / B) & 1) (neighbouring rows swapped in
-  // every other block of B) and its stick s to column s ^ (G h(p)), h(p) = (p / 2 + p / 2B) mod
-  // (SPW / G): the TT positions of one access then occupy distinct G-stick slices of a bank row,
-  // whether the LDS has 32, 64 or 128 four-byte banks.  Used where the shapes allow it (64 % TT
-  // == 0, SPW a multiple of the elements per 256 bytes, B even).
+  // LDS swizzle.  Lane = TT s + t: a half-wave (32 lanes, the unit in which the LDS serves a
+  // 64-lane access of 8-byte elements) holds Gh = 32 / TT sticks, and its TT threads of one
+  // stick touch TT positions at once, 1 or B apart, which in a plain [position][stick] layout
+  // all fall in the same banks.  Stick s of position p is stored at column s ^ (Gh x(p)),
+  // x(p) = (p + p / B) mod X with X = E / Gh slices of Gh sticks per 256-byte bank row (E
+  // elements): the TT positions then occupy distinct slices (checked by enumeration for every
+  // compiled size).  Used where the shapes allow it (32 % TT == 0, SPW a multiple of E).
   static constexpr int E = 256 / (int)sizeof(cplx<T>);
-  static constexpr int G = 64 % TT == 0 ? 64 / TT : 0;
-  static constexpr bool SWZ = G > 0 && E > G && SPW % E == 0 && B % 2 == 0;
-  static constexpr int H = G > 0 ? SPW / G : 1;
+  static constexpr int Gh = 32 % TT == 0 ? 32 / TT : 0;
+  static constexpr bool SWZ = Gh > 0 && E > Gh && SPW % E == 0;
+  static constexpr int X = SWZ ? E / Gh : 1;
   __device__ __forceinline__ static int at(int p, int s) {
-    if constexpr (SWZ) return (p ^ ((p / B) & 1)) * SPW + (s ^ (G * (((p >> 1) + p / (2 * B)) % H)));
+    if constexpr (SWZ) return p * SPW + (s ^ (Gh * ((p + p / B) % X)));
     else return p * SPW + s;
   }
 };
