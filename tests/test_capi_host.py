@@ -136,3 +136,15 @@ def test_lobpcg_plan_needs_one_block():
     assert ok.footprint_bytes > base.footprint_bytes
     with pytest.raises(Exception):
         pw.plan(cell, pw.PW_MIXED, flags=pw.PW_FLAG_LOBPCG, filter_block=64)
+
+
+def test_binding_flags_and_statuses_match_the_header():
+    """The Python constants mirror include/pw.h (flags and status codes)."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pw.h")).read()
+    for name, val in re.findall(r"#define (PW_FLAG_[A-Z0-9_]+) (\d+)u", hdr):
+        assert getattr(pw, name) == int(val), name
+    for name, val in re.findall(r"\b(PW_[A-Z]+) = (-?\d+)", hdr):
+        if hasattr(pw, name):
+            assert getattr(pw, name) == int(val), name
