@@ -446,3 +446,17 @@ def test_lobpcg_converges_to_dense(si8):
         if r.resid[:8].max() < 1e-9:
             break
     assert np.abs(r.eig[:8] - lam[:8]).max() < 1e-8
+
+
+def test_lanczos_bound_brackets_the_top_of_the_spectrum(si8):
+    """The Lanczos estimate (largest Ritz value plus the last off-diagonal) bounds lambda_max of the
+    dense H from above (the Ritz value interlaces below it; the residual term covers the gap); on a
+    Krylov space that is the whole space it is lambda_max itself."""
+    cell, model, H, lam, V = si8
+    hop = lambda x: H @ x
+    for steps, seed in ((20, 1), (80, 2)):
+        assert O.lanczos_max(hop, model.npw, steps, seed=seed) >= lam[-1] - 1e-9
+    # a Krylov space that is the whole space gives lambda_max exactly (the off-diagonal vanishes)
+    small = H[:6, :6]
+    ev = np.linalg.eigvalsh(small)
+    assert abs(O.lanczos_max(lambda x: small @ x, 6, 6, seed=3) - ev[-1]) < 1e-8
