@@ -164,6 +164,23 @@ pw_status pw_get_gvectors(const pw_handle *h, int *miller_host);
 pw_status pw_apply_h(pw_handle *h, const void *X_dev, void *HX_dev, int nb, int ld);
 
 /*
+ * pw_apply_h for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same H X, through the same kernels, with
+ * the work buffers of the H applications (stick and pencil FFT intermediates, split-K partials of
+ * the projections, D P and the bf16 planes of the block) placed in a static device array of the
+ * library (64 MiB per device, held until the process ends) instead of the handle's arena.
+ * Allocates nothing and creates nothing: no hipMalloc or hipFree, no library allocation, no
+ * stream or event; phase timers are not recorded during the call.  Bands are processed in groups
+ * of as many columns as the array holds; PW_ENOMEM when not even one band of this cell fits
+ * (e.g. a 192^3 grid in FP64), PW_EINVAL as pw_apply_h.  The array keeps the last call's
+ * contents; nothing in it needs to start at zero.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (several host threads, or several
+ * streams with work in flight) race and give wrong results; serialise them on one stream.
+ * Asynchronous on the handle's stream, like pw_apply_h.
+ */
+pw_status pw_apply_h_noalloc(pw_handle *h, const void *X_dev, void *HX_dev, int nb, int ld);
+
+/*
  * Charge density of nb bands (1 <= nb <= nbands; X as for pw_apply_h), the quantity the SCF
  * loop forms from the eigenfunctions (Section II-A): rho(r_j) = sum_n occ[n] |psi_n(r_j)|^2 at
  * the FFT grid points r_j = (j1 L1/N1, j2 L2/N2, j3 L3/N3), psi_n(r) = sum_G X[G, n] exp(+i G.r)

@@ -33,6 +33,35 @@ using namespace pw;
 
 static thread_local std::string g_last_error;
 
+// Work array of pw_apply_h_noalloc, for callers that cannot allocate device memory.  Each device
+// the library runs on holds its own copy for the life of the process; host code reaches it only
+// through the device address hipGetSymbolAddress returns (kept per device below), never through
+// the array's name.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch[kMaxDevices] = {};
+
+// Device address of this device's work array (the device must be current); null on failure.
+static unsigned char* scratch_address(int dev, std::string* err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = "device ordinal beyond the library's table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch[dev] = static_cast<unsigned char*>(ptr);
+  }
+  return g_scratch[dev];
+}
+
 struct pw_handle_s {
   Plan plan;
   unsigned char* arena = nullptr;
@@ -52,6 +81,14 @@ struct pw_handle_s {
   int yp_n = 0;
   // Block whose planes follow those of yp_src (the Gram product's second operand), or null.
   const void* wp_src = nullptr;
+  // This device's copy of the library's static work array (device address), and, while a call of
+  // pw_apply_h_noalloc runs, the work buffers of its H applications placed in it: stick and
+  // pencil intermediates, split-K partials, D P and the bf16 planes of the block, for ws_cols
+  // columns per H application and ws_fft_batch bands per FFT launch.
+  unsigned char* scratch = nullptr;
+  unsigned char* ws = nullptr;
+  size_t ws_sb = 0, ws_g1 = 0, ws_parts = 0, ws_pt = 0, ws_yp = 0;
+  int ws_cols = 0, ws_fft_batch = 0;
   std::chrono::steady_clock::time_point t_step;
   void report(const char* what, int i, int n) {
     if (!progress) return;
@@ -197,13 +234,23 @@ struct Engine {
   }
   unsigned int* beta_hi() const { return h->at<unsigned int>(P.lay.beta); }
   unsigned int* beta_lo() const { return beta_hi() + (size_t)P.ldw * P.nproj; }
-  unsigned int* yp_hi() const { return h->at<unsigned int>(P.lay.yp); }
-  unsigned int* yp_lo() const { return yp_hi() + (size_t)P.ldw * P.yp_cols; }
+  // Work buffers of an H application: the arena's, or the static work array's during
+  // pw_apply_h_noalloc.
+  template <typename X>
+  X* work(size_t arena_off, size_t ws_off) const {
+    return h->ws ? reinterpret_cast<X*>(h->ws + ws_off) : h->at<X>(arena_off);
+  }
+  cplx<T>* sb_buf() const { return work<cplx<T>>(P.lay.sb, h->ws_sb); }
+  cplx<T>* g1_buf() const { return work<cplx<T>>(P.lay.g1, h->ws_g1); }
+  double2* parts_buf() const { return work<double2>(P.lay.parts, h->ws_parts); }
+  int fft_batch() const { return h->ws ? h->ws_fft_batch : P.fft_batch; }
+  unsigned int* yp_hi() const { return work<unsigned int>(P.lay.yp, h->ws_yp); }
+  unsigned int* yp_lo() const { return yp_hi() + (size_t)P.ldw * (h->ws ? h->ws_cols : P.yp_cols); }
   // the unblocked step keeps the planes of W = H Y beside those of Y for the Gram product
   bool gram_planes() const { return beta_planes() && P.yp_cols >= 2 * P.nbb; }
   // with projector planes, D B^H Y is kept as the nonlocal product's B planes in the bytes of PT
-  unsigned int* pt_hi() const { return h->at<unsigned int>(P.lay.pt); }
-  unsigned int* pt_lo() const { return pt_hi() + (size_t)P.nproj * P.nbb; }
+  unsigned int* pt_hi() const { return work<unsigned int>(P.lay.pt, h->ws_pt); }
+  unsigned int* pt_lo() const { return pt_hi() + (size_t)P.nproj * (h->ws ? h->ws_cols : P.nbb); }
   bool planes_of(const void* Y, int nb) const { return Y && h->yp_src == Y && nb <= h->yp_n; }
   void set_planes(const void* Y, int nb) {
     h->yp_src = Y;
@@ -271,16 +318,17 @@ struct Engine {
   pw_status local_part(const cplx<T>* Y, long ldy, cplx<T>* Z, long ldz, int nb, hipStream_t sm) {
     const GridDesc& g = P.g;
     const T scale = (T)(1.0 / ((double)g.n1 * g.n2 * g.n3));
-    cplx<T>* SB = h->at<cplx<T>>(P.lay.sb);
-    cplx<T>* G1 = h->at<cplx<T>>(P.lay.g1);
+    cplx<T>* SB = sb_buf();
+    cplx<T>* G1 = g1_buf();
     const Stick* st = h->at<Stick>(P.lay.sticks);
     const int* cs = h->at<int>(P.lay.colstart);
     const T* V = h->at<T>(P.lay.vr);
     const cplx<T>* tw1 = h->at<cplx<T>>(P.lay.tw1);
     const cplx<T>* tw2 = h->at<cplx<T>>(P.lay.tw2);
     const cplx<T>* tw3 = h->at<cplx<T>>(P.lay.tw3);
-    for (int b0 = 0; b0 < nb; b0 += P.fft_batch) {
-      const int nbt = std::min(P.fft_batch, nb - b0);
+    const int fb = fft_batch();
+    for (int b0 = 0; b0 < nb; b0 += fb) {
+      const int nbt = std::min(fb, nb - b0);
       PW_TIMED_ON(PW_PH_STICKS_INV, sm,
                   launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, sm));
       if (P.fl.sized) {
@@ -320,9 +368,9 @@ struct Engine {
     pw_status s = local_part(Y, ldy, Zl, ldz, nb, overlap ? h->aux : h->stream);
     if (s != PW_OK) return s;
     if (overlap) PW_HIP(hipEventRecord(h->ev_join, h->aux));
-    cplx<T>* PT = h->at<cplx<T>>(P.lay.pt);
+    cplx<T>* PT = work<cplx<T>>(P.lay.pt, h->ws_pt);
     if (P.nproj > 0) {
-      double2* parts = h->at<double2>(P.lay.parts);
+      double2* parts = parts_buf();
       if constexpr (std::is_same<T, float>::value) {
         if (beta_planes()) {
           if (!planes_of(Y, nb)) {
@@ -424,10 +472,12 @@ struct Engine {
     return PW_OK;
   }
 
-  pw_status apply_h(const cplx<T>* X, cplx<T>* HX, int nb, int ld) {
+  // HX = H X in column groups of `step` bands (the filter block, or what the static work array
+  // holds during pw_apply_h_noalloc).
+  pw_status apply_h(const cplx<T>* X, cplx<T>* HX, int nb, int ld, int step) {
     set_planes(nullptr, 0);
-    for (int c0 = 0; c0 < nb; c0 += P.nbb) {
-      const int w = std::min(P.nbb, nb - c0);
+    for (int c0 = 0; c0 < nb; c0 += step) {
+      const int w = std::min(step, nb - c0);
       pw_status s = hop(X + (long)c0 * ld, ld, w, HX + (long)c0 * ld, ld, HX + (long)c0 * ld, ld, 1.0, 0.0, 0.0,
                         nullptr, 0);
       if (s != PW_OK) return s;
@@ -791,7 +841,7 @@ struct Engine {
     std::vector<double> al, be;
     double bprev = 0.0;
     for (int it = 0; it < steps && it < n; ++it) {
-      pw_status s = apply_h(V1, Wv, 1, (int)P.ldw);
+      pw_status s = apply_h(V1, Wv, 1, (int)P.ldw, P.nbb);
       if (s != PW_OK) return s;
       PW_HIP(launch_lanczos_step<T>(Wv, V1, V0, bprev, n, sc, h->stream));
       double hs[2];
@@ -1015,6 +1065,14 @@ pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes
     return fail(nullptr, PW_EDEVICE, "no HIP device");
   }
   h->device = dev;
+  {
+    std::string serr;
+    h->scratch = scratch_address(dev, &serr);
+    if (!h->scratch) {
+      delete h;
+      return fail(nullptr, PW_EDEVICE, serr);
+    }
+  }
   h->max_lds = device_max_lds();
   if (const char* e = std::getenv("PW_PROGRESS")) h->progress = e[0] == '1';
   std::string err;
@@ -1099,8 +1157,76 @@ pw_status pw_apply_h(pw_handle* h, const void* X, void* HX, int nb, int ld) {
   const size_t span = ((size_t)(nb - 1) * ld + h->plan.npw) * cb;
   if (x0 < y0 + span && y0 < x0 + span) return fail(h, PW_EINVAL, "X and HX overlap");
   if (h->plan.prec == PW_FP64)
-    return Engine<double>(h).apply_h(static_cast<const double2*>(X), static_cast<double2*>(HX), nb, ld);
-  return Engine<float>(h).apply_h(static_cast<const float2*>(X), static_cast<float2*>(HX), nb, ld);
+    return Engine<double>(h).apply_h(static_cast<const double2*>(X), static_cast<double2*>(HX), nb, ld,
+                                     h->plan.nbb);
+  return Engine<float>(h).apply_h(static_cast<const float2*>(X), static_cast<float2*>(HX), nb, ld, h->plan.nbb);
+}
+
+// Columns per H application that the static work array holds, and the placement of the work
+// buffers in it; 0 when not even one column fits.
+static int noalloc_layout(pw_handle* h, int nb) {
+  const Plan& P = h->plan;
+  const GridDesc& g = P.g;
+  const size_t cb = 2 * (size_t)P.real_bytes;
+  const size_t sb1 = (size_t)P.nst * g.n3 * cb;
+  const size_t g11 = P.fl.fused ? 0 : (size_t)g.n3 * g.n2 * g.n1a * cb;
+  const bool planes = P.real_bytes == 4 && (P.flags & PW_FLAG_BF16_KB) && P.nproj > 0;
+  const size_t per_col = sb1 + g11 + (P.nproj ? 16 * (size_t)P.nsplit_proj * P.nproj + cb * P.nproj : 0) +
+                         (planes ? 8 * (size_t)P.ldw : 0);
+  const size_t slack = 5 * kArenaAlign;
+  if (kScratchBytes <= slack) return 0;
+  long w = (long)((kScratchBytes - slack) / per_col);
+  w = std::min<long>(w, std::min(nb, P.nbb));
+  if (w < 1) return 0;
+  auto al = [](size_t x) { return (x + kArenaAlign - 1) / kArenaAlign * kArenaAlign; };
+  const size_t fb = (size_t)std::min<long>(P.fft_batch, w);
+  size_t off = 0;
+  h->ws_sb = off;
+  off = al(off + sb1 * fb);
+  h->ws_g1 = off;
+  off = al(off + g11 * fb);
+  h->ws_parts = off;
+  off = al(off + (P.nproj ? 16 * (size_t)P.nsplit_proj * P.nproj * w : 0));
+  h->ws_pt = off;
+  off = al(off + (P.nproj ? cb * P.nproj * w : 0));
+  h->ws_yp = off;
+  off = al(off + (planes ? 8 * (size_t)P.ldw * w : 0));
+  if (off > kScratchBytes) return 0;
+  h->ws_cols = (int)w;
+  h->ws_fft_batch = (int)fb;
+  return (int)w;
+}
+
+pw_status pw_apply_h_noalloc(pw_handle* h, const void* X, void* HX, int nb, int ld) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  pw_status s = check_block(h, X, nb, ld);
+  if (s != PW_OK) return s;
+  if (!HX) return fail(h, PW_EINVAL, "null output");
+  const size_t cb = 2 * (size_t)h->plan.real_bytes;
+  const char* x0 = static_cast<const char*>(X);
+  const char* y0 = static_cast<const char*>(HX);
+  const size_t span = ((size_t)(nb - 1) * ld + h->plan.npw) * cb;
+  if (x0 < y0 + span && y0 < x0 + span) return fail(h, PW_EINVAL, "X and HX overlap");
+  if (!h->scratch) return fail(h, PW_EDEVICE, "no static work array on this device");
+  const int w = noalloc_layout(h, nb);
+  if (w < 1)
+    return fail(h, PW_ENOMEM, "one band of this cell needs more than the " + std::to_string(kScratchBytes >> 20) +
+                                  " MiB static work array of pw_apply_h_noalloc");
+  // phase timers would create events: not recorded during this call
+  const bool timing = h->timing;
+  h->timing = false;
+  h->ws = h->scratch;
+  if (h->plan.prec == PW_FP64)
+    s = Engine<double>(h).apply_h(static_cast<const double2*>(X), static_cast<double2*>(HX), nb, ld, w);
+  else
+    s = Engine<float>(h).apply_h(static_cast<const float2*>(X), static_cast<float2*>(HX), nb, ld, w);
+  // the planes bookkeeping refers to the work array only during this call
+  h->ws = nullptr;
+  h->timing = timing;
+  h->yp_src = nullptr;
+  h->yp_n = 0;
+  h->wp_src = nullptr;
+  return s;
 }
 
 pw_status pw_density(pw_handle* h, const void* X, int nb, int ld, const double* occ_host, void* rho_dev) {

@@ -135,6 +135,7 @@ def lib() -> ctypes.CDLL:
         "pw_query": ([vp, P(Info)]),
         "pw_get_gvectors": ([vp, P(ctypes.c_int)]),
         "pw_apply_h": ([vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "pw_apply_h_noalloc": ([vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "pw_density": ([vp, vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_double), vp]),
         "pw_lobpcg_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
                             P(ctypes.c_double), P(ctypes.c_int)]),
@@ -299,6 +300,16 @@ class Handle:
             raise ValueError("X and HX must have the same shape and stride")
         _check(lib().pw_apply_h(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(HX.data_ptr()), nb, ld),
                self._h)
+        return HX
+
+    def apply_h_noalloc(self, X, HX):
+        """HX = H X through pw_apply_h_noalloc (work buffers in the library's static array)."""
+        nb, ld = self._check_block(X)
+        nb2, ld2 = self._check_block(HX)
+        if nb2 != nb or ld2 != ld:
+            raise ValueError("X and HX must have the same shape and stride")
+        _check(lib().pw_apply_h_noalloc(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(HX.data_ptr()), nb,
+                                        ld), self._h)
         return HX
 
     def density(self, X, occ, rho=None):
