@@ -337,14 +337,18 @@ def dense_h(model: Model) -> np.ndarray:
     return H
 
 
-def apply_nonlocal_atomwise(model: Model, X: np.ndarray) -> np.ndarray:
+def apply_nonlocal_atomwise(model: Model, X: np.ndarray,
+                            progress: Optional[Callable[[int], None]] = None) -> np.ndarray:
     """V_NL X = sum_a B_a D (B_a^H X), one atom at a time (Section III-A: the pseudopotential
-    of each atom is applied to every wavefunction).  Never forms the full projector matrix."""
+    of each atom is applied to every wavefunction).  Never forms the full projector matrix.
+    progress, when given, is called with the number of atoms done after every 64 atoms."""
     out = np.zeros_like(X)
     d = model.D[:4]
     for a in range(model.tau.shape[0]):
         Ba = projector_matrix(model.miller, model.L, model.tau[a:a + 1], model.sigma, model.sf_sign)
         out += Ba @ (d[:, None] * (Ba.conj().T @ X))
+        if progress is not None and (a + 1) % 64 == 0:
+            progress(a + 1)
     return out
 
 
