@@ -298,7 +298,7 @@ def serving_leg(n, rate, slots, flags, degree):
         "peak_in_flight": peak_in_flight([(r["t_admit"], r["t_done"]) for r in res]),
         "converged": int(sum(r["status"] == 0 for r in res)),
         "not_converged": [{"cell": m["name"], "ecut_ha": float(m["cell"].ecut), "seed": int(m["seed"]),
-                           "status": int(r["status"]), "steps": int(r["steps"])}
+                           "status": int(r["status"]), "steps": int(r["steps"]), "message": r.get("message", "")}
                           for r, m in zip(res, mix) if r["status"] != 0],
         "mean_steps": float(np.mean([r["steps"] for r in res])),
         "p50_latency_by_cell_s": {k: float(np.percentile(v, 50)) for k, v in sorted(by.items())},

@@ -224,10 +224,26 @@ pw_status pw_lobpcg_step(pw_handle *h, void *X_dev, void *P_dev, int nb, int ld,
  * {lambda_1, lambda_nb, b}: the a_lo and a of the next step, and the b used.
  * HX_dev may be NULL unless want_hx.  PW_ENOTPD when the Cholesky fails (X unchanged
  * content is not guaranteed), PW_ENUMERIC on a non-finite eigenvalue or residual.
- * For degree > 0 the bounds must satisfy a_lo < a < b.
+ * For degree > 0 the bounds must satisfy a_lo < a < b.  A NaN bound takes the library's value:
+ * a_lo and a from the last successful step on this handle (lambda_1, lambda_nb; PW_EINVAL when
+ * there was none), b from the Lanczos estimate of pw_spectrum_bound (20 steps, seed 1, computed
+ * once per handle).
  */
 pw_status pw_eig_step(pw_handle *h, void *X_dev, void *HX_dev, int nb, int ld, const pw_step_params *p,
                       double *eig_host, double *resid_host, double bounds_out[3]);
+
+/*
+ * The solve loop around pw_eig_step (an iterative eigensolver run to convergence, Section II-A):
+ * one degree-0 step (Rayleigh-Ritz on the input block, which gives the first filter bounds), then
+ * degree-`degree` steps, each taking a_lo, a from the previous step, until the residual norms of
+ * the lowest nconv bands (0 = all nb) are all <= tol, or max_steps steps were taken (then
+ * PW_ENOTCONV with the last eig/resid written).  b: upper filter bound; NaN = the library's
+ * Lanczos estimate (pw_spectrum_bound with 20 steps, seed 1, computed once per handle).
+ * eig_host, resid_host: nb doubles (host); *steps (may be NULL) receives the steps taken.
+ * Errors of a step are returned as they are (its pw_last_error text names the step).
+ */
+pw_status pw_solve(pw_handle *h, void *X_dev, int nb, int ld, int nconv, double tol, int degree, int max_steps,
+                   double b, double *eig_host, double *resid_host, int *steps);
 
 /*
  * Seeded starting block on the device: entry (g, j) = w_g (x + i y) / ||column j||, with x, y
@@ -282,14 +298,16 @@ const char *pw_last_error(const pw_handle *h);
  * Serving: a request loop that takes eigen-solves of different cells as they arrive.
  *
  * The server owns max_slots host worker threads, each with its own HIP stream (default
- * priority) on the device current at creation.  Requests are admitted first come, first
- * served when a slot is free and the request's device footprint (pw_plan footprint plus its
- * wavefunction block) fits in the free part of the caller's arena (first-fit); a request that
- * could never fit fails with PW_ENOMEM at submission.  An admitted request builds its own
+ * priority) on the device current at creation.  Requests are admitted in arrival order when a
+ * slot is free: the first queued request whose device footprint (pw_plan footprint plus its
+ * wavefunction block) fits in the free part of the caller's arena (first-fit placement) is
+ * taken, so smaller requests may pass one that does not fit yet, but at most 16 times; after
+ * that nothing behind it is admitted until it fits (no starvation).  A request that could never
+ * fit fails with PW_ENOMEM at submission.  An admitted request builds its own
  * handle inside its arena range, draws its seeded starting block, estimates the filter bound,
  * and is advanced step by step (first step degree 0, then `degree`) until the residual norms
  * of its lowest `nconv` bands are <= tol or max_steps is reached (PW_ENOTCONV, partial
- * results kept).  Admitted requests run concurrently, so their kernels overlap on the device;
+ * results kept): the loop of pw_solve.  Admitted requests run concurrently, so their kernels overlap on the device;
  * each request's arithmetic is independent of the others (same results alone or in a mix).
  * pw_submit / pw_poll / pw_server_clock are thread safe.
  */
@@ -300,6 +318,9 @@ typedef struct {
   size_t arena_bytes;
   int max_slots;        /* concurrent requests, 1..64 */
   unsigned flags;       /* PW_SERVER_* */
+  void *hip_stream;     /* the caller's hipStream_t (NULL = default stream): work enqueued on it before
+                           pw_server_create (e.g. filling the arena) completes before any request
+                           starts; the slot streams wait on an event recorded on it */
 } pw_server_cfg;
 
 typedef struct {
@@ -317,6 +338,7 @@ typedef struct {
   double *eig;          /* caller buffer of nbands doubles (filled by pw_poll), may be NULL */
   double *resid;        /* caller buffer of nbands doubles, may be NULL */
   double t_arrive, t_admit, t_done;  /* server clock (s) */
+  char message[256];    /* for a failed request: the failing call and its pw_last_error text */
 } pw_result;
 
 typedef struct pw_server_s pw_server;

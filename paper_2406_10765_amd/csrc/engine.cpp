@@ -72,6 +72,8 @@ struct pw_handle_s {
   size_t max_lds = kDefaultMaxLds;
   std::string err;
   double bmax_cached = NAN;
+  // lambda_1 and lambda_nb of the last successful pw_eig_step on this handle (NaN before one)
+  double last_lo = NAN, last_hi = NAN;
   // PW_PROGRESS=1 in the environment: report each completed filter block of a band-blocked
   // step on stderr (the stream is synchronised at each report).
   bool progress = false;
@@ -1276,7 +1278,13 @@ pw_status pw_eig_step(pw_handle* h, void* X, void* HX, int nb, int ld, const pw_
   if (p->want_hx && !HX) return fail(h, PW_EINVAL, "want_hx without HX");
   pw_step_params q = *p;
   if (q.degree > 0) {
-    if (!std::isfinite(q.b)) {
+    if (std::isnan(q.a_lo) || std::isnan(q.a)) {
+      if (!std::isfinite(h->last_lo) || !std::isfinite(h->last_hi))
+        return fail(h, PW_EINVAL, "NaN filter bounds need a previous step on this handle");
+      if (std::isnan(q.a_lo)) q.a_lo = h->last_lo;
+      if (std::isnan(q.a)) q.a = h->last_hi;
+    }
+    if (std::isnan(q.b)) {
       if (!std::isfinite(h->bmax_cached)) {
         double bb = 0.0;
         s = pw_spectrum_bound(h, 20, 1, &bb);
@@ -1285,14 +1293,67 @@ pw_status pw_eig_step(pw_handle* h, void* X, void* HX, int nb, int ld, const pw_
       }
       q.b = h->bmax_cached;
     }
-    if (!(std::isfinite(q.a_lo) && std::isfinite(q.a) && q.a_lo < q.a && q.a < q.b))
+    if (!(std::isfinite(q.a_lo) && std::isfinite(q.a) && std::isfinite(q.b) && q.a_lo < q.a && q.a < q.b))
       return fail(h, PW_EINVAL, "filter bounds must satisfy a_lo < a < b");
   }
   if (h->plan.prec == PW_FP64)
-    return Engine<double>(h).eig_step(static_cast<double2*>(X), static_cast<double2*>(HX), nb, ld, q, eig, resid,
-                                      bounds_out);
-  return Engine<float>(h).eig_step(static_cast<float2*>(X), static_cast<float2*>(HX), nb, ld, q, eig, resid,
+    s = Engine<double>(h).eig_step(static_cast<double2*>(X), static_cast<double2*>(HX), nb, ld, q, eig, resid,
                                    bounds_out);
+  else
+    s = Engine<float>(h).eig_step(static_cast<float2*>(X), static_cast<float2*>(HX), nb, ld, q, eig, resid,
+                                  bounds_out);
+  if (s == PW_OK) {
+    h->last_lo = eig[0];
+    h->last_hi = eig[nb - 1];
+  }
+  return s;
+}
+
+pw_status pw_solve(pw_handle* h, void* X, int nb, int ld, int nconv, double tol, int degree, int max_steps,
+                   double b, double* eig, double* resid, int* steps) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  pw_status s = check_block(h, X, nb, ld);
+  if (s != PW_OK) return s;
+  if (!eig || !resid) return fail(h, PW_EINVAL, "null output");
+  if (!(tol > 0.0) || degree < 1 || degree > 1000 || max_steps < 1 || nconv < 0 || nconv > nb)
+    return fail(h, PW_EINVAL, "bad solve parameters (tol > 0, 1 <= degree <= 1000, max_steps >= 1, "
+                              "0 <= nconv <= nb)");
+  if (steps) *steps = 0;
+  if (std::isnan(b)) {
+    if (!std::isfinite(h->bmax_cached)) {
+      s = pw_spectrum_bound(h, 20, 1, &h->bmax_cached);
+      if (s != PW_OK) return s;
+    }
+    b = h->bmax_cached;
+  }
+  if (!std::isfinite(b)) return fail(h, PW_EINVAL, "non-finite filter bound b");
+  const int nc = nconv > 0 ? nconv : nb;
+  auto converged = [&]() {
+    for (int i = 0; i < nc; ++i)
+      if (!(resid[i] <= tol)) return false;
+    return true;
+  };
+  pw_step_params p{0, NAN, NAN, b, 0};
+  double bnd[3] = {0, 0, 0};
+  int k = 0;
+  s = pw_eig_step(h, X, nullptr, nb, ld, &p, eig, resid, bnd);
+  if (s == PW_OK) k = 1;
+  while (s == PW_OK && !converged() && k < max_steps) {
+    p.degree = degree;
+    p.a_lo = bnd[0];
+    p.a = bnd[1];
+    p.b = b;
+    s = pw_eig_step(h, X, nullptr, nb, ld, &p, eig, resid, bnd);
+    if (s == PW_OK) ++k;
+  }
+  if (steps) *steps = k;
+  if (s != PW_OK) {
+    h->err = "step " + std::to_string(k + 1) + ": " + h->err;
+    g_last_error = h->err;
+    return s;
+  }
+  if (!converged()) return fail(h, PW_ENOTCONV, "max_steps reached before the tolerance");
+  return PW_OK;
 }
 
 pw_status pw_random_block(pw_handle* h, void* X, int nb, int ld, unsigned long long seed) {

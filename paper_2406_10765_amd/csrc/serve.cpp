@@ -6,6 +6,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -36,6 +37,8 @@ struct Request {
   size_t plan_bytes = 0, block_bytes = 0, need = 0;
   size_t off = 0;
   long ld = 0;
+  int bypassed = 0;     // times a later request was admitted ahead of this one
+  std::string message;  // pw_last_error text of the failing call (empty when status is PW_OK)
 };
 
 // First-fit allocator over [0, size) with coalescing.
@@ -90,13 +93,35 @@ struct pw_server_s {
   std::vector<std::thread> workers;
   unsigned long long next_ticket = 1;
   bool stop = false;
+  hipEvent_t start_ev = nullptr;  // recorded on the caller's stream at creation
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   void worker(int slot);
   void run(Request* q, hipStream_t stream);
+  Request* admit_locked();
 };
+
+// Admission (called with the lock held): the first queued request, in arrival order, whose
+// footprint fits the free arena (first-fit placement).  A request that does not fit may be passed
+// by later, smaller ones, but only kMaxBypass times; after that nothing behind it is admitted until
+// it fits, so a large request is delayed by a bounded amount of work and never starved.
+Request* pw_server_s::admit_locked() {
+  constexpr int kMaxBypass = 16;
+  for (auto it = queue.begin(); it != queue.end(); ++it) {
+    Request* c = *it;
+    size_t off = 0;
+    if (mem->alloc(c->need, &off)) {
+      c->off = off;
+      for (auto jt = queue.begin(); jt != it; ++jt) ++(*jt)->bypassed;
+      queue.erase(it);
+      return c;
+    }
+    if (c->bypassed >= kMaxBypass) return nullptr;
+  }
+  return nullptr;
+}
 
 void pw_server_s::run(Request* q, hipStream_t stream) {
   pw_request& r = q->r;
@@ -120,40 +145,32 @@ void pw_server_s::run(Request* q, hipStream_t stream) {
   pw_status s = pw_setup(&r.cell, base, q->plan_bytes, stream, &h);
   if (s != PW_OK) {
     q->status = s;
+    q->message = std::string("pw_setup: ") + pw_last_error(nullptr);
     return;
   }
   void* X = base + q->plan_bytes;
   s = pw_random_block(h, X, nb, (int)q->ld, r.seed);
   if (s != PW_OK) {
     q->status = s;
+    q->message = std::string("pw_random_block: ") + pw_last_error(h);
     pw_destroy(h);
     return;
   }
   double b = 0.0;
   s = pw_spectrum_bound(h, 20, r.seed + 1, &b);
-  pw_step_params p{0, NAN, NAN, b, 0};
-  double bnd[3] = {0, 0, 0};
-  const int nconv = (r.nconv > 0 && r.nconv <= nb) ? r.nconv : nb;
+  if (s != PW_OK) {
+    q->status = s;
+    q->message = std::string("pw_spectrum_bound: ") + pw_last_error(h);
+    pw_destroy(h);
+    return;
+  }
   int steps = 0;
-  auto converged = [&]() {
-    for (int i = 0; i < nconv; ++i)
-      if (!(q->resid[i] <= r.tol)) return false;
-    return true;
-  };
-  if (s == PW_OK) {
-    s = pw_eig_step(h, X, nullptr, nb, (int)q->ld, &p, q->eig.data(), q->resid.data(), bnd);
-    steps = 1;
-  }
-  while (s == PW_OK && !converged() && steps < r.max_steps) {
-    p.degree = r.degree;
-    p.a_lo = bnd[0];
-    p.a = bnd[1];
-    p.b = b;
-    s = pw_eig_step(h, X, nullptr, nb, (int)q->ld, &p, q->eig.data(), q->resid.data(), bnd);
-    ++steps;
-  }
+  const int nconv = (r.nconv > 0 && r.nconv <= nb) ? r.nconv : nb;
+  s = pw_solve(h, X, nb, (int)q->ld, nconv, r.tol, r.degree, r.max_steps, b, q->eig.data(), q->resid.data(),
+               &steps);
   q->steps = steps;
-  q->status = s != PW_OK ? s : (converged() ? PW_OK : PW_ENOTCONV);
+  q->status = s;
+  if (s != PW_OK) q->message = std::string("pw_solve: ") + pw_last_error(h);
   pw_destroy(h);
 }
 
@@ -162,6 +179,7 @@ void pw_server_s::worker(int slot) {
   hipStream_t stream = nullptr;
   if (!(cfg.flags & PW_SERVER_DRY_RUN)) {
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    if (start_ev) (void)hipStreamWaitEvent(stream, start_ev, 0);
   }
   for (;;) {
     Request* q = nullptr;
@@ -169,16 +187,8 @@ void pw_server_s::worker(int slot) {
       std::unique_lock<std::mutex> lk(mu);
       for (;;) {
         if (stop) break;
-        if (!queue.empty()) {
-          Request* head = queue.front();
-          size_t off = 0;
-          if (mem->alloc(head->need, &off)) {
-            head->off = off;
-            q = head;
-            queue.pop_front();
-            break;
-          }
-        }
+        q = admit_locked();
+        if (q) break;
         cv.wait(lk);
       }
       if (!q) break;
@@ -210,9 +220,14 @@ pw_status pw_server_create(const pw_server_cfg* cfg, pw_server** out) {
     s->cfg = *cfg;
     s->t0 = std::chrono::steady_clock::now();
     s->mem.reset(new Range(cfg->arena_bytes / kAlign * kAlign));
-    if (!(cfg->flags & PW_SERVER_DRY_RUN) && hipGetDevice(&s->device) != hipSuccess) {
-      delete s;
-      return PW_EDEVICE;
+    if (!(cfg->flags & PW_SERVER_DRY_RUN)) {
+      if (hipGetDevice(&s->device) != hipSuccess ||
+          hipEventCreateWithFlags(&s->start_ev, hipEventDisableTiming) != hipSuccess ||
+          hipEventRecord(s->start_ev, static_cast<hipStream_t>(cfg->hip_stream)) != hipSuccess) {
+        if (s->start_ev) hipEventDestroy(s->start_ev);
+        delete s;
+        return PW_EDEVICE;
+      }
     }
     for (int i = 0; i < cfg->max_slots; ++i) s->workers.emplace_back(&pw_server_s::worker, s, i);
   } catch (...) {
@@ -235,7 +250,7 @@ double pw_server_clock(const pw_server* s) { return s ? s->now() : NAN; }
 
 pw_status pw_submit(pw_server* s, const pw_request* r, double t_arrive, unsigned long long* ticket) {
   if (!s || !r || !ticket) return PW_EINVAL;
-  if (r->max_steps < 1 || r->degree < 1 || !(r->tol > 0.0) || r->nconv < 0) return PW_EINVAL;
+  if (r->max_steps < 1 || r->degree < 1 || r->degree > 1000 || !(r->tol > 0.0) || r->nconv < 0) return PW_EINVAL;
   pw_info info;
   pw_status st = pw_plan(&r->cell, &info);
   if (st != PW_OK) return st;
@@ -292,6 +307,7 @@ pw_status pw_poll(pw_server* s, unsigned long long ticket, pw_result* out) {
   out->t_arrive = q->t_arrive;
   out->t_admit = q->t_admit;
   out->t_done = q->t_done;
+  std::snprintf(out->message, sizeof(out->message), "%s", q->message.c_str());
   return PW_OK;
 }
 
@@ -304,6 +320,7 @@ pw_status pw_server_destroy(pw_server* s) {
   }
   s->cv.notify_all();
   for (auto& t : s->workers) t.join();
+  if (s->start_ev) hipEventDestroy(s->start_ev);
   delete s;
   return PW_OK;
 }

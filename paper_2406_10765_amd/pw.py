@@ -89,7 +89,7 @@ PW_SERVER_DRY_RUN = 1
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("arena_dev", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
-                ("flags", ctypes.c_uint)]
+                ("flags", ctypes.c_uint), ("hip_stream", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
@@ -100,7 +100,8 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("nbands", ctypes.c_int), ("steps", ctypes.c_int),
                 ("eig", ctypes.POINTER(ctypes.c_double)), ("resid", ctypes.POINTER(ctypes.c_double)),
-                ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+                ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("message", ctypes.c_char * 256)]
 
 
 class PWError(RuntimeError):
@@ -141,6 +142,8 @@ def lib() -> ctypes.CDLL:
                             P(ctypes.c_double), P(ctypes.c_int)]),
         "pw_eig_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, P(StepParams), P(ctypes.c_double),
                          P(ctypes.c_double), P(ctypes.c_double)]),
+        "pw_solve": ([vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                      ctypes.c_double, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int)]),
         "pw_spectrum_bound": ([vp, ctypes.c_int, ctypes.c_ulonglong, P(ctypes.c_double)]),
         "pw_set_timing": ([vp, ctypes.c_int]),
         "pw_get_stats": ([vp, P(PhaseStat)]),
@@ -386,14 +389,19 @@ class Handle:
         return {name: {"launches": int(arr[i].launches), "ms": float(arr[i].ms)} for i, name in enumerate(PHASES)}
 
     def solve(self, X, nocc: int, tol: float, degree: int = 10, max_steps: int = 200, b: Optional[float] = None):
-        """Repeat steps (first m = 0) until max residual over the lowest nocc bands <= tol."""
-        bmax = self.spectrum_bound() if b is None else b
-        eig, res, bnd = self.eig_step(X, 0, b=bmax)
-        steps = 1
-        while float(res[:nocc].max()) > tol and steps < max_steps:
-            eig, res, bnd = self.eig_step(X, degree, bnd[0], bnd[1], bmax)
-            steps += 1
-        return eig, res, steps, float(res[:nocc].max()) <= tol
+        """pw_solve: a degree-0 step, then degree-m steps until max residual over the lowest nocc bands
+        <= tol.  Returns (eig, resid, steps, converged)."""
+        nb, ld = self._check_block(X)
+        eig = np.empty(nb)
+        res = np.empty(nb)
+        steps = ctypes.c_int(0)
+        dp = ctypes.POINTER(ctypes.c_double)
+        st = lib().pw_solve(self._h, ctypes.c_void_p(X.data_ptr()), nb, ld, int(nocc), float(tol), int(degree),
+                            int(max_steps), float("nan") if b is None else float(b), eig.ctypes.data_as(dp),
+                            res.ctypes.data_as(dp), ctypes.byref(steps))
+        if st not in (PW_OK, PW_ENOTCONV):
+            _check(st, self._h)
+        return eig, res, int(steps.value), st == PW_OK
 
 
 def permutation_to(miller_from: np.ndarray, miller_to: np.ndarray) -> np.ndarray:
@@ -413,6 +421,7 @@ class Server:
 
     def __init__(self, arena_bytes: int, max_slots: int, dry_run: bool = False):
         self._arena = None
+        stream = None
         if dry_run:
             ptr = 1 << 20  # never dereferenced
         else:
@@ -420,11 +429,13 @@ class Server:
 
             self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
             ptr = self._arena.data_ptr()
+            stream = torch.cuda.current_stream().cuda_stream
         cfg = ServerCfg(ctypes.c_void_p(ptr), ctypes.c_size_t(int(arena_bytes)), int(max_slots),
-                        PW_SERVER_DRY_RUN if dry_run else 0)
+                        PW_SERVER_DRY_RUN if dry_run else 0, ctypes.c_void_p(stream))
         s = ctypes.c_void_p()
         _check(lib().pw_server_create(ctypes.byref(cfg), ctypes.byref(s)))
         self._s = s
+        self._nbands = {}
 
     def clock(self) -> float:
         return float(lib().pw_server_clock(self._s))
@@ -436,10 +447,13 @@ class Server:
         r = Request(d, seed, tol, max_steps, degree, nconv)
         t = ctypes.c_ulonglong()
         _check(lib().pw_submit(self._s, ctypes.byref(r), float(t_arrive), ctypes.byref(t)))
+        self._nbands[int(t.value)] = int(d.nbands)
         return int(t.value)
 
-    def poll(self, ticket: int, nbands: int):
-        """None while pending; else a dict with status, eig, resid, steps and times."""
+    def poll(self, ticket: int, nbands: Optional[int] = None):
+        """None while pending; else a dict with status, eig, resid, steps, times and message.  The
+        result buffers hold the request's own band count (the nbands argument is only a lower bound)."""
+        nbands = max(int(nbands or 0), self._nbands.get(int(ticket), 0))
         eig = np.empty(nbands)
         res = np.empty(nbands)
         out = Result()
@@ -451,7 +465,8 @@ class Server:
             return None
         _check(st)
         return {"status": out.status, "eig": eig[: out.nbands], "resid": res[: out.nbands], "steps": out.steps,
-                "t_arrive": out.t_arrive, "t_admit": out.t_admit, "t_done": out.t_done}
+                "t_arrive": out.t_arrive, "t_admit": out.t_admit, "t_done": out.t_done,
+                "message": out.message.decode(errors="replace")}
 
     def close(self):
         if getattr(self, "_s", None):

@@ -91,3 +91,68 @@ def test_serving_mix_recipe():
     for m in mix:
         assert m["cell"].nbands == 2 * m["cell"].natoms + 8
         assert m["cell"].ecut in (10.0, 15.0, 20.0)
+
+
+def _need(cell):
+    return footprint(cell)
+
+
+def test_concurrent_submitters_respect_slots_and_arena():
+    """Six client threads submit 30 requests of two sizes at once into an arena that holds only a
+    few: at every instant the admitted requests fit the arena and the slots, and all complete."""
+    import threading
+
+    small = [synth.silicon_cell((1, 1, 1), 10.0, disp_seed=300 + i) for i in range(15)]
+    large = [synth.silicon_cell((1, 1, 1), 20.0, disp_seed=400 + i) for i in range(15)]
+    cells = [c for pair in zip(small, large) for c in pair]
+    arena = int(2.5 * _need(large[0]))
+    srv = pw.Server(arena, max_slots=4, dry_run=True)
+    tickets = [None] * len(cells)
+
+    def client(k):
+        for i in range(k, len(cells), 6):
+            tickets[i] = srv.submit(cells[i], seed=i)
+
+    th = [threading.Thread(target=client, args=(k,)) for k in range(6)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    out = {}
+    t0 = time.time()
+    while len(out) < len(cells):
+        for i, t in enumerate(tickets):
+            if i not in out:
+                r = srv.poll(t, cells[i].nbands)
+                if r is not None:
+                    out[i] = r
+        assert time.time() - t0 < 30
+        time.sleep(0.002)
+    srv.close()
+    assert all(r["status"] == pw.PW_OK and r["message"] == "" for r in out.values())
+    iv = [(out[i]["t_admit"], out[i]["t_done"], _need(cells[i])) for i in range(len(cells))]
+    for a, _, _ in iv:
+        running = [(s, e, n) for s, e, n in iv if s <= a < e]
+        assert len(running) <= 4
+        assert sum(n for _, _, n in running) <= arena
+
+
+def test_small_requests_pass_a_large_head_a_bounded_number_of_times():
+    """A request that does not fit yet is passed by later, smaller ones, but only 16 times."""
+    big = synth.silicon_cell((1, 1, 2), 20.0, disp_seed=7)
+    small = [synth.silicon_cell((1, 1, 1), 10.0, disp_seed=500 + i) for i in range(40)]
+    nb_big, ns = _need(big), _need(small[0])
+    assert nb_big > 2 * ns
+    arena = nb_big + ns // 2  # the big one fits only when nothing else runs
+    srv = pw.Server(arena, max_slots=2, dry_run=True)
+    first = [srv.submit(small[i], seed=i) for i in range(2)]
+    tb = srv.submit(big, seed=99)
+    rest = [srv.submit(small[i], seed=i) for i in range(2, 40)]
+    res = wait_all(srv, first + [tb] + rest, big.nbands, timeout=60)
+    srv.close()
+    t_big = res[tb]["t_admit"]
+    passed = [t for t in rest if res[t]["t_admit"] < t_big]
+    assert res[tb]["status"] == pw.PW_OK
+    assert 1 <= len(passed) <= 16
+    # the ones behind it that did not pass were admitted after it
+    assert all(res[t]["t_admit"] >= t_big for t in rest if t not in passed)
