@@ -962,6 +962,8 @@ struct Engine {
     else if (p.nproj)
       PW_HIP(launch_beta_table<T>(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), p.natoms, p.L,
                                   p.beta_sigma, beta(), p.ldw, st));
+    // the block planes' words past the last plane wave stay zero from here on (the cn products read them)
+    if (p.yp_cols > 0) PW_HIP(launch_zero_plane_rows(yp_hi(), yp_lo(), p.ldw, p.npw, p.yp_cols, st));
     PW_HIP(hipStreamSynchronize(st));
     return PW_OK;
   }
@@ -1218,6 +1220,17 @@ pw_status pw_apply_h_noalloc(pw_handle* h, const void* X, void* HX, int nb, int 
   const bool timing = h->timing;
   h->timing = false;
   h->ws = h->scratch;
+  // the bf16 planes of the block live in the shared array: clear the words past the last plane
+  // wave, which the projection reads as zeros
+  if (h->plan.real_bytes == 4 && (h->plan.flags & PW_FLAG_BF16_KB) && h->plan.nproj > 0) {
+    unsigned int* yh = reinterpret_cast<unsigned int*>(h->ws + h->ws_yp);
+    if (launch_zero_plane_rows(yh, yh + (size_t)h->plan.ldw * w, h->plan.ldw, h->plan.npw, w, h->stream) !=
+        hipSuccess) {
+      h->ws = nullptr;
+      h->timing = timing;
+      return fail(h, PW_EDEVICE, "clearing the work array failed");
+    }
+  }
   if (h->plan.prec == PW_FP64)
     s = Engine<double>(h).apply_h(static_cast<const double2*>(X), static_cast<double2*>(HX), nb, ld, w);
   else

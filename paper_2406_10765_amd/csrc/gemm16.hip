@@ -31,6 +31,7 @@
 #include "bf16split.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "pipe_addr.hpp"
 
 namespace pw {
 
@@ -521,6 +522,117 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   } while (it < ntiles);
 }
 
+// Epilogue of the nn products for a wave's AT x BT blocks of 16 x 16 (accumulator layout of the
+// 16 x 16 MFMA: lane l holds rows 4 (l / 16) + r, column l % 16): out = update(acc) as EpiH says,
+// plus the bf16 planes of out when e.ph is set.
+template <int AT, int BT>
+__device__ __forceinline__ void epi_tile(const v4f16 (&cr)[AT][BT], const v4f16 (&ci)[AT][BT], int row_base,
+                                         int col_base, int lane, int M, int N, float2* out, long ldo,
+                                         const EpiH& e) {
+  const float* kin = static_cast<const float*>(e.kin);
+  const float2* Y = static_cast<const float2*>(e.Y);
+  const float2* Zl = static_cast<const float2*>(e.Zl);
+  const float2* Yp = static_cast<const float2*>(e.Yp);
+  const float alpha = (float)e.alpha, cc = (float)e.c, beta = (float)e.beta;
+  const float2 zero2 = make_float2(0.f, 0.f);
+  // one entry: v = accumulator, kr = kin[row], y, z, p = Y, Zl, Yp at (row, col)
+  auto update = [&](float2 v, float kr, float2 y, float2 z, float2 p) {
+    if (e.mode == 1) {
+      const float kc = kr - cc;
+      v.x = alpha * (kc * y.x + z.x + v.x);
+      v.y = alpha * (kc * y.y + z.y + v.y);
+      if (Yp) {
+        v.x -= beta * p.x;
+        v.y -= beta * p.y;
+      }
+    }
+    if (e.mode == 2) {
+      v.x += z.x;
+      v.y += z.y;
+    }
+    return v;
+  };
+#pragma unroll
+  for (int a = 0; a < AT; ++a)
+#pragma unroll
+    for (int b = 0; b < BT; ++b) {
+      // one 16 x 16 block at a time: no loads hoisted across blocks (bounded register use)
+      __builtin_amdgcn_sched_barrier(0);
+      const int col = col_base + b * 16 + (lane & 15);
+      const int row0 = row_base + a * 16 + 4 * (lane >> 4);
+      if (e.vec4 && col < N && row0 + 4 <= M) {
+        // the lane's four consecutive rows of one column: 16-byte accesses
+        float2 v[4], y[4], z[4], q[4];
+        float kr[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[r] = z[r] = q[r] = zero2;
+        if (e.mode == 1) {
+          const float4 k4 = *reinterpret_cast<const float4*>(kin + row0);
+          kr[0] = k4.x;
+          kr[1] = k4.y;
+          kr[2] = k4.z;
+          kr[3] = k4.w;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float4 yy = reinterpret_cast<const float4*>(Y + (long)col * e.ldy + row0)[h];
+            y[2 * h] = make_float2(yy.x, yy.y);
+            y[2 * h + 1] = make_float2(yy.z, yy.w);
+            if (Yp) {
+              const float4 pp = reinterpret_cast<const float4*>(Yp + (long)col * e.ldp + row0)[h];
+              q[2 * h] = make_float2(pp.x, pp.y);
+              q[2 * h + 1] = make_float2(pp.z, pp.w);
+            }
+          }
+        }
+        if (e.mode >= 1) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float4 zz = reinterpret_cast<const float4*>(Zl + (long)col * e.ldz + row0)[h];
+            z[2 * h] = make_float2(zz.x, zz.y);
+            z[2 * h + 1] = make_float2(zz.z, zz.w);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = update(make_float2(cr[a][b][r], ci[a][b][r]), kr[r], y[r], z[r], q[r]);
+        float4* oq = reinterpret_cast<float4*>(out + (long)col * ldo + row0);
+        oq[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+        oq[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+        if (e.ph) {
+          unsigned int wh[4], wl[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const Split2 sr = split(v[r].x), si = split(v[r].y);
+            wh[r] = pack(sr.h, si.h);
+            wl[r] = pack(sr.l, si.l);
+          }
+          const long o = (long)col * e.ldpl + row0;
+          *reinterpret_cast<uint4*>(static_cast<unsigned int*>(e.ph) + o) = uint4{wh[0], wh[1], wh[2], wh[3]};
+          *reinterpret_cast<uint4*>(static_cast<unsigned int*>(e.pl) + o) = uint4{wl[0], wl[1], wl[2], wl[3]};
+        }
+        continue;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + r;
+        if (row < M && col < N) {
+          const bool m1 = e.mode == 1;
+          const float2 y = m1 ? Y[(long)col * e.ldy + row] : zero2;
+          const float2 z = e.mode >= 1 ? Zl[(long)col * e.ldz + row] : zero2;
+          const float2 q = m1 && Yp ? Yp[(long)col * e.ldp + row] : zero2;
+          const float2 v = update(make_float2(cr[a][b][r], ci[a][b][r]), m1 ? kin[row] : 0.f, y, z, q);
+          out[(long)col * ldo + row] = v;
+          if (e.ph) {
+            const Split2 sr = split(v.x), si = split(v.y);
+            const long o = (long)col * e.ldpl + row;
+            static_cast<unsigned int*>(e.ph)[o] = pack(sr.h, si.h);
+            static_cast<unsigned int*>(e.pl)[o] = pack(sr.l, si.l);
+          }
+        }
+      }
+    }
+}
+
+
 // ------------------------------------------------------------------------------------------
 // nn: out = epilogue(A B) (fp32 data, bf16x3 products).
 // ------------------------------------------------------------------------------------------
@@ -615,105 +727,338 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     }
     __syncthreads();
   }
-  const float* kin = static_cast<const float*>(e.kin);
-  const float2* Y = static_cast<const float2*>(e.Y);
-  const float2* Zl = static_cast<const float2*>(e.Zl);
-  const float2* Yp = static_cast<const float2*>(e.Yp);
-  const float alpha = (float)e.alpha, cc = (float)e.c, beta = (float)e.beta;
-  const float2 zero2 = make_float2(0.f, 0.f);
-  // one entry: v = accumulator, kr = kin[row], y, z, p = Y, Zl, Yp at (row, col)
-  auto update = [&](float2 v, float kr, float2 y, float2 z, float2 p) {
-    if (e.mode == 1) {
-      const float kc = kr - cc;
-      v.x = alpha * (kc * y.x + z.x + v.x);
-      v.y = alpha * (kc * y.y + z.y + v.y);
-      if (Yp) {
-        v.x -= beta * p.x;
-        v.y -= beta * p.y;
+  epi_tile<AT, BT>(cr, ci, i0 + mo, j0 + no, lane, M, N, out, ldo, e);
+}
+
+// ------------------------------------------------------------------------------------------
+// Pipelined nn form on pre-split planes (the nonlocal product and the rotations).  Operand tiles
+// go from global memory straight into LDS (the direct global-to-LDS loads of gfx950, 16 bytes per
+// lane), three K tiles of 256 x 128 in a ring, so a tile's loads have two tiles of MFMA work to
+// arrive in.  One workgroup per CU (the ring takes 149 KB of LDS).  NW = 8 waves of 64 x 64
+// (two per SIMD, which hide each other's LDS reads) or NW = 4 waves of 128 x 64 (one per SIMD,
+// the next tile's fragments read into registers while the current ones are used).
+//   B (K-contiguous planes, the D P or coefficient words): lane i of a load of 16 columns fetches
+//     chunk (column, slot) with slot = i / 16 and column = (i % 16) ^ slot, so the LDS image is
+//     the chunk layout of chunk_of() and fragments are read lane-linearly without bank conflicts.
+//   A (M-contiguous planes, the projector or block words): one load per (plane, k) copies 256
+//     consecutive rows (1 KB) into a row of 260 words; a fragment is four 32-bit reads (k = 4 (l / 16)
+//     + j for row l % 16), whose four lane groups fall 16 banks apart.
+// Rows and columns beyond the operands are clamped to the last ones (their results are dropped;
+// pipe_addr.hpp holds the arithmetic, checked by a host test over every load).
+// ------------------------------------------------------------------------------------------
+constexpr int pTM = 256, pTN = 128, pST = 3;
+constexpr int pApitch = 260;                       // words per (plane, k) row of the A tile
+constexpr int pAbytes = 2 * hBK * pApitch * 4;     // 33,280 B
+constexpr int pBbytes = 2 * pTN * hBK * 4;         // 16,384 B
+constexpr int pStage = pAbytes + pBbytes;
+
+__device__ __forceinline__ void dma16(const unsigned int* g, void* l) {
+  __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+}
+// s_waitcnt vmcnt(N) alone (expcnt and lgkmcnt left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xc07f); }  // lgkmcnt(0)
+
+// Address of the 16 bytes a lane loads: a wave-uniform base plus a per-lane 32-bit byte offset.
+__device__ __forceinline__ const unsigned int* at_off(const unsigned int* base, unsigned int byte_off) {
+  return reinterpret_cast<const unsigned int*>(reinterpret_cast<const unsigned char*>(base) + byte_off);
+}
+
+// K-contiguous tile: NC columns x 16 k, hi and lo planes, 2 NC / 16 loads of 1 KB (16 columns
+// each), this wave issuing those with index wave, wave + NW, ...  (the B tile, and the A tile of
+// the cn form).  The columns a lane loads are the same for every K tile; off[q] is computed once.
+template <int NC, int NW>
+struct KTile {
+  static constexpr int G = NC / 16, Q = 2 * G / NW;
+  unsigned int off[Q];
+  __device__ __forceinline__ void offsets(long ld, int c0, int ncols, int wave, int lane) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) off[q] = pipe_koff_bytes(c0, (wave + NW * q) % G, ncols, ld, lane);
+  }
+  __device__ __forceinline__ void load(const unsigned int* __restrict__ H, const unsigned int* __restrict__ L, long ld,
+                                       int c0, int ncols, int k0, unsigned char* dst, int wave) const {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = wave + NW * q, pl = j / G, g = j % G;
+      const unsigned int* base = (pl ? L : H) + (long)pipe_kbase_col(c0, g, ncols) * ld + k0;
+      dma16(at_off(base, off[q]), dst + (pl * G + g) * 1024);
+    }
+  }
+};
+// M-contiguous A tile (nn form): 256 rows x 16 k, hi and lo planes, 32 loads of 1 KB (one per
+// plane and k).
+template <int NW>
+struct ATile {
+  static constexpr int Q = 32 / NW;
+  unsigned int off;
+  __device__ __forceinline__ void offsets(long ld, int r0, int lane) { off = pipe_moff_bytes(ld, r0, lane); }
+  __device__ __forceinline__ void load(const unsigned int* __restrict__ H, const unsigned int* __restrict__ L, long ld,
+                                       int r0, int k0, unsigned char* dst, int wave) const {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = wave + NW * q, pl = j >> 4, k = j & 15;
+      const unsigned int* base = (pl ? L : H) + (long)(k0 + k) * ld + r0;
+      dma16(at_off(base, off), dst + (pl * 16 + k) * (pApitch * 4));
+    }
+  }
+};
+
+// A fragment (rows ra .. ra + 15 of the tile) from the A tile plane.
+__device__ __forceinline__ v8bf frag_m(const unsigned int* plane, int ra, int lane) {
+  const int row = ra + (lane & 15), kg = lane >> 4;
+  uint4 u;
+  u.x = plane[(4 * kg + 0) * pApitch + row];
+  u.y = plane[(4 * kg + 1) * pApitch + row];
+  u.z = plane[(4 * kg + 2) * pApitch + row];
+  u.w = plane[(4 * kg + 3) * pApitch + row];
+  return __builtin_bit_cast(v8bf, u);
+}
+
+// The fragments a wave needs from one K tile: AT A blocks and 4 B blocks, hi and lo.  CN: the cn
+// form (A tile in the chunk layout, AB bytes of A before the B tile), else the nn form.
+template <int AT, bool CN>
+struct TileFrags {
+  static constexpr int AB = CN ? 2 * pTM * hBK * 4 : pAbytes;
+  v8bf ah[AT], al[AT], bh[4], bl[4];
+  __device__ __forceinline__ void read(const unsigned char* st, int ra0, int cb0, int lane) {
+    const uint4* Bh = reinterpret_cast<const uint4*>(st + AB);
+    const uint4* Bl = Bh + pTN * 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      bh[b] = frag(Bh, cb0 + b * 16, lane);
+      bl[b] = frag(Bl, cb0 + b * 16, lane);
+    }
+#pragma unroll
+    for (int a = 0; a < AT; ++a) {
+      if constexpr (CN) {
+        const uint4* Ah = reinterpret_cast<const uint4*>(st);
+        ah[a] = frag(Ah, ra0 + a * 16, lane);
+        al[a] = frag(Ah + pTM * 4, ra0 + a * 16, lane);
+      } else {
+        const unsigned int* Ah = reinterpret_cast<const unsigned int*>(st);
+        ah[a] = frag_m(Ah, ra0 + a * 16, lane);
+        al[a] = frag_m(Ah + hBK * pApitch, ra0 + a * 16, lane);
       }
     }
-    if (e.mode == 2) {
-      v.x += z.x;
-      v.y += z.y;
+  }
+  // Re C += A' B, Im C += A'' B with the A words rotated (only the B fragments stay in registers
+  // across the blocks):
+  //   nn  C = A B:    A'' = (ai, -ar), B as stored (br, -bi)
+  //   cn  C = A^H B:  A'' = (-ai, ar), B as stored (br, bi)
+  template <int NTERM>
+  __device__ __forceinline__ void mfma(v4f16 (&cr)[AT][4], v4f16 (&ci)[AT][4]) const {
+#pragma unroll
+    for (int a = 0; a < AT; ++a) {
+      const v8bf h = ah[a], l = al[a];
+      const v8bf h2 = CN ? swapneg_lo(h) : swapneg_hi(h);
+      const v8bf l2 = CN ? swapneg_lo(l) : swapneg_hi(l);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        cr[a][b] = mma16(h, bh[b], cr[a][b]);
+        ci[a][b] = mma16(h2, bh[b], ci[a][b]);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        cr[a][b] = mma16(h, bl[b], cr[a][b]);
+        ci[a][b] = mma16(h2, bl[b], ci[a][b]);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        cr[a][b] = mma16(l, bh[b], cr[a][b]);
+        ci[a][b] = mma16(l2, bh[b], ci[a][b]);
+      }
+      if constexpr (NTERM == 4) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          cr[a][b] = mma16(l, bl[b], cr[a][b]);
+          ci[a][b] = mma16(l2, bl[b], ci[a][b]);
+        }
+      }
     }
-    return v;
-  };
+  }
+};
+
+// out = epilogue(A B), A M-contiguous planes (lda words per k), B K-contiguous (br, -bi) planes
+// (ldb words per column).  K a multiple of 16.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4))) void k_gemm_nn_pipe(
+    const unsigned int* __restrict__ Ah, const unsigned int* __restrict__ Al, long lda,
+    const unsigned int* __restrict__ Bh, const unsigned int* __restrict__ Bl, long ldb, int M, int N, int K,
+    int tiles_n, float2* out, long ldo, EpiH e) {
+  constexpr int WM = NW / 2, RT = pTM / WM, AT = RT / 16;  // waves along M, rows per wave
+  constexpr int LPW = ATile<NW>::Q + KTile<pTN, NW>::Q;    // direct loads per wave per K tile
+  constexpr bool DB = NW == 4;                             // fragments double-buffered in registers
+  __shared__ __align__(16) unsigned char smem[pST * pStage];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t = xcd_tile16(blockIdx.x, gridDim.x);
+  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  const int i0 = tm * pTM, j0 = tn * pTN;
+  const int wm = wave % WM, wn = wave / WM;
+  const int ra0 = wm * RT, cb0 = wn * 64;
+  v4f16 cr[AT][4], ci[AT][4];
 #pragma unroll
   for (int a = 0; a < AT; ++a)
 #pragma unroll
-    for (int b = 0; b < BT; ++b) {
-      const int col = j0 + no + b * 16 + (lane & 15);
-      const int row0 = i0 + mo + a * 16 + 4 * (lane >> 4);
-      if (e.vec4 && col < N && row0 + 4 <= M) {
-        // the lane's four consecutive rows of one column: 16-byte accesses
-        float2 v[4], y[4], z[4], q[4];
-        float kr[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int r = 0; r < 4; ++r) y[r] = z[r] = q[r] = zero2;
-        if (e.mode == 1) {
-          const float4 k4 = *reinterpret_cast<const float4*>(kin + row0);
-          kr[0] = k4.x;
-          kr[1] = k4.y;
-          kr[2] = k4.z;
-          kr[3] = k4.w;
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const float4 yy = reinterpret_cast<const float4*>(Y + (long)col * e.ldy + row0)[h];
-            y[2 * h] = make_float2(yy.x, yy.y);
-            y[2 * h + 1] = make_float2(yy.z, yy.w);
-            if (Yp) {
-              const float4 pp = reinterpret_cast<const float4*>(Yp + (long)col * e.ldp + row0)[h];
-              q[2 * h] = make_float2(pp.x, pp.y);
-              q[2 * h + 1] = make_float2(pp.z, pp.w);
-            }
-          }
-        }
-        if (e.mode >= 1) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const float4 zz = reinterpret_cast<const float4*>(Zl + (long)col * e.ldz + row0)[h];
-            z[2 * h] = make_float2(zz.x, zz.y);
-            z[2 * h + 1] = make_float2(zz.z, zz.w);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = update(make_float2(cr[a][b][r], ci[a][b][r]), kr[r], y[r], z[r], q[r]);
-        float4* oq = reinterpret_cast<float4*>(out + (long)col * ldo + row0);
-        oq[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
-        oq[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
-        if (e.ph) {
-          unsigned int wh[4], wl[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const Split2 sr = split(v[r].x), si = split(v[r].y);
-            wh[r] = pack(sr.h, si.h);
-            wl[r] = pack(sr.l, si.l);
-          }
-          const long o = (long)col * e.ldpl + row0;
-          *reinterpret_cast<uint4*>(static_cast<unsigned int*>(e.ph) + o) = uint4{wh[0], wh[1], wh[2], wh[3]};
-          *reinterpret_cast<uint4*>(static_cast<unsigned int*>(e.pl) + o) = uint4{wl[0], wl[1], wl[2], wl[3]};
-        }
-        continue;
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + r;
-        if (row < M && col < N) {
-          const bool m1 = e.mode == 1;
-          const float2 y = m1 ? Y[(long)col * e.ldy + row] : zero2;
-          const float2 z = e.mode >= 1 ? Zl[(long)col * e.ldz + row] : zero2;
-          const float2 q = m1 && Yp ? Yp[(long)col * e.ldp + row] : zero2;
-          const float2 v = update(make_float2(cr[a][b][r], ci[a][b][r]), m1 ? kin[row] : 0.f, y, z, q);
-          out[(long)col * ldo + row] = v;
-          if (e.ph) {
-            const Split2 sr = split(v.x), si = split(v.y);
-            const long o = (long)col * e.ldpl + row;
-            static_cast<unsigned int*>(e.ph)[o] = pack(sr.h, si.h);
-            static_cast<unsigned int*>(e.pl)[o] = pack(sr.l, si.l);
-          }
-        }
-      }
+    for (int b = 0; b < 4; ++b) cr[a][b] = ci[a][b] = v4f16{0, 0, 0, 0};
+  const int ntiles = K / hBK;
+  ATile<NW> ta;
+  KTile<pTN, NW> tb;
+  ta.offsets(lda, i0, lane);
+  tb.offsets(ldb, j0, N, wave, lane);
+  auto issue = [&](int kt) {
+    unsigned char* st = smem + (kt % pST) * pStage;
+    ta.load(Ah, Al, lda, i0, kt * hBK, st, wave);
+    tb.load(Bh, Bl, ldb, j0, N, kt * hBK, st + pAbytes, wave);
+  };
+  if constexpr (DB) {
+    // Iteration it: wait for tile it + 1, barrier (every wave has read tile it into registers, so
+    // its stage is free), issue tile it + 3 into it, read tile it + 1's fragments, then run tile
+    // it's MFMAs while those reads land.
+    for (int p = 0; p < pST && p < ntiles; ++p) issue(p);
+    TileFrags<AT, false> cur, nxt;
+    if (ntiles > 0) {
+      if (ntiles > 2) wait_vm<2 * LPW>();
+      else if (ntiles > 1) wait_vm<LPW>();
+      else wait_vm<0>();
+      __builtin_amdgcn_s_barrier();
+      cur.read(smem, ra0, cb0, lane);
     }
+    for (int it = 0; it < ntiles; ++it) {
+      const bool more = it + 1 < ntiles;
+      if (more) {
+        if (it + 2 < ntiles) wait_vm<LPW>();
+        else wait_vm<0>();
+        wait_lds();
+        __builtin_amdgcn_s_barrier();
+        if (it + 3 < ntiles) issue(it + 3);
+        nxt.read(smem + ((it + 1) % pST) * pStage, ra0, cb0, lane);
+      }
+      cur.template mfma<3>(cr, ci);
+      if (more) cur = nxt;
+    }
+  } else {
+    // Iteration it: wait for tile it (tile it + 1 may be in flight), barrier (every wave is done
+    // with tile it - 1), issue tile it + 2 into tile it - 1's stage, read and use tile it.
+    if (ntiles > 0) issue(0);
+    if (ntiles > 1) issue(1);
+    for (int it = 0; it < ntiles; ++it) {
+      if (it + 1 < ntiles) wait_vm<LPW>();
+      else wait_vm<0>();
+      wait_lds();
+      __builtin_amdgcn_s_barrier();
+      if (it + 2 < ntiles) issue(it + 2);
+      TileFrags<AT, false> f;
+      f.read(smem + (it % pST) * pStage, ra0, cb0, lane);
+      f.template mfma<3>(cr, ci);
+    }
+  }
+  epi_tile<AT, 4>(cr, ci, i0 + ra0, j0 + cb0, lane, M, N, out, ldo, e);
+}
+
+// cn on planes, pipelined like the nn form: part[s] = A^H B over K chunk s, A (256-column tiles)
+// and B (128-column tiles) both K-contiguous planes, NW = 8 waves of 64 x 64; fp32 accumulation
+// moved to the fp64 partial every hFlush tiles (one owner per partial entry, no atomics).  The K
+// range is covered by whole tiles of 16: the words of each column from K up to its leading
+// dimension must be zero in both operands (the launcher checks that the leading dimensions reach
+// K rounded up to 16; the planes this library writes hold zeros there).
+template <int NTERM>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_cn_pipe(
+    const unsigned int* __restrict__ Ah, const unsigned int* __restrict__ Al, long lda,
+    const unsigned int* __restrict__ Bh, const unsigned int* __restrict__ Bl, long ldb, int M, int N, int K,
+    int kchunk, int tiles_m, int tiles_n, double2* __restrict__ part) {
+  constexpr int NW = 8, AT = 4;
+  constexpr int AB = TileFrags<AT, true>::AB, SB = AB + pBbytes;
+  constexpr int LPW = KTile<pTM, NW>::Q + KTile<pTN, NW>::Q;
+  __shared__ __align__(16) unsigned char smem[pST * SB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t = xcd_tile16(blockIdx.x, gridDim.x);
+  const int sp = t / (tiles_m * tiles_n);
+  const int tr = t - sp * tiles_m * tiles_n;
+  const int tm = tr / tiles_n, tn = tr - tm * tiles_n;
+  const int i0 = tm * pTM, j0 = tn * pTN;
+  const int kb = sp * kchunk, ke = min(K, kb + kchunk);
+  const int ra0 = (wave & 3) * 64, cb0 = (wave >> 2) * 64;
+  const int ntiles = ke > kb ? (ke - kb + hBK - 1) / hBK : 0;
+  KTile<pTM, NW> ta;
+  KTile<pTN, NW> tb;
+  ta.offsets(lda, i0, M, wave, lane);
+  tb.offsets(ldb, j0, N, wave, lane);
+  auto issue = [&](int kt) {
+    unsigned char* st = smem + (kt % pST) * SB;
+    const int k0 = kb + kt * hBK;
+    ta.load(Ah, Al, lda, i0, M, k0, st, wave);
+    tb.load(Bh, Bl, ldb, j0, N, k0, st + AB, wave);
+  };
+  if (ntiles > 0) issue(0);
+  if (ntiles > 1) issue(1);
+  v4f16 cr[AT][4], ci[AT][4];
+  bool stored = false;
+  int it = 0;
+  do {
+    const int fend = min(ntiles, it + hFlush);
+#pragma unroll
+    for (int a = 0; a < AT; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cr[a][b] = ci[a][b] = v4f16{0, 0, 0, 0};
+    for (; it < fend; ++it) {
+      // tile it has landed (tile it + 1 may be in flight); every wave is done with tile it - 1,
+      // whose stage receives tile it + 2
+      if (it + 1 < ntiles) wait_vm<LPW>();
+      else wait_vm<0>();
+      wait_lds();
+      __builtin_amdgcn_s_barrier();
+      if (it + 2 < ntiles) issue(it + 2);
+      TileFrags<AT, true> f;
+      f.read(smem + (it % pST) * SB, ra0, cb0, lane);
+      f.template mfma<NTERM>(cr, ci);
+    }
+#pragma unroll
+    for (int a = 0; a < AT; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int col = j0 + cb0 + b * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + ra0 + a * 16 + 4 * (lane >> 4) + r;
+          if (row < M && col < N) {
+            double2* dst = part + ((long)sp * N + col) * M + row;
+            double2 v;
+            v.x = (double)cr[a][b][r];
+            v.y = (double)ci[a][b][r];
+            if (stored) {
+              const double2 o = *dst;
+              v.x += o.x;
+              v.y += o.y;
+            }
+            *dst = v;
+          }
+        }
+      }
+    stored = true;
+  } while (it < ntiles);
+}
+
+// Zero words [r0, ld) of each of cols columns of a pair of planes (the padding the pipelined cn
+// form reads past the last row).
+__global__ void k_zero_plane_rows(unsigned int* __restrict__ H, unsigned int* __restrict__ L, long ld, int r0,
+                                  int cols) {
+  const long pad = ld - r0;
+  PW_GRID_STRIDE(idx, pad * cols) {
+    const long c = idx / pad, r = r0 + (idx - c * pad);
+    H[c * ld + r] = 0u;
+    L[c * ld + r] = 0u;
+  }
+}
+
+hipError_t launch_zero_plane_rows(unsigned int* H, unsigned int* L, long ld, int r0, int cols, hipStream_t s) {
+  const long n = (ld - r0) * (long)cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_plane_rows, dim3(stride_blocks(n)), dim3(256), 0, s, H, L, ld, r0, cols);
+  return hipGetLastError();
 }
 
 // hi/lo planes of fp32 complex columns: word (re, im) of bf16(x) and of bf16(x - hi).
@@ -858,11 +1203,32 @@ int gemm_cn_bf16_planes_tiles(int M, int N) {
   return planes_wide(M) ? ceil_div(M, hWM) * ceil_div(N, hTN) : gemm_cn_bf16_tiles(M, N);
 }
 
+
+// The pipelined forms need 16-byte aligned planes with leading dimensions a multiple of 4 words,
+// and enough work to fill the chip with 256 x 128 tiles.
+constexpr int kPipeWaves = 8;
+static bool use_pipe(const void* a, const void* a2, long lda, const void* b, const void* b2, long ldb, long M,
+                     long N) {
+  return ok_planes(a, a2, lda) && ok_planes(b, b2, ldb) && lda >= 4 && ldb >= 4 && M * N >= (1L << 20);
+}
+
 hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
                                         const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
                                         int nsplit, double2* part, hipStream_t s, int nterm) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int kchunk = cn_chunk(K, nsplit);
+  const long kpad = (long)ceil_div(K, hBK) * hBK;  // the last tile reads the zero words up to here
+  if (kpad <= lda && kpad <= ldb && use_pipe(Ahi, Alo, lda, Bhi, Blo, ldb, M, N)) {
+    const int tm = ceil_div(M, pTM), tn = ceil_div(N, pTN);
+    dim3 grid(tm * tn * nsplit);
+    if (nterm == 4)
+      hipLaunchKernelGGL(k_gemm_cn_pipe<4>, grid, dim3(512), 0, s, Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, kchunk, tm,
+                         tn, part);
+    else
+      hipLaunchKernelGGL(k_gemm_cn_pipe<3>, grid, dim3(512), 0, s, Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, kchunk, tm,
+                         tn, part);
+    return hipGetLastError();
+  }
   const bool vec = ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb);
   const void* a0 = Ahi;
   const void* a1 = Alo;
@@ -938,6 +1304,12 @@ hipError_t launch_gemm_nn_bf16x3_planes(const unsigned int* Ahi, const unsigned 
                                         float2* out, long ldo, const EpiH& e, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const EpiH ev = epi_vec4(e, out, ldo);
+  if (K % hBK == 0 && K > 0 && lda >= M && use_pipe(Ahi, Alo, lda, Bhi, Blo, ldb, M, N)) {
+    const int tm = ceil_div(M, pTM), tn = ceil_div(N, pTN);
+    hipLaunchKernelGGL(k_gemm_nn_pipe<kPipeWaves>, dim3(tm * tn), dim3(64 * kPipeWaves), 0, s, Ahi, Alo, lda, Bhi, Blo,
+                       ldb, M, N, K, tn, out, ldo, ev);
+    return hipGetLastError();
+  }
   const int tm = ceil_div(M, hTM), tn = ceil_div(N, hTN);
   const bool vec = ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb);
   dim3 grid(tm * tn);

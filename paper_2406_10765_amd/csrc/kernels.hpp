@@ -123,6 +123,7 @@ template <typename T>
 hipError_t launch_gemm_nn(const cplx<T>* A, long lda, const cplx<T>* B, long ldb, int M, int N, int K,
                           cplx<T>* out, long ldo, const EpiH& e, hipStream_t s);
 
+
 // Split-precision (bf16x3) forms of the two GEMM shapes, fp32 data.
 int gemm_cn_bf16_tiles(int M, int N);
 // tiles of the projection product with pre-split planes (launch_gemm_cn_bf16x3_planes)
@@ -138,6 +139,11 @@ hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, lon
 hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
                                         const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
                                         int nsplit, double2* part, hipStream_t s, int nterm = 3);
+// The cn form on planes reads the words of each column from K up to the next multiple of 16 when
+// both leading dimensions reach that far: those words must be zero.  The projector planes are
+// written with zeros there; the block planes are cleared once (at set-up, or by
+// launch_zero_plane_rows for planes in other memory) and never written there afterwards.
+hipError_t launch_zero_plane_rows(unsigned int* H, unsigned int* L, long ld, int r0, int cols, hipStream_t s);
 // hi/lo planes (one (re, im) word per entry, leading dimension ldp) of rows x cols fp32 complex.
 hipError_t launch_split_planes(const float2* X, long ldx, int rows, int cols, unsigned int* H, unsigned int* L,
                                long ldp, hipStream_t s);
