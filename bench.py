@@ -455,46 +455,57 @@ def main():
         if roofline["traffic"] is not None:
             roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
-    # ---- LOBPCG step on the same cell (three H applications and a 3 N_b Rayleigh-Ritz) ------
+    # ---- LOBPCG and PPCG steps on the same cell ----------------------------------------------
+    # LOBPCG: three H applications and a Rayleigh-Ritz of size 3 N_b (the kept part of the span
+    # when [X R P] is numerically dependent); PPCG: three H applications of N_b columns and a
+    # Rayleigh-Ritz of size N_b plus one 3 x 3 problem per column.
     lobpcg = None
+    ppcg = None
     if not big and not args.no_lobpcg:
         try:
             hl = pw.Handle(cell, pw.PW_MIXED, flags=mflags | pw.PW_FLAG_LOBPCG)
             Xl = (snap if snap is not None else X).clone()
             Pl = hl.empty_block(nb)
             hl.lobpcg_step(Xl, Pl, False)
-            # steps with search directions; when the three-block Gram matrix is numerically singular
-            # the entry point redoes the step on [X R] (counted as a restart)
-            times, sizes, restarts = [], [], 0
-            have_p = True
+            times, kept, failures = [], [], 0
             for _ in range(3):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 info = {}
                 try:
-                    el, rl = hl.lobpcg_step(Xl, Pl, have_p, info)
-                except pw.PWError:
-                    restarts += 1
-                    have_p = False
+                    el, rl = hl.lobpcg_step(Xl, Pl, True, info)
+                except pw.PWError as exc:
+                    failures += 1
+                    log(f"lobpcg step failed: {exc}")
                     continue
                 times.append(time.perf_counter() - t0)
-                redone = bool(info.get("restarted"))
-                restarts += int(redone)
-                sizes.append(3 * nb if have_p and not redone else 2 * nb)
-                have_p = True
+                kept.append(info.get("kept"))
             if times:
-                lobpcg = {"ms_per_step": [round(1000.0 * t, 2) for t in times], "rayleigh_ritz_sizes": sizes,
-                          "restarts_without_directions": restarts,
-                          "rayleigh_ritz_note": "a restarted step applied H three times but solved on [X R]",
+                lobpcg = {"ms_per_step": [round(1000.0 * t, 2) for t in times],
+                          "rayleigh_ritz_basis": 3 * nb, "rayleigh_ritz_kept": kept,
+                          "restarts_without_directions": failures,
                           "max_resid_occ_input": float(rl[: cell.nocc].max()),
-                          "what": "mixed-precision LOBPCG steps from the filter's starting block"}
+                          "what": "mixed-precision LOBPCG steps with search directions, from the filter's "
+                                  "starting block after one step without them"}
+                log(f"lobpcg: ms/step {lobpcg['ms_per_step']}, Rayleigh-Ritz kept {kept} of {3 * nb}")
+            Xl.copy_((snap if snap is not None else X))
+            hl.ppcg_step(Xl, Pl, False)
+            ptimes, pres = [], None
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ep, pres = hl.ppcg_step(Xl, Pl, True)
+                ptimes.append(time.perf_counter() - t0)
+            ppcg = {"ms_per_step": [round(1000.0 * t, 2) for t in ptimes],
+                    "max_resid_occ_input": float(pres[: cell.nocc].max()),
+                    "what": "mixed-precision PPCG steps with search directions, from the filter's starting "
+                            "block after one step without them"}
+            log(f"ppcg: ms/step {ppcg['ms_per_step']}")
             del hl, Xl, Pl
             torch.cuda.empty_cache()
-            if lobpcg:
-                log(f"lobpcg: ms/step {lobpcg['ms_per_step']}, Rayleigh-Ritz sizes {sizes}, restarts {restarts}")
         except Exception as exc:  # a failed side measurement must not lose the headline line
             lobpcg = {"error": str(exc)}
-            log(f"lobpcg measurement failed: {exc}")
+            log(f"lobpcg/ppcg measurement failed: {exc}")
 
     # ---- FP64 form from the same block and bounds -----------------------------------------
     fp64 = None
@@ -598,7 +609,7 @@ def main():
         "band_apps_per_sec": band_apps,
         "apply_h_band_apps_per_sec": apply_rate,
         "density": density,
-        "lobpcg": lobpcg,
+        "lobpcg": lobpcg, "ppcg": ppcg,
         "device": device_info(torch, minfo),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -194,6 +194,14 @@ pw_status pw_apply_h_noalloc(pw_handle *h, const void *X_dev, void *HX_dev, int 
 pw_status pw_density(pw_handle *h, const void *X_dev, int nb, int ld, const double *occ_host, void *rho_dev);
 
 /*
+ * Basis directions dropped by the Rayleigh-Ritz of pw_lobpcg_step and pw_ppcg_step when a basis
+ * Gram matrix is singular: those whose eigenvalue in the unit-diagonal scaling of the Gram matrix
+ * is at most this fraction of the largest (FP64 handles; FP32 and split-precision handles).
+ */
+#define PW_DROP_TOL_FP64 1e-10
+#define PW_DROP_TOL_MIXED 1e-5
+
+/*
  * One LOBPCG step (locally optimal block preconditioned conjugate gradient, one of the inner
  * eigensolvers the paper names in Section II-A) on X (in/out, nb columns) with search
  * directions P (in/out, nb columns, same ld; its input is ignored when have_p == 0):
@@ -201,17 +209,40 @@ pw_status pw_density(pw_handle *h, const void *X_dev, int nb, int ld, const doub
  *   R = T (W - X diag(theta)), T = diag(1 / (1 + |G|^2/2)) (diagonal preconditioner),
  *   the columns of R and P scaled to unit norm,
  *   Rayleigh-Ritz of H on Z = [X R P] (or [X R]): [S | H_s] = Z^H [Z | HZ] and the FP64
- *   generalised eigensolve H_s C = S C Lambda of size 3 nb (2 nb),
+ *   generalised eigensolve H_s C = S C Lambda of size k = 3 nb (2 nb),
  *   X' = Z C_1 (C_1: the nb lowest Ritz vectors), P' = [R P] times the R and P rows of C_1.
- * eig (host, nb): the nb lowest Ritz values; resid (host, nb): ||w_i - theta_i x_i|| of the
- * input block.  Three H applications per step (X, R, P).  When the basis Gram matrix with P
- * fails the Cholesky test (the directions have become numerically dependent), the step is redone
- * on [X R] alone and *restarted (optional, may be NULL) is set to 1, else 0.  Needs a handle
- * planned with PW_FLAG_LOBPCG (PW_EINVAL otherwise); PW_ENOTPD when even [X R] is dependent.
+ * When S fails the Cholesky test (the directions have become numerically dependent), the
+ * Rayleigh-Ritz runs on the part of span Z that a truncated SVQB basis keeps: S scaled to unit
+ * diagonal, diagonalised, and the directions with eigenvalue <= PW_DROP_TOL_* times the largest
+ * dropped; *kept (optional, may be NULL) receives the dimension of the span used (k when nothing
+ * was dropped).  eig (host, nb): the nb lowest Ritz values; resid (host, nb): ||w_i - theta_i x_i||
+ * of the input block.  Three H applications per step (X, R, P).  Needs a handle planned with
+ * PW_FLAG_LOBPCG (PW_EINVAL otherwise); PW_ENOTPD when fewer than nb directions are kept.
  * Synchronises before returning.
  */
 pw_status pw_lobpcg_step(pw_handle *h, void *X_dev, void *P_dev, int nb, int ld, int have_p, double *eig,
-                         double *resid, int *restarted);
+                         double *resid, int *kept);
+
+/*
+ * One PPCG step (projected preconditioned conjugate gradient, Vecharynski, Yang and Pask; one of
+ * the inner eigensolvers the paper names in Section II-A) on X (in/out, nb columns) with search
+ * directions P (in/out, same shape; its input ignored when have_p == 0):
+ *   Rayleigh-Ritz on span X ([S | H_s] = X^H [X | HX], FP64 eigensolve of size nb):
+ *     X <- X C (Ritz vectors, Ritz values Lambda), P <- P C (the directions follow their columns);
+ *   R = H X - X Lambda (resid: its column norms), W = T R (the preconditioner of pw_lobpcg_step);
+ *   W <- W - X (X^H W), P <- P - X (X^H P);
+ *   per column j, Rayleigh-Ritz of H on span{x_j, w_j, p_j} (span{x_j, w_j} without P; the
+ *     entry for x_j is lambda_j; a dependent vector is dropped as in pw_lobpcg_step, FP64, one
+ *     thread per column): the lowest Ritz vector a x_j + b w_j + g p_j with a real and >= 0;
+ *   X <- a X + b W + g P, P <- b W + g P (column by column).
+ * eig (host, nb): Lambda; resid (host, nb): ||H x_j - lambda_j x_j|| of the Ritz vectors.  The
+ * output X is not orthonormal; the next step's Rayleigh-Ritz makes it so.  Three H applications
+ * of nb columns per step (X, W, P), one Rayleigh-Ritz of size nb.  Needs a handle planned with
+ * PW_FLAG_LOBPCG (the same buffers); PW_ENOTPD when X is rank-deficient.  Synchronises before
+ * returning.
+ */
+pw_status pw_ppcg_step(pw_handle *h, void *X_dev, void *P_dev, int nb, int ld, int have_p, double *eig,
+                       double *resid);
 
 /*
  * One block-eigensolver step on X (in/out, nb columns, ld >= npw):

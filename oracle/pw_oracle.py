@@ -443,22 +443,65 @@ def eig_step(hop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, m: int, a_l
     return StepResult(eig=lam, X=Xn, HX=Wn, resid=resid, a_lo=float(lam[0]), a=float(lam[-1]))
 
 
+def svqb_rayleigh_ritz(S: np.ndarray, Hs: np.ndarray, drop_tol: float):
+    """Rayleigh-Ritz on the span of a basis whose Gram matrix S may be singular (S, Hs Hermitian).
+
+    The basis is scaled to unit columns (D = diag(S)^-1/2; a zero column gets weight 0), the
+    scaled Gram matrix is diagonalised, D S D = U diag(sigma) U^H, and the directions with
+    sigma <= drop_tol * max(sigma) are dropped: T = D U_kept diag(sigma_kept)^-1/2 spans the kept
+    part of the span with T^H S T = I (the SVQB orthonormalisation of Stathopoulos and Wu, here
+    with truncation).  Then T^H Hs T = V diag(lam) V^H and C = T V, so that C^H S C = I and
+    C^H Hs C = diag(lam).  Returns lam (ascending), C (k x k_kept) and k_kept.
+    """
+    dS = np.real(np.diag(S)).copy()
+    d = np.where(dS > 0.0, 1.0 / np.sqrt(np.where(dS > 0.0, dS, 1.0)), 0.0)
+    St = d[:, None] * S * d[None, :]
+    St = 0.5 * (St + St.conj().T)
+    sig, U = np.linalg.eigh(St)
+    keep = sig > drop_tol * sig.max()
+    T = d[:, None] * U[:, keep] / np.sqrt(sig[keep])[None, :]
+    A = T.conj().T @ Hs @ T
+    A = 0.5 * (A + A.conj().T)
+    lam, V = np.linalg.eigh(A)
+    return lam, T @ V, int(keep.sum())
+
+
+def numerically_definite(S: np.ndarray, drop_tol: Optional[float]) -> bool:
+    """Whether a Gram matrix is safe for the Cholesky-based Rayleigh-Ritz: its Cholesky factor
+    exists and every pivot keeps more than drop_tol of its diagonal entry, |L_ii|^2 > drop_tol S_ii
+    (the squared sine between column i and the span of the columns before it, for unit columns).
+    Without drop_tol a failed factorisation raises numpy.linalg.LinAlgError."""
+    try:
+        Lc = np.linalg.cholesky(S)
+    except np.linalg.LinAlgError:
+        if drop_tol is None:
+            raise
+        return False
+    if drop_tol is None:
+        return True
+    piv = np.abs(np.diag(Lc)) ** 2 / np.real(np.diag(S))
+    return bool(piv.min() > drop_tol)
+
+
 @dataclasses.dataclass
 class LobpcgResult:
     X: np.ndarray  # the nb lowest Ritz vectors
     P: np.ndarray  # their components along [R, P] (the next search directions)
     eig: np.ndarray  # the nb lowest Ritz values
     resid: np.ndarray  # ||H x_i - theta_i x_i|| of the input block
+    kept: int = 0  # basis directions kept in the Rayleigh-Ritz (all of them unless S was singular)
 
 
 def lobpcg_step(hop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, P: Optional[np.ndarray],
-                kin: np.ndarray) -> LobpcgResult:
+                kin: np.ndarray, drop_tol: Optional[float] = None) -> LobpcgResult:
     """One step of the locally optimal block preconditioned conjugate gradient method, one of
     the inner eigensolvers of Section II-A (Knyazev's block form).  The Rayleigh quotients of the
     columns of X give the residuals W - X theta; the diagonal preconditioner 1 / (1 + |G|^2/2)
     acts on them; R and P are scaled to unit columns; Rayleigh-Ritz of H on span[X, R, P] (or
     span[X, R] without P) keeps the nb lowest Ritz pairs; the new P is the part of the new X
-    along [R, P]."""
+    along [R, P].  When drop_tol is given and the Gram matrix of [X, R, P] is not numerically
+    positive definite (numerically_definite), the Rayleigh-Ritz runs on the kept part of the span
+    (svqb_rayleigh_ritz) instead of failing."""
     nb = X.shape[1]
     W = hop(X)
     theta = np.real(np.sum(X.conj() * W, axis=0)) / np.real(np.sum(X.conj() * X, axis=0))
@@ -475,9 +518,96 @@ def lobpcg_step(hop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, P: Optio
     Hs = Z.conj().T @ HZ
     S = 0.5 * (S + S.conj().T)
     Hs = 0.5 * (Hs + Hs.conj().T)
-    lam, C = scipy.linalg.eigh(Hs, S)
+    kept = Z.shape[1]
+    if numerically_definite(S, drop_tol):
+        lam, C = scipy.linalg.eigh(Hs, S)
+    else:
+        lam, C, kept = svqb_rayleigh_ritz(S, Hs, drop_tol)
     C1 = C[:, :nb]
-    return LobpcgResult(X=Z @ C1, P=Z[:, nb:] @ C1[nb:], eig=lam[:nb], resid=resid)
+    return LobpcgResult(X=Z @ C1, P=Z[:, nb:] @ C1[nb:], eig=lam[:nb], resid=resid, kept=kept)
+
+
+@dataclasses.dataclass
+class PpcgResult:
+    X: np.ndarray  # the next iterate (columns x_j', not orthonormalised)
+    P: np.ndarray  # the next search directions p_j'
+    eig: np.ndarray  # Ritz values of the input block
+    resid: np.ndarray  # ||H x_j - lam_j x_j|| of the input block's Ritz vectors
+    coef: np.ndarray  # nb x 3 coefficients (alpha, beta, gamma) of x_j' on (x_j, w_j, p_j)
+
+
+def small_lowest_pair(G: np.ndarray, A: np.ndarray, drop_tol: float) -> np.ndarray:
+    """The lowest Ritz vector of the pencil (A, G) on a basis of up to three vectors (G their Gram
+    matrix, A the matrix of H on them), by svqb_rayleigh_ritz, with its phase fixed so that its
+    first component is real and non-negative."""
+    _, C, _ = svqb_rayleigh_ritz(G, A, drop_tol)
+    c = C[:, 0]
+    if abs(c[0]) > 0.0:
+        c = c * (abs(c[0]) / c[0])
+    return c
+
+
+def ppcg_step(hop: Callable[[np.ndarray], np.ndarray], X: np.ndarray, P: Optional[np.ndarray],
+              kin: np.ndarray, drop_tol: float) -> PpcgResult:
+    """One step of the projected preconditioned conjugate gradient method (Vecharynski, Yang and
+    Pask), one of the inner eigensolvers of Section II-A, in this order:
+
+    1. Rayleigh-Ritz on span X (X^H X and X^H H X, FP64 generalised eigenproblem): X <- X C are
+       the Ritz vectors, lam their Ritz values; the directions follow the columns, P <- P C.
+    2. Residuals R = H X - X diag(lam); preconditioned residuals W = K R with the diagonal
+       K = 1 / (1 + |G|^2/2); W and P are projected against span X: Y <- Y - X (X^H Y).
+    3. For each column j, Rayleigh-Ritz of H on span{x_j, w_j, p_j} (span{x_j, w_j} without P):
+       the lowest Ritz vector x_j' = alpha x_j + beta w_j + gamma p_j (alpha real >= 0), and
+       p_j' = beta w_j + gamma p_j.  The entry of H for (x_j, x_j) is lam_j.
+
+    The next step's Rayleigh-Ritz orthonormalises X' again, so the output is not orthonormal."""
+    nb = X.shape[1]
+    HX = hop(X)
+    S = X.conj().T @ X
+    Hs = X.conj().T @ HX
+    lam, C = rayleigh_ritz_gram(0.5 * (S + S.conj().T), 0.5 * (Hs + Hs.conj().T))
+    X = X @ C
+    HX = HX @ C
+    if P is not None:
+        P = P @ C
+    R = HX - X * lam[None, :]
+    resid = np.linalg.norm(R, axis=0)
+    W = R / (1.0 + kin)[:, None]
+    W = W - X @ (X.conj().T @ W)
+    if P is not None:
+        P = P - X @ (X.conj().T @ P)
+    HW = hop(W)
+    HP = hop(P) if P is not None else None
+    Xn = np.empty_like(X)
+    Pn = np.empty_like(X)
+    coef = np.zeros((nb, 3), dtype=complex)
+    for j in range(nb):
+        basis = [X[:, j], W[:, j]] + ([P[:, j]] if P is not None else [])
+        hbasis = [None, HW[:, j]] + ([HP[:, j]] if P is not None else [])
+        n = len(basis)
+        G = np.array([[np.vdot(basis[a], basis[b]) for b in range(n)] for a in range(n)])
+        A = np.zeros((n, n), dtype=complex)
+        A[0, 0] = lam[j]
+        for a in range(n):
+            for b in range(max(a, 1), n):
+                A[a, b] = np.vdot(basis[a], hbasis[b])
+                A[b, a] = np.conj(A[a, b])
+        c = small_lowest_pair(0.5 * (G + G.conj().T), A, drop_tol)
+        coef[j, :n] = c
+        Xn[:, j] = sum(c[i] * basis[i] for i in range(n))
+        Pn[:, j] = sum(c[i] * basis[i] for i in range(1, n))
+    return PpcgResult(X=Xn, P=Pn, eig=lam, resid=resid, coef=coef)
+
+
+def rayleigh_ritz_gram(S: np.ndarray, Hs: np.ndarray):
+    """Rayleigh-Ritz from the Gram matrix S and the projected matrix Hs of a basis (the second half
+    of rayleigh_ritz): S = L L^H, L^-1 Hs L^-H = Q diag(lam) Q^H, C = L^-H Q."""
+    Lc = np.linalg.cholesky(S)
+    T = scipy.linalg.solve_triangular(Lc, Hs, lower=True)
+    Hh = scipy.linalg.solve_triangular(Lc, T.conj().T, lower=True)
+    Hh = 0.5 * (Hh + Hh.conj().T)
+    lam, Q = np.linalg.eigh(Hh)
+    return lam, scipy.linalg.solve_triangular(Lc.conj().T, Q, lower=False)
 
 
 def lanczos_max(hop: Callable[[np.ndarray], np.ndarray], npw: int, steps: int = 20,

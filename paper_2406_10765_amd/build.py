@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpw.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["fft.hip", "fft_plane.hip", "gemm.hip", "gemm16.hip", "misc.hip", "plan.cpp", "engine.cpp", "serve.cpp"]
+SOURCES = ["fft.hip", "fft_plane.hip", "gemm.hip", "gemm16.hip", "misc.hip", "solver.hip", "plan.cpp", "engine.cpp", "serve.cpp"]
 
 # Packed-FP32 instructions are disabled for every device pass.
 CFLAGS = [

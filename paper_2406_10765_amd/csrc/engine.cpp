@@ -650,7 +650,9 @@ struct Engine {
 
   // Sum the split-K partials of [S | H_s] (n x 2n), take Hermitian parts, and solve
   // H_s C = S C diag(lambda), C^H S C = I in FP64 (C in the H_s storage, lambda ascending).
-  pw_status dense_solve(int nb, int nsplit) {
+  // With min_pivot > 0 a factor whose smallest pivot keeps no more than min_pivot of its diagonal
+  // entry (|L_ii|^2 <= min_pivot S_ii) counts as a failed factorisation (PW_ENOTPD).
+  pw_status dense_solve(int nb, int nsplit, double min_pivot = 0.0) {
     double2* parts = h->at<double2>(P.lay.parts);
     double2* SH = h->at<double2>(P.lay.sh);
     double2* S = SH;
@@ -670,15 +672,25 @@ struct Engine {
     auto* Hz = reinterpret_cast<rocblas_double_complex*>(Hs);
     const rocblas_double_complex one(1.0, 0.0);
     h->tbegin();
+    double* dS = h->at<double>(P.lay.ework);
+    double* piv_d = h->at<double>(P.lay.scal) + 3;  // [0, 2) belong to the Lanczos bound
+    if (min_pivot > 0.0) PW_HIP(launch_diag_copy(S, nb, nb, dS, h->stream));
     rocblas_status rs = rocsolver_zpotrf(h->blas, rocblas_fill_lower, nb, Sz, nb, info_d);
     if (rs != rocblas_status_success)
       return fail(h, PW_EDEVICE, std::string("rocsolver_zpotrf: ") + rocblas_status_to_string(rs));
+    if (min_pivot > 0.0) PW_HIP(launch_min_pivot(S, nb, nb, dS, piv_d, h->stream));
     int info[2] = {0, 0};
+    double piv = 1.0;
     PW_HIP(hipMemcpyAsync(&info[0], info_d, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    if (min_pivot > 0.0) PW_HIP(hipMemcpyAsync(&piv, piv_d, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     PW_HIP(hipStreamSynchronize(h->stream));
     if (info[0] > 0) {
       h->tend(PW_PH_EIGSOLVE);
       return fail(h, PW_ENOTPD, "Cholesky of the Gram matrix failed (rank-deficient block)");
+    }
+    if (min_pivot > 0.0 && !(piv > min_pivot)) {
+      h->tend(PW_PH_EIGSOLVE);
+      return fail(h, PW_ENOTPD, "Gram matrix numerically singular (a Cholesky pivot below the drop tolerance)");
     }
     rs = rocblas_ztrsm(h->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
                        rocblas_diagonal_non_unit, nb, nb, &one, Sz, nb, Hz, nb);
@@ -702,11 +714,84 @@ struct Engine {
     return PW_OK;
   }
 
+  // Rayleigh-Ritz on the kept part of a basis whose Gram matrix failed the Cholesky test: the
+  // split-K partials of [S | H_s] are summed again, S is scaled to unit diagonal
+  // (D = diag(S)^-1/2), D S D = U diag(sigma) U^H, the directions with sigma <= tol * max(sigma)
+  // dropped, T = D U_kept diag(sigma_kept)^-1/2 (T^H S T = I), T^H H_s T = V diag(lambda) V^H
+  // and C = T V (the nb lowest columns, in the H_s storage with leading dimension k).  *kept is
+  // the dimension of the kept span; PW_ENOTPD when it is below nb.
+  pw_status dense_solve_svqb(int k, int nb, int nsplit, double tol, int* kept_out) {
+    double2* parts = h->at<double2>(P.lay.parts);
+    double2* SH = h->at<double2>(P.lay.sh);
+    double2* S = SH;
+    double2* Hs = SH + (size_t)k * k;
+    double* d = h->at<double>(P.lay.ct);  // k doubles; the coefficient table is written later
+    double* sig = h->at<double>(P.lay.eig);
+    int* info_d = h->at<int>(P.lay.info);
+    h->tbegin();
+    PW_HIP(launch_reduce_parts<T>(parts, nsplit, k, 2 * k, nullptr, 0, SH, k, (cplx<T>*)nullptr, 0, h->stream));
+    PW_HIP(launch_hermitize(S, k, k, h->stream));
+    PW_HIP(launch_hermitize(Hs, k, k, h->stream));
+    PW_HIP(launch_svqb_scale(S, k, k, d, h->stream));
+    auto* Sz = reinterpret_cast<rocblas_double_complex*>(S);
+    auto* Hz = reinterpret_cast<rocblas_double_complex*>(Hs);
+    rocblas_status rs = rocsolver_zheevd(h->blas, rocblas_evect_original, rocblas_fill_lower, k, Sz, k, sig,
+                                         h->at<double>(P.lay.ework), info_d + 1);
+    if (rs != rocblas_status_success)
+      return fail(h, PW_EDEVICE, std::string("rocsolver_zheevd: ") + rocblas_status_to_string(rs));
+    std::vector<double> sh(k);
+    int info = 0;
+    PW_HIP(hipMemcpyAsync(sh.data(), sig, sizeof(double) * k, hipMemcpyDeviceToHost, h->stream));
+    PW_HIP(hipMemcpyAsync(&info, info_d + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    PW_HIP(hipStreamSynchronize(h->stream));
+    if (info > 0) return fail(h, PW_ENUMERIC, "eigensolver of the basis Gram matrix did not converge");
+    const double smax = sh[k - 1];
+    int first = 0;
+    while (first < k && !(sh[first] > tol * smax)) ++first;
+    const int kept = k - first;
+    if (kept_out) *kept_out = kept;
+    if (!(smax > 0.0) || kept < nb) {
+      h->tend(PW_PH_EIGSOLVE);
+      return fail(h, PW_ENOTPD, "basis spans fewer directions than the block has columns");
+    }
+    // T (k x kept) and H_s T (k x kept) in the partials' storage, T^H H_s T in the S storage
+    double2* Tm = parts;
+    double2* HT = parts + (size_t)k * kept;
+    PW_HIP(launch_svqb_basis(S, k, k, sig, d, first, kept, Tm, k, h->stream));
+    auto* Tz = reinterpret_cast<rocblas_double_complex*>(Tm);
+    auto* HTz = reinterpret_cast<rocblas_double_complex*>(HT);
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    rs = rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, k, kept, k, &one, Hz, k, Tz, k,
+                       &zero, HTz, k);
+    if (rs == rocblas_status_success)
+      rs = rocblas_zgemm(h->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, kept, kept, k, &one,
+                         Tz, k, HTz, k, &zero, Sz, kept);
+    if (rs != rocblas_status_success)
+      return fail(h, PW_EDEVICE, std::string("rocblas_zgemm: ") + rocblas_status_to_string(rs));
+    PW_HIP(launch_hermitize(S, kept, kept, h->stream));
+    rs = rocsolver_zheevd(h->blas, rocblas_evect_original, rocblas_fill_lower, kept, Sz, kept, sig,
+                          h->at<double>(P.lay.ework), info_d + 1);
+    if (rs != rocblas_status_success)
+      return fail(h, PW_EDEVICE, std::string("rocsolver_zheevd: ") + rocblas_status_to_string(rs));
+    rs = rocblas_zgemm(h->blas, rocblas_operation_none, rocblas_operation_none, k, nb, kept, &one, Tz, k, Sz, kept,
+                       &zero, Hz, k);
+    if (rs != rocblas_status_success)
+      return fail(h, PW_EDEVICE, std::string("rocblas_zgemm: ") + rocblas_status_to_string(rs));
+    h->tend(PW_PH_EIGSOLVE);
+    PW_HIP(hipMemcpyAsync(&info, info_d + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    PW_HIP(hipStreamSynchronize(h->stream));
+    if (info > 0) return fail(h, PW_ENUMERIC, "dense eigensolver did not converge");
+    return PW_OK;
+  }
+
+  // Basis directions whose scaled Gram eigenvalue is below this fraction of the largest are
+  // dropped (the Gram matrix of FP32 data is accurate to about 1e-7 of its diagonal).
+  static constexpr double drop_tol() { return sizeof(T) == 8 ? PW_DROP_TOL_FP64 : PW_DROP_TOL_MIXED; }
+
   // One LOBPCG step (the C ABI's pw_lobpcg_step): Z = [X R P], HZ = [HX HR HP] in the arena,
   // Rayleigh-Ritz on span Z, X' = Z C_1 into X, P' = [R P] C_1(R and P rows) into Pd.
   pw_status lobpcg_step(cplx<T>* X, cplx<T>* Pd, int nb, long ld, bool have_p, double* eig_host,
-                        double* resid_host, int* restarted) {
-    if (restarted) *restarted = 0;
+                        double* resid_host, int* kept) {
     set_planes(nullptr, 0);
     const long ldw = P.ldw;
     cplx<T>* Z = h->at<cplx<T>>(P.lay.lz);
@@ -737,21 +822,15 @@ struct Engine {
       s = hop(Pz, ldw, nb, HZ + (size_t)2 * nb * ldw, ldw, HZ + (size_t)2 * nb * ldw, ldw, 1.0, 0.0, 0.0, nullptr, 0);
       if (s != PW_OK) return s;
     }
-    // Rayleigh-Ritz on span Z; when the basis with P is numerically dependent (its Gram matrix
-    // fails the Cholesky test), again on span [X R] alone
+    // Rayleigh-Ritz on span Z; when the basis is numerically dependent (its Gram matrix fails the
+    // Cholesky test), on the part of the span that the truncated SVQB basis keeps
     double2* parts = h->at<double2>(P.lay.parts);
-    int k = (have_p ? 3 : 2) * nb;
-    for (;;) {
-      PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Z, ldw, Z, ldw, HZ, ldw, k, k, 2 * k, P.npw, P.nsplit_lob,
-                              parts, 4));
-      s = dense_solve(k, P.nsplit_lob);
-      if (s == PW_ENOTPD && k == 3 * nb) {
-        k = 2 * nb;
-        if (restarted) *restarted = 1;
-        continue;
-      }
-      break;
-    }
+    const int k = (have_p ? 3 : 2) * nb;
+    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Z, ldw, Z, ldw, HZ, ldw, k, k, 2 * k, P.npw, P.nsplit_lob,
+                            parts, 4));
+    if (kept) *kept = k;
+    s = dense_solve(k, P.nsplit_lob, drop_tol());
+    if (s == PW_ENOTPD) s = dense_solve_svqb(k, nb, P.nsplit_lob, drop_tol(), kept);
     if (s != PW_OK) return s;
     const cplx<T>* C = coeffs(k);
     EpiH e;
@@ -761,6 +840,81 @@ struct Engine {
     PW_TIMED(PW_PH_ROTATE, nn(flag(PW_FLAG_BF16_ROT), R, ldw, C + nb, k, P.npw, nb, k - nb, Pd, ld, e));
     PW_HIP(hipMemcpyAsync(eig_host, h->at<double>(P.lay.eig), sizeof(double) * nb, hipMemcpyDeviceToHost,
                           h->stream));
+    PW_HIP(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < nb; ++i)
+      if (!std::isfinite(eig_host[i]) || !std::isfinite(resid_host[i]))
+        return fail(h, PW_ENUMERIC, "non-finite Ritz value or residual");
+    return PW_OK;
+  }
+
+  // One PPCG step (the C ABI's pw_ppcg_step).  Arena: Z = [X0 | W | P] and HZ = [H X0 | H W | H P]
+  // (the LOBPCG buffers).  Rayleigh-Ritz on span X (X <- X C, P <- P C), residuals of the Ritz
+  // vectors, W = T R, [W P] <- [W P] - X (X^H [W P]), H W and H P, then per column the Ritz vector
+  // of span{x_j, w_j, p_j}: X <- a X + b W + g P, P <- b W + g P.
+  pw_status ppcg_step(cplx<T>* X, cplx<T>* Pd, int nb, long ld, bool have_p, double* eig_host, double* resid_host) {
+    set_planes(nullptr, 0);
+    const long ldw = P.ldw;
+    cplx<T>* Z = h->at<cplx<T>>(P.lay.lz);
+    cplx<T>* HZ = Z + (size_t)3 * P.nbands * ldw;
+    cplx<T>* Zw = Z + (size_t)nb * ldw;
+    cplx<T>* Zp = Z + (size_t)2 * nb * ldw;
+    cplx<T>* HZw = HZ + (size_t)nb * ldw;
+    cplx<T>* HZp = HZ + (size_t)2 * nb * ldw;
+    double* eig_d = h->at<double>(P.lay.eig);
+    double* resid_d = h->at<double>(P.lay.resid);
+    const T* kin = h->at<T>(P.lay.kin);
+    double2* parts = h->at<double2>(P.lay.parts);
+    // Rayleigh-Ritz on span X
+    PW_TIMED(PW_PH_OTHER, launch_copy_cols<T>(X, ld, Z, ldw, P.npw, nb, h->stream));
+    pw_status s = hop(Z, ldw, nb, HZ, ldw, HZ, ldw, 1.0, 0.0, 0.0, nullptr, 0);
+    if (s != PW_OK) return s;
+    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Z, ldw, Z, ldw, HZ, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
+                            parts, 4));
+    s = dense_solve(nb, P.nsplit_gram);
+    if (s != PW_OK) return s;
+    const cplx<T>* C = coeffs(nb);
+    EpiH e;
+    std::memset(&e, 0, sizeof(e));
+    e.mode = 0;
+    const bool r16 = flag(PW_FLAG_BF16_ROT);
+    PW_TIMED(PW_PH_ROTATE, nn(r16, Z, ldw, C, nb, P.npw, nb, nb, X, ld, e));    // Ritz vectors
+    PW_TIMED(PW_PH_ROTATE, nn(r16, HZ, ldw, C, nb, P.npw, nb, nb, Zw, ldw, e));  // H times them
+    if (have_p) PW_TIMED(PW_PH_ROTATE, nn(r16, Pd, ld, C, nb, P.npw, nb, nb, Zp, ldw, e));
+    // residual norms, then W = T (H X - X Lambda) in place of H X
+    PW_TIMED(PW_PH_RESID, launch_resid<T>(Zw, ldw, X, ld, eig_d, P.npw, nb, resid_d, h->stream));
+    PW_TIMED(PW_PH_OTHER, launch_precond_resid<T>(Zw, ldw, X, ld, eig_d, kin, P.npw, nb, Zw, ldw, h->stream));
+    // [W P] <- [W P] - X (X^H [W P]): the coefficients summed with the factor -1
+    const int ncols = have_p ? 2 * nb : nb;
+    double* neg = h->at<double>(P.lay.scal) + 2;
+    static const double kMinusOne = -1.0;
+    PW_HIP(hipMemcpyAsync(neg, &kMinusOne, sizeof(double), hipMemcpyHostToDevice, h->stream));
+    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), X, ld, Zw, ldw, nullptr, 0, ncols, nb, ncols, P.npw,
+                            P.nsplit_gram, parts, 4));
+    cplx<T>* Cp = h->at<cplx<T>>(P.lay.ct);
+    PW_TIMED(PW_PH_GRAM_REDUCE, launch_reduce_parts<T>(parts, P.nsplit_gram, nb, ncols, neg, 1, nullptr, 0, Cp, nb,
+                                                       h->stream));
+    e.mode = 2;
+    e.Zl = Zw;
+    e.ldz = ldw;
+    PW_TIMED(PW_PH_ROTATE, nn(r16, X, ld, Cp, nb, P.npw, ncols, nb, Zw, ldw, e));
+    // H W and H P
+    s = hop(Zw, ldw, nb, HZw, ldw, HZw, ldw, 1.0, 0.0, 0.0, nullptr, 0);
+    if (s != PW_OK) return s;
+    if (have_p) {
+      s = hop(Zp, ldw, nb, HZp, ldw, HZp, ldw, 1.0, 0.0, 0.0, nullptr, 0);
+      if (s != PW_OK) return s;
+    }
+    // per-column Rayleigh-Ritz and the update
+    double2* dots = parts;
+    double2* coef = parts + (size_t)11 * nb;
+    PW_TIMED(PW_PH_OTHER, launch_ppcg_dots<T>(X, ld, Zw, Zp, HZw, HZp, ldw, P.npw, nb, have_p ? 1 : 0, dots,
+                                              h->stream));
+    PW_TIMED(PW_PH_OTHER, launch_ppcg_small(dots, eig_d, nb, have_p ? 1 : 0, drop_tol(), coef, h->stream));
+    PW_TIMED(PW_PH_OTHER, launch_ppcg_update<T>(X, ld, Pd, ld, Zw, Zp, ldw, P.npw, nb, have_p ? 1 : 0, coef,
+                                                h->stream));
+    PW_HIP(hipGetLastError());
+    PW_HIP(hipMemcpyAsync(eig_host, eig_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
+    PW_HIP(hipMemcpyAsync(resid_host, resid_d, sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
     PW_HIP(hipStreamSynchronize(h->stream));
     for (int i = 0; i < nb; ++i)
       if (!std::isfinite(eig_host[i]) || !std::isfinite(resid_host[i]))
@@ -1263,7 +1417,7 @@ pw_status pw_density(pw_handle* h, const void* X, int nb, int ld, const double* 
 }
 
 pw_status pw_lobpcg_step(pw_handle* h, void* X, void* Pd, int nb, int ld, int have_p, double* eig, double* resid,
-                         int* restarted) {
+                         int* kept) {
   if (!h) return fail(nullptr, PW_EINVAL, "null handle");
   pw_status s = check_block(h, X, nb, ld);
   if (s != PW_OK) return s;
@@ -1276,9 +1430,27 @@ pw_status pw_lobpcg_step(pw_handle* h, void* X, void* Pd, int nb, int ld, int ha
   if (x0 < p0 + span && p0 < x0 + span) return fail(h, PW_EINVAL, "X and P overlap");
   if (h->plan.prec == PW_FP64)
     return Engine<double>(h).lobpcg_step(static_cast<double2*>(X), static_cast<double2*>(Pd), nb, ld, have_p != 0,
-                                         eig, resid, restarted);
+                                         eig, resid, kept);
   return Engine<float>(h).lobpcg_step(static_cast<float2*>(X), static_cast<float2*>(Pd), nb, ld, have_p != 0, eig,
-                                      resid, restarted);
+                                      resid, kept);
+}
+
+pw_status pw_ppcg_step(pw_handle* h, void* X, void* Pd, int nb, int ld, int have_p, double* eig, double* resid) {
+  if (!h) return fail(nullptr, PW_EINVAL, "null handle");
+  pw_status s = check_block(h, X, nb, ld);
+  if (s != PW_OK) return s;
+  if (!Pd || !eig || !resid) return fail(h, PW_EINVAL, "null directions or output");
+  if (!(h->plan.flags & PW_FLAG_LOBPCG)) return fail(h, PW_EINVAL, "handle not planned with PW_FLAG_LOBPCG");
+  const size_t cb = 2 * (size_t)h->plan.real_bytes;
+  const char* x0 = static_cast<const char*>(X);
+  const char* p0 = static_cast<const char*>(Pd);
+  const size_t span = ((size_t)(nb - 1) * ld + h->plan.npw) * cb;
+  if (x0 < p0 + span && p0 < x0 + span) return fail(h, PW_EINVAL, "X and P overlap");
+  if (h->plan.prec == PW_FP64)
+    return Engine<double>(h).ppcg_step(static_cast<double2*>(X), static_cast<double2*>(Pd), nb, ld, have_p != 0, eig,
+                                       resid);
+  return Engine<float>(h).ppcg_step(static_cast<float2*>(X), static_cast<float2*>(Pd), nb, ld, have_p != 0, eig,
+                                    resid);
 }
 
 pw_status pw_eig_step(pw_handle* h, void* X, void* HX, int nb, int ld, const pw_step_params* p, double* eig,

@@ -174,6 +174,27 @@ hipError_t launch_rayleigh(const cplx<T>* W, long ldw, const cplx<T>* X, long ld
 template <typename T>
 hipError_t launch_precond_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, const double* theta,
                                 const T* kin, int rows, int cols, cplx<T>* R, long ldr, hipStream_t s);
+// PPCG pieces (solver.hip): per-column FP64 inner products of x_j, w_j, p_j and H w_j, H p_j
+// (11 per column, see k_ppcg_dots), the per-column Rayleigh-Ritz on span{x_j, w_j, p_j} (coef:
+// 3 per column), and the update X <- a X + b W + g P, Pd <- b W + g P.
+template <typename T>
+hipError_t launch_ppcg_dots(const cplx<T>* X, long ldx, const cplx<T>* W, const cplx<T>* Pp, const cplx<T>* HW,
+                            const cplx<T>* HP, long ldz, int rows, int cols, int have_p, double2* dots,
+                            hipStream_t s);
+hipError_t launch_ppcg_small(const double2* dots, const double* lam, int nb, int have_p, double drop_tol,
+                             double2* coef, hipStream_t s);
+template <typename T>
+hipError_t launch_ppcg_update(cplx<T>* X, long ldx, cplx<T>* Pd, long ldp, const cplx<T>* W, const cplx<T>* Pp,
+                              long ldz, int rows, int cols, int have_p, const double2* coef, hipStream_t s);
+// Truncated SVQB basis of a k x k Gram matrix: S <- D S D with d_i = S_ii^-1/2 (d: k doubles), and
+// T[:, c] = D U[:, first + c] / sqrt(sigma[first + c]) for c < kept.
+// Pivot test of a Cholesky factor: d = Re diag(S) before the factorisation, then
+// out = min_i |L_ii|^2 / d_i (one double, device).
+hipError_t launch_diag_copy(const double2* S, long lds, int k, double* d, hipStream_t s);
+hipError_t launch_min_pivot(const double2* L, long ldl, int k, const double* d, double* out, hipStream_t s);
+hipError_t launch_svqb_scale(double2* S, long lds, int k, double* d, hipStream_t s);
+hipError_t launch_svqb_basis(const double2* U, long ldu, int k, const double* sigma, const double* d, int first,
+                             int kept, double2* Tm, long ldt, hipStream_t s);
 // Charge density: rho[r] = (first ? 0 : rho[r]) + sum_b occ[b] psq[b * nr + r], bands in order.
 template <typename T>
 hipError_t launch_density_acc(const T* psq, int nbt, long nr, const double* occ, double* rho, bool first,

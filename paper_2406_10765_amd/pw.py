@@ -140,6 +140,8 @@ def lib() -> ctypes.CDLL:
         "pw_density": ([vp, vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_double), vp]),
         "pw_lobpcg_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
                             P(ctypes.c_double), P(ctypes.c_int)]),
+        "pw_ppcg_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
+                          P(ctypes.c_double)]),
         "pw_eig_step": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, P(StepParams), P(ctypes.c_double),
                          P(ctypes.c_double), P(ctypes.c_double)]),
         "pw_solve": ([vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -182,6 +184,9 @@ PW_FLAG_BF16_ROT = 8
 PW_FLAG_BF16_ALL = PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT
 PW_FLAG_BETA_OTF = 16
 PW_FLAG_LOBPCG = 32
+# fraction of the largest scaled Gram eigenvalue below which basis directions are dropped
+PW_DROP_TOL_FP64 = 1e-10
+PW_DROP_TOL_MIXED = 1e-5
 
 
 def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,
@@ -335,7 +340,8 @@ class Handle:
     def lobpcg_step(self, X, P, have_p: bool, info: Optional[dict] = None):
         """One LOBPCG step on X and the directions P (both in place; P's input ignored when
         not have_p).  Returns (Ritz values, residual norms of the input X) as numpy arrays;
-        info["restarted"] tells whether the step fell back to the basis without P."""
+        info["kept"] is the dimension of the span the Rayleigh-Ritz used (3 nb or 2 nb unless
+        dependent directions were dropped)."""
         nb, ld = self._check_block(X)
         nb2, ld2 = self._check_block(P)
         if nb2 != nb or ld2 != ld:
@@ -343,12 +349,26 @@ class Handle:
         eig = np.empty(nb)
         res = np.empty(nb)
         dp = ctypes.POINTER(ctypes.c_double)
-        rs = ctypes.c_int(0)
+        kept = ctypes.c_int(0)
         _check(lib().pw_lobpcg_step(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(P.data_ptr()), nb, ld,
                                     1 if have_p else 0, eig.ctypes.data_as(dp), res.ctypes.data_as(dp),
-                                    ctypes.byref(rs)), self._h)
+                                    ctypes.byref(kept)), self._h)
         if info is not None:
-            info["restarted"] = bool(rs.value)
+            info["kept"] = int(kept.value)
+        return eig, res
+
+    def ppcg_step(self, X, P, have_p: bool):
+        """One PPCG step on X and the directions P (both in place).  Returns (Ritz values of the
+        input block, residual norms of its Ritz vectors) as numpy arrays."""
+        nb, ld = self._check_block(X)
+        nb2, ld2 = self._check_block(P)
+        if nb2 != nb or ld2 != ld:
+            raise ValueError("X and P must have the same shape and stride")
+        eig = np.empty(nb)
+        res = np.empty(nb)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().pw_ppcg_step(self._h, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(P.data_ptr()), nb, ld,
+                                  1 if have_p else 0, eig.ctypes.data_as(dp), res.ctypes.data_as(dp)), self._h)
         return eig, res
 
     def eig_step(self, X, degree: int, a_lo: float = float("nan"), a: float = float("nan"),
