@@ -148,6 +148,66 @@ def occupied_angle(Xa, Xb, nocc, npw):
     return float(np.arccos(min(1.0, float(s.min()))))
 
 
+def accuracy_at_convergence(pw, synth, torch, workload, mflags, degree, tol_mixed=5e-5, tol_fp64=1e-9):
+    """Mixed and FP64 solves of one cell from the same seeded block, compared at convergence:
+    eigenvalue differences, per-cluster principal angles with the Davis-Kahan bound beside them
+    (residuals of the mixed span from an FP64 Rayleigh-Ritz on it), and the FP64 polish (FP64 steps
+    started from the converged mixed block)."""
+    from paper_2406_10765_amd import accuracy as acc
+
+    cell = synth.make_cell(workload)
+    nb, nocc = cell.nbands, cell.nocc
+    hm = pw.Handle(cell, pw.PW_MIXED, flags=mflags)
+    h64 = pw.Handle(cell, pw.PW_FP64)
+    if not np.array_equal(hm.gvectors(), h64.gvectors()):
+        raise RuntimeError("mixed and FP64 handles order the plane waves differently")
+    X0 = hm.random_block(nb, synth.SEED_X0 + synth.WORKLOADS[workload]["index"])
+    t0 = time.perf_counter()
+    Xm = X0.clone()
+    em, rm, sm, cm = hm.solve(Xm, nocc, tol_mixed, degree, 200)
+    t_m = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    X64 = X0.to(torch.complex128)
+    e64, r64, s64, c64 = h64.solve(X64, nocc, tol_fp64, degree, 400)
+    t_64 = time.perf_counter() - t0
+    # FP64 Rayleigh-Ritz on span X_m: same span, FP64 Ritz values and exact residuals
+    Y = Xm.to(torch.complex128)
+    erep, rrep, _ = h64.eig_step(Y, 0, b=1.0)
+    t0 = time.perf_counter()
+    Xp = Y.clone()
+    ep, rp, sp, cp = h64.solve(Xp, nocc, tol_fp64, degree, 400)
+    t_p = time.perf_counter() - t0
+    A64, Am, Ap = h64.to_host(X64), h64.to_host(Y), h64.to_host(Xp)
+    rows_m = acc.cluster_report(Am, erep, rrep, A64, e64, r64, nocc)
+    rows_p = acc.cluster_report(Ap, ep, rp, A64, e64, r64, nocc)
+    worst = sorted(rows_m, key=lambda r: -r[2])[:8]
+    out = {
+        "workload": workload, "mixed_flags": mflags, "degree": degree, "nocc": nocc, "clusters": len(rows_m),
+        "mixed": {"tol": tol_mixed, "steps": sm, "converged": bool(cm), "seconds": round(t_m, 3),
+                  "max_resid_occ": float(rm[:nocc].max())},
+        "fp64": {"tol": tol_fp64, "steps": s64, "converged": bool(c64), "seconds": round(t_64, 3),
+                 "max_resid_occ": float(r64[:nocc].max())},
+        "max_abs_deig_occ_mixed_vs_fp64_Ha": float(np.abs(em[:nocc] - e64[:nocc]).max()),
+        "max_abs_deig_occ_mixed_span_fp64_rr_Ha": float(np.abs(erep[:nocc] - e64[:nocc]).max()),
+        "max_cluster_angle_rad": float(max(r[2] for r in rows_m)),
+        "max_davis_kahan_bound": float(max(r[3] for r in rows_m)),
+        "angles_within_bound": bool(all(r[2] <= r[3] * (1 + 1e-9) + 1e-15 for r in rows_m)),
+        "worst_clusters": [{"bands": [lo, hi], "angle_rad": float(a), "davis_kahan_bound": float(b)}
+                           for lo, hi, a, b in worst],
+        "polish": {"fp64_steps": sp, "converged": bool(cp), "seconds": round(t_p, 3),
+                   "fp64_steps_from_scratch": s64,
+                   "max_abs_deig_occ_Ha": float(np.abs(ep[:nocc] - e64[:nocc]).max()),
+                   "max_cluster_angle_rad": float(max(r[2] for r in rows_p)),
+                   "max_davis_kahan_bound": float(max(r[3] for r in rows_p))},
+        "what": "both forms converged from the same seeded block (occupied residuals <= tol); angles per "
+                "cluster of FP64 eigenvalues (gap < 1e-3 Ha) against the FP64 block; the bound adds the "
+                "Davis-Kahan bounds ||R||_F / delta of both blocks; polish = FP64 steps from the mixed block",
+    }
+    del hm, h64, X0, Xm, X64, Y, Xp
+    torch.cuda.empty_cache()
+    return out
+
+
 def device_info(torch, minfo):
     p = torch.cuda.get_device_properties(0)
     out = {"name": p.name, "arch": getattr(p, "gcnArchName", None), "hbm_gib": round(p.total_memory / 2**30, 1),
@@ -326,6 +386,8 @@ def main():
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--accuracy-workload", default="si64",
+                    help="cell of the mixed-vs-FP64 comparison at convergence ('none' to skip)")
     ap.add_argument("--filter-only", action="store_true",
                     help="set up the workload, run one degree-m filter step and exit (for counter runs)")
     args = ap.parse_args()
@@ -575,6 +637,19 @@ def main():
         torch.cuda.empty_cache()
         log(f"fp64: {ms64:.1f} ms/step; one-step |de| mixed vs fp64 = {accuracy['max_abs_deig_occ_mixed_vs_fp64_Ha']:.2e}")
 
+    accuracy_converged = None
+    if args.accuracy_workload != "none":
+        try:
+            accuracy_converged = accuracy_at_convergence(pw, synth, torch, args.accuracy_workload, mflags, m)
+            a = accuracy_converged
+            log(f"accuracy at convergence ({a['workload']}): |de| {a['max_abs_deig_occ_mixed_vs_fp64_Ha']:.2e} Ha, "
+                f"max cluster angle {a['max_cluster_angle_rad']:.2e} (bound {a['max_davis_kahan_bound']:.2e}); "
+                f"after FP64 polish ({a['polish']['fp64_steps']} steps vs {a['fp64']['steps']}): "
+                f"|de| {a['polish']['max_abs_deig_occ_Ha']:.2e}, angle {a['polish']['max_cluster_angle_rad']:.2e}")
+        except Exception as exc:  # a failed side measurement must not lose the headline line
+            accuracy_converged = {"error": str(exc)}
+            log(f"accuracy study failed: {exc}")
+
     serving = None
     if args.serving_requests > 0:
         serving = serving_leg(args.serving_requests, args.serving_rate, args.serving_slots, mflags, m)
@@ -598,7 +673,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": "c64+bf16x3" if mflags & (pw.PW_FLAG_BF16_ALL) else "c64",
+        "dtype_note": "complex FP32 data and FFTs; projector, rotation and Gram products as split-bf16 MFMA "
+                      "(3 and 4 terms, FP32 accumulation, FP64 split-K sums) per the flags; FP64 eigensolve and "
+                      "residual norms",
         "data": "synthetic",
         "config": {"workload": f"{args.workload.capitalize()}: {cell.natoms} Si atoms ({'x'.join(str(int(round(L / synth.A0_BOHR))) for L in cell.L)} diamond cells, a=10.26 bohr), "
                                f"Ecut {cell.ecut:g} Ha, Gamma point, {G.shape[0]} plane waves, {nb} bands, "
@@ -615,6 +693,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64": fp64,
         "accuracy": accuracy,
+        "accuracy_converged": accuracy_converged,
         "phases": phases,
         "serving": serving,
     }

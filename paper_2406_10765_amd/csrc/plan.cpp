@@ -213,8 +213,11 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   if (fb < 1) fb = 1;
   if (fb > P.nbb) fb = P.nbb;
   P.fft_batch = fb;
-  auto pick_split = [](int tiles, int K) {
-    int s = (2048 + tiles - 1) / tiles;
+  // K splits: enough workgroups to fill the chip several times over (the pipelined split-bf16
+  // forms run one workgroup per CU, and more, shorter chunks balance their tail: measured at
+  // Si512, 57 splits of the projection and 49 of the Gram take 1.0 and 2 ms less than 29 and 25)
+  auto pick_split = [](int tiles, int K, int target = 2048) {
+    int s = (target + tiles - 1) / tiles;
     int kmax = K / 512;
     if (s > kmax) s = kmax;
     if (s > 64) s = 64;
@@ -223,15 +226,15 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   };
   const bool f64 = P.prec == PW_FP64;
   const bool bkb = (P.flags & PW_FLAG_BF16_KB) != 0, bgr = (P.flags & PW_FLAG_BF16_GRAM) != 0;
-  P.nsplit_proj = P.nproj ? pick_split(bkb ? gemm_cn_bf16_planes_tiles(P.nproj, P.nbb) : gemm_cn_tiles(P.nproj, P.nbb, f64),
-                                       P.npw)
+  P.nsplit_proj = P.nproj ? (bkb ? pick_split(gemm_cn_bf16_planes_tiles(P.nproj, P.nbb), P.npw, 4096)
+                                  : pick_split(gemm_cn_tiles(P.nproj, P.nbb, f64), P.npw))
                           : 1;
   const bool gram_planes = bkb && bgr && P.nbb >= P.nbands;
   P.yp_cols = bkb ? P.nbb * (gram_planes ? 2 : 1) : 0;
-  P.nsplit_gram = pick_split(gram_planes ? gemm_cn_bf16_planes_tiles(P.nbands, 2 * P.nbands)
-                             : bgr       ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands)
-                                         : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
-                             P.npw);
+  P.nsplit_gram = gram_planes ? pick_split(gemm_cn_bf16_planes_tiles(P.nbands, 2 * P.nbands), P.npw, 4096)
+                  : pick_split(bgr ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands)
+                                   : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
+                               P.npw);
   const bool lob = (P.flags & PW_FLAG_LOBPCG) != 0;
   if (lob && P.nbb < P.nbands) {
     *err = "PW_FLAG_LOBPCG needs every band in one block (the plan would filter in blocks)";
