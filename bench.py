@@ -360,6 +360,9 @@ def serving_leg(n, rate, slots, flags, degree):
         "not_converged": [{"cell": m["name"], "ecut_ha": float(m["cell"].ecut), "seed": int(m["seed"]),
                            "status": int(r["status"]), "steps": int(r["steps"]), "message": r.get("message", "")}
                           for r, m in zip(res, mix) if r["status"] != 0],
+        "retried_steps": [{"cell": m["name"], "ecut_ha": float(m["cell"].ecut), "seed": int(m["seed"]),
+                           "status": int(r["status"]), "message": r.get("message", "")}
+                          for r, m in zip(res, mix) if r.get("retried", 0) > 0],
         "mean_steps": float(np.mean([r["steps"] for r in res])),
         "p50_latency_by_cell_s": {k: float(np.percentile(v, 50)) for k, v in sorted(by.items())},
         "mean_service_by_cell_s": {k: float(np.mean(v)) for k, v in sorted(svc.items())},

@@ -271,10 +271,19 @@ pw_status pw_eig_step(pw_handle *h, void *X_dev, void *HX_dev, int nb, int ld, c
  * PW_ENOTCONV with the last eig/resid written).  b: upper filter bound; NaN = the library's
  * Lanczos estimate (pw_spectrum_bound with 20 steps, seed 1, computed once per handle).
  * eig_host, resid_host: nb doubles (host); *steps (may be NULL) receives the steps taken.
- * Errors of a step are returned as they are (its pw_last_error text names the step).
+ * A filtered step whose Gram matrix fails the Cholesky test leaves X as it was (unblocked plans:
+ * the filter never writes X); such a step is taken again once at half the degree, and the retry
+ * is counted (pw_solve_retries) with the first failure's text kept (pw_last_error stays as it
+ * was before the retry when the retry succeeds: see pw_solve_retries).  Other errors of a step,
+ * and a second failure, are returned as they are (the pw_last_error text names the step).
  */
 pw_status pw_solve(pw_handle *h, void *X_dev, int nb, int ld, int nconv, double tol, int degree, int max_steps,
                    double b, double *eig_host, double *resid_host, int *steps);
+
+/* Steps of the last pw_solve on h that were taken again after a failed Cholesky test (0 or 1);
+ * when non-zero, *msg (may be NULL) points to the text of that failure (valid until the next call
+ * on h).  -1 for a null handle. */
+int pw_solve_retries(pw_handle *h, const char **msg);
 
 /*
  * Seeded starting block on the device: entry (g, j) = w_g (x + i y) / ||column j||, with x, y
@@ -369,7 +378,9 @@ typedef struct {
   double *eig;          /* caller buffer of nbands doubles (filled by pw_poll), may be NULL */
   double *resid;        /* caller buffer of nbands doubles, may be NULL */
   double t_arrive, t_admit, t_done;  /* server clock (s) */
-  char message[256];    /* for a failed request: the failing call and its pw_last_error text */
+  char message[256];    /* for a failed request: the failing call and its pw_last_error text; for a
+                           request whose solve retried a step: the text of the failure retried */
+  int retried;          /* steps of the solve taken again after a failed Cholesky test */
 } pw_result;
 
 typedef struct pw_server_s pw_server;

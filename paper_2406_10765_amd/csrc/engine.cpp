@@ -74,6 +74,8 @@ struct pw_handle_s {
   double bmax_cached = NAN;
   // lambda_1 and lambda_nb of the last successful pw_eig_step on this handle (NaN before one)
   double last_lo = NAN, last_hi = NAN;
+  int solve_retries = 0;        // steps of the last pw_solve taken again after a failed Cholesky
+  std::string solve_retry_msg;  // the text of that failure
   // PW_PROGRESS=1 in the environment: report each completed filter block of a band-blocked
   // step on stderr (the stream is synchronised at each report).
   bool progress = false;
@@ -334,7 +336,7 @@ struct Engine {
       PW_TIMED_ON(PW_PH_STICKS_INV, sm,
                   launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, sm));
       if (P.fl.sized) {
-        PW_TIMED_ON(PW_PH_PLANE, sm, launch_plane_n<T>(SB, V, nbt, st, g, tw1, scale, sm));
+        PW_TIMED_ON(PW_PH_PLANE, sm, launch_plane_n<T>(SB, V, nbt, st, cs, g, tw1, scale, sm));
       } else if (P.fl.fused) {
         PW_TIMED_ON(PW_PH_PLANE, sm,
                     launch_plane_fused<T>(SB, V, nbt, st, g, tw1, tw2, scale, 0, (T*)nullptr, P.fl, sm));
@@ -1521,14 +1523,25 @@ pw_status pw_solve(pw_handle* h, void* X, int nb, int ld, int nconv, double tol,
   pw_step_params p{0, NAN, NAN, b, 0};
   double bnd[3] = {0, 0, 0};
   int k = 0;
+  h->solve_retries = 0;
+  h->solve_retry_msg.clear();
   s = pw_eig_step(h, X, nullptr, nb, ld, &p, eig, resid, bnd);
   if (s == PW_OK) k = 1;
+  const bool x_kept_on_failure = h->plan.nbb >= h->plan.nbands;  // the unblocked filter never writes X
   while (s == PW_OK && !converged() && k < max_steps) {
     p.degree = degree;
     p.a_lo = bnd[0];
     p.a = bnd[1];
     p.b = b;
     s = pw_eig_step(h, X, nullptr, nb, ld, &p, eig, resid, bnd);
+    if (s == PW_ENOTPD && x_kept_on_failure && h->solve_retries == 0) {
+      // X still holds the previous iterate: take the step again at half the degree (a smaller
+      // spread of the filter's amplification), once
+      h->solve_retries = 1;
+      h->solve_retry_msg = "step " + std::to_string(k + 1) + ": " + h->err;
+      p.degree = degree > 1 ? degree / 2 : 1;
+      s = pw_eig_step(h, X, nullptr, nb, ld, &p, eig, resid, bnd);
+    }
     if (s == PW_OK) ++k;
   }
   if (steps) *steps = k;
@@ -1539,6 +1552,12 @@ pw_status pw_solve(pw_handle* h, void* X, int nb, int ld, int nconv, double tol,
   }
   if (!converged()) return fail(h, PW_ENOTCONV, "max_steps reached before the tolerance");
   return PW_OK;
+}
+
+int pw_solve_retries(pw_handle* h, const char** msg) {
+  if (!h) return -1;
+  if (msg) *msg = h->solve_retries ? h->solve_retry_msg.c_str() : nullptr;
+  return h->solve_retries;
 }
 
 pw_status pw_random_block(pw_handle* h, void* X, int nb, int ld, unsigned long long seed) {

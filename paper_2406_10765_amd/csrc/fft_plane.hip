@@ -303,6 +303,213 @@ __global__ __launch_bounds__(NT) void k_plane_n(cplx<T>* __restrict__ SB, const 
   }
 }
 
+// ---- 128 x 128 FP32 planes with wave-local lines ---------------------------------------------
+// The same transform as k_plane_n (inverse along y on the active columns, inverse along x, * V,
+// forward along x, forward along y on the active columns), arranged so that the 8 threads of a
+// line sit in one wave: the exchange between the two stages of a line is ordered by the wave
+// itself and needs no workgroup barrier, and the plane needs no zero fill, scatter or gather:
+//   y passes read their input straight from the sticks (zeros off the stick's n2 range) and the
+//   forward one writes its stick positions straight back;
+//   the plane in LDS holds only the active columns xa = n1 + n1max, at column xa ^ sy(row) of
+//   each 128-word row (sy(r) = 8 ((r >> 4 ^ r) & 1));
+//   the x pass uses its row as exchange space: stage-1 word (n2, k1) of the inverse at
+//   16 k1 + (n2 ^ k1 ^ 8 (y & 1)), word (m1, q2) of the forward at (8 q2 + (m1 ^ (q2 & 7))) ^ 8 (y & 1).
+// Each swizzle spreads the 64 lanes of a wave (8 lines x 8 threads) over all 16 eight-byte bank
+// slots in every access of the three passes.  Three workgroup barriers per plane.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ int p128_col(int row, int xa) { return xa ^ ((((row >> 4) ^ row) & 1) << 3); }
+
+__global__ __launch_bounds__(1024) void k_plane128(float2* __restrict__ SB, const float* __restrict__ V,
+                                                   const int* __restrict__ colstart, GridDesc g,
+                                                   const float2* __restrict__ twg, float scale) {
+  using T = float;
+  constexpr int N = 128, A = 8, B = 16, LPW = 8, NW = 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* plane = reinterpret_cast<float2*>(smem_raw);
+  float2* tw = plane + N * N;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l = lane >> 3, t = lane & 7;
+  const int z = blockIdx.x, b = blockIdx.y;
+  const int n1max = g.n1max, n1a = g.n1a;
+  const int yrow = wv * LPW + l;
+  for (int i = tid; i < N; i += 1024) tw[i] = twg[i];
+  float2* sb = SB + ((long)b * g.n3 + z) * g.nst;
+  __syncthreads();
+  const float2 zero = mk<T>(0, 0);
+  // ---- inverse along y, active columns ----
+  for (int grp = wv; grp * LPW < n1a; grp += NW) {
+    const int xa = grp * LPW + l;
+    const bool act = xa < n1a;
+    int cs = 0, m = -1;
+    if (act) {
+      cs = colstart[xa];
+      m = (colstart[xa + 1] - cs - 1) >> 1;
+    }
+    float2 r1[2][A];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) {
+        const int y = B * n1 + t + 8 * i;
+        const int n2 = y < N / 2 ? y : y - N;
+        r1[i][n1] = (n2 <= m && -n2 <= m) ? sb[cs + n2 + m] : zero;
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int n2 = t + 8 * i;
+      SmallDft<T, A, +1>::run(r1[i]);
+#pragma unroll
+      for (int k1 = 1; k1 < A; ++k1) {
+        float2 w = tw[(n2 * k1) % N];
+        w.y = -w.y;
+        r1[i][k1] = cmul<T>(r1[i][k1], w);
+      }
+      if (act)
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+          const int e = B * k1 + n2;
+          plane[e * N + p128_col(e, xa)] = r1[i][k1];
+        }
+    }
+    wave_sync();
+    float2 r2[B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      const int e = B * t + n2;
+      r2[n2] = plane[e * N + p128_col(e, xa)];
+    }
+    SmallDft<T, B, +1>::run(r2);
+    wave_sync();
+    if (act)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) {
+        const int e = t + A * k2;
+        plane[e * N + p128_col(e, xa)] = r2[k2];
+      }
+  }
+  __syncthreads();
+  // ---- along x on every row: inverse, * V, forward ----
+  {
+    // V(r) of this thread's row (x = t + 8 k2), issued before the inverse stages that hide it
+    T vr[B];
+    {
+      const T* vz = V + ((long)z * N + yrow) * N + t;
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) vr[k2] = vz[A * k2];
+    }
+    const int y = yrow;
+    const int sy = (((y >> 4) ^ y) & 1) << 3, py = (y & 1) << 3;
+    float2* row = plane + y * N;
+    float2 r1[2][A];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) {
+        const int x = B * n1 + t + 8 * i;
+        const int k = x < N / 2 ? x : x - N;
+        r1[i][n1] = (k <= n1max && -k <= n1max) ? row[(k + n1max) ^ sy] : zero;
+      }
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int n2 = t + 8 * i;
+      SmallDft<T, A, +1>::run(r1[i]);
+#pragma unroll
+      for (int k1 = 1; k1 < A; ++k1) {
+        float2 w = tw[(n2 * k1) % N];
+        w.y = -w.y;
+        r1[i][k1] = cmul<T>(r1[i][k1], w);
+      }
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) row[B * k1 + (n2 ^ k1 ^ py)] = r1[i][k1];
+    }
+    wave_sync();
+    float2 r2[B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) r2[n2] = row[B * t + (n2 ^ t ^ py)];
+    SmallDft<T, B, +1>::run(r2);  // r2[k2] = value at x = t + 8 k2
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) r2[k2] = cscale<T>(r2[k2], vr[k2]);
+    SmallDft<T, B, -1>::run(r2);  // over m2, output q2
+#pragma unroll
+    for (int q2 = 1; q2 < B; ++q2) r2[q2] = cmul<T>(r2[q2], tw[(t * q2) % N]);
+    wave_sync();
+#pragma unroll
+    for (int q2 = 0; q2 < B; ++q2) row[(A * q2 + (t ^ (q2 & 7))) ^ py] = r2[q2];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int q2 = t + 8 * i;
+#pragma unroll
+      for (int m1 = 0; m1 < A; ++m1) r1[i][m1] = row[(A * q2 + (m1 ^ (q2 & 7))) ^ py];
+      SmallDft<T, A, -1>::run(r1[i]);  // r1[i][q1] = F[16 q1 + q2]
+    }
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q1 = 0; q1 < A; ++q1) {
+        const int x = B * q1 + t + 8 * i;
+        const int k = x < N / 2 ? x : x - N;
+        if (k <= n1max && -k <= n1max) row[(k + n1max) ^ sy] = r1[i][q1];
+      }
+  }
+  __syncthreads();
+  // ---- forward along y, active columns, into the sticks ----
+  for (int grp = wv; grp * LPW < n1a; grp += NW) {
+    const int xa = grp * LPW + l;
+    const bool act = xa < n1a;
+    int cs = 0, m = -1;
+    if (act) {
+      cs = colstart[xa];
+      m = (colstart[xa + 1] - cs - 1) >> 1;
+    }
+    float2 r1[2][A];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) {
+        const int e = B * n1 + t + 8 * i;
+        r1[i][n1] = plane[e * N + p128_col(e, xa)];
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int n2 = t + 8 * i;
+      SmallDft<T, A, -1>::run(r1[i]);
+#pragma unroll
+      for (int k1 = 1; k1 < A; ++k1) r1[i][k1] = cmul<T>(r1[i][k1], tw[(n2 * k1) % N]);
+    }
+    wave_sync();
+    if (act)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+          const int e = B * k1 + t + 8 * i;
+          plane[e * N + p128_col(e, xa)] = r1[i][k1];
+        }
+    wave_sync();
+    float2 r2[B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      const int e = B * t + n2;
+      r2[n2] = plane[e * N + p128_col(e, xa)];
+    }
+    SmallDft<T, B, -1>::run(r2);  // r2[k2] = value at y = t + 8 k2
+    if (act)
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) {
+        const int y = t + A * k2;
+        const int n2 = y < N / 2 ? y : y - N;
+        if (n2 <= m && -n2 <= m) sb[cs + n2 + m] = cscale<T>(r2[k2], scale);
+      }
+  }
+}
+
 // ---- z transforms of the sticks with compile-time N = A B ---------------------------------
 // gcd(A, B) threads share a stick; a block takes SPW sticks of one band (at most 256 threads and
 // 48 KB of LDS).  Stick element i (0 <= i < len, h = (len - 1) / 2) sits at z = i - h mod N.
@@ -553,8 +760,15 @@ bool plane_n_supported(int n1, int n2, int real_bytes, size_t max_lds) {
 }
 
 template <typename T>
-hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const GridDesc& g,
-                          const cplx<T>* tw, T scale, hipStream_t s) {
+hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const int* colstart,
+                          const GridDesc& g, const cplx<T>* tw, T scale, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (g.n1 == 128 && g.n2 == 128 && g.n1a <= 128) {
+      const size_t lds = (size_t)(128 * 128 + 128) * sizeof(float2);
+      hipLaunchKernelGGL(k_plane128, dim3(g.n3, nbatch), dim3(1024), lds, s, SB, V, colstart, g, tw, scale);
+      return hipGetLastError();
+    }
+  }
   hipError_t e = hipErrorInvalidValue;
   if (!launch_plane_n_sized<T>(g.n1, SB, V, nbatch, st, g, tw, scale, s, &e)) return hipErrorInvalidValue;
   return e;
@@ -577,11 +791,13 @@ void pw_allow_large_lds_plane_n() {
   PW_ALLOW(8, 12, 512)
   PW_ALLOW(8, 16, 1024)
 #undef PW_ALLOW
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_plane128), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
 }
 
-template hipError_t launch_plane_n<float>(cplx<float>*, const float*, int, const Stick*, const GridDesc&,
-                                          const cplx<float>*, float, hipStream_t);
-template hipError_t launch_plane_n<double>(cplx<double>*, const double*, int, const Stick*, const GridDesc&,
-                                           const cplx<double>*, double, hipStream_t);
+template hipError_t launch_plane_n<float>(cplx<float>*, const float*, int, const Stick*, const int*,
+                                          const GridDesc&, const cplx<float>*, float, hipStream_t);
+template hipError_t launch_plane_n<double>(cplx<double>*, const double*, int, const Stick*, const int*,
+                                           const GridDesc&, const cplx<double>*, double, hipStream_t);
 
 }  // namespace pw

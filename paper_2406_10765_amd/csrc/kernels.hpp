@@ -40,9 +40,11 @@ template <typename T>
 hipError_t launch_sticks_fwd_n(const cplx<T>* SB, cplx<T>* Z, long ldz, int nbatch, const Stick* st,
                                const GridDesc& g, const cplx<T>* tw3, hipStream_t s);
 bool plane_n_supported(int n1, int n2, int real_bytes, size_t max_lds);
+// colstart: first stick of each active column xa = n1 + n1max (n1a + 1 entries; a column's sticks
+// run over n2 = -m .. m in order).
 template <typename T>
-hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const GridDesc& g,
-                          const cplx<T>* tw, T scale, hipStream_t s);
+hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const int* colstart,
+                          const GridDesc& g, const cplx<T>* tw, T scale, hipStream_t s);
 void pw_allow_large_lds_plane_n();
 // Pencil form: y inverse (sticks -> G1), x rows (inverse, * V, forward; mode 1: inverse only to vout),
 // y forward (G1 -> sticks * scale).

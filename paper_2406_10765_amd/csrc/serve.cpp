@@ -38,7 +38,8 @@ struct Request {
   size_t off = 0;
   long ld = 0;
   int bypassed = 0;     // times a later request was admitted ahead of this one
-  std::string message;  // pw_last_error text of the failing call (empty when status is PW_OK)
+  std::string message;  // pw_last_error text of the failing call, or of a step the solve retried
+  int retried = 0;      // steps the solve took again after a failed Cholesky test
 };
 
 // First-fit allocator over [0, size) with coalescing.
@@ -170,7 +171,12 @@ void pw_server_s::run(Request* q, hipStream_t stream) {
                &steps);
   q->steps = steps;
   q->status = s;
-  if (s != PW_OK) q->message = std::string("pw_solve: ") + pw_last_error(h);
+  const char* rmsg = nullptr;
+  q->retried = pw_solve_retries(h, &rmsg);
+  if (s != PW_OK)
+    q->message = std::string("pw_solve: ") + pw_last_error(h);
+  else if (q->retried > 0 && rmsg)
+    q->message = std::string("pw_solve retried ") + rmsg;
   pw_destroy(h);
 }
 
@@ -308,6 +314,7 @@ pw_status pw_poll(pw_server* s, unsigned long long ticket, pw_result* out) {
   out->t_admit = q->t_admit;
   out->t_done = q->t_done;
   std::snprintf(out->message, sizeof(out->message), "%s", q->message.c_str());
+  out->retried = q->retried;
   return PW_OK;
 }
 

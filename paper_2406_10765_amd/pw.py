@@ -101,7 +101,7 @@ class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("nbands", ctypes.c_int), ("steps", ctypes.c_int),
                 ("eig", ctypes.POINTER(ctypes.c_double)), ("resid", ctypes.POINTER(ctypes.c_double)),
                 ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
-                ("message", ctypes.c_char * 256)]
+                ("message", ctypes.c_char * 256), ("retried", ctypes.c_int)]
 
 
 class PWError(RuntimeError):
@@ -161,6 +161,8 @@ def lib() -> ctypes.CDLL:
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    L.pw_solve_retries.argtypes = [vp, P(ctypes.c_char_p)]
+    L.pw_solve_retries.restype = ctypes.c_int
     L.pw_server_clock.argtypes = [vp]
     L.pw_server_clock.restype = ctypes.c_double
     L.pw_last_error.argtypes = [vp]
@@ -421,6 +423,7 @@ class Handle:
                             res.ctypes.data_as(dp), ctypes.byref(steps))
         if st not in (PW_OK, PW_ENOTCONV):
             _check(st, self._h)
+        self.last_solve_retries = int(lib().pw_solve_retries(self._h, None))
         return eig, res, int(steps.value), st == PW_OK
 
 
@@ -486,7 +489,7 @@ class Server:
         _check(st)
         return {"status": out.status, "eig": eig[: out.nbands], "resid": res[: out.nbands], "steps": out.steps,
                 "t_arrive": out.t_arrive, "t_admit": out.t_admit, "t_done": out.t_done,
-                "message": out.message.decode(errors="replace")}
+                "message": out.message.decode(errors="replace"), "retried": int(out.retried)}
 
     def close(self):
         if getattr(self, "_s", None):

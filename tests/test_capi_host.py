@@ -148,3 +148,7 @@ def test_binding_flags_and_statuses_match_the_header():
     for name, val in re.findall(r"\b(PW_[A-Z]+) = (-?\d+)", hdr):
         if hasattr(pw, name):
             assert getattr(pw, name) == int(val), name
+
+
+def test_solve_retries_of_a_null_handle():
+    assert pw.lib().pw_solve_retries(None, None) == -1

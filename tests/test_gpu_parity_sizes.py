@@ -32,7 +32,7 @@ def gpu():
 
 
 # --- H X at every compiled FFT size (Si8 with the grid forced) --------------------------------
-SIZES = [32, 48, 54, 81, 96, 192]
+SIZES = [32, 48, 54, 81, 96, 128, 192]
 CASES = []
 for n in SIZES:
     CASES.append((n, pw.PW_FP64, 0, 1e-12))

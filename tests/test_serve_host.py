@@ -129,7 +129,7 @@ def test_concurrent_submitters_respect_slots_and_arena():
         assert time.time() - t0 < 30
         time.sleep(0.002)
     srv.close()
-    assert all(r["status"] == pw.PW_OK and r["message"] == "" for r in out.values())
+    assert all(r["status"] == pw.PW_OK and r["message"] == "" and r["retried"] == 0 for r in out.values())
     iv = [(out[i]["t_admit"], out[i]["t_done"], _need(cells[i])) for i in range(len(cells))]
     for a, _, _ in iv:
         running = [(s, e, n) for s, e, n in iv if s <= a < e]
