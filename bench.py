@@ -300,6 +300,30 @@ def cpu_baseline(cell, nb: int, m: int, sample_bands: int = 32):
     }
 
 
+def validate_cpu_baseline(workload: str, m: int, sample_bands: int = 32):
+    """The extrapolation of cpu_baseline next to one fully timed oracle step of the same cell (all
+    bands, degree m, from a seeded block), on the same cores: the check of the extrapolation."""
+    from oracle import pw_oracle as O
+    from paper_2406_10765_amd import synth
+
+    cell = synth.make_cell(workload)
+    nb = cell.nbands
+    est = cpu_baseline(cell, nb, m, sample_bands)
+    cores = est["cores"]
+    O.FFT_WORKERS = cores
+    model = O.model_from_cell(cell)
+    hop = lambda Y: O.apply_h(model, Y)
+    X0 = synth.initial_block(model.miller, cell.L, nb, 6)
+    s0 = O.eig_step(hop, X0, 0, 0.0, 0.0, 1.0)
+    b = 1.01 * O.lanczos_max(hop, model.npw, 20, seed=3)
+    t0 = time.time()
+    O.eig_step(hop, s0.X, m, s0.a_lo, s0.a, b)
+    full = time.time() - t0
+    return {"workload": workload, "bands": nb, "degree": m, "cores": cores,
+            "extrapolated_step_s": est["extrapolated_step_s"], "timed_step_s": full,
+            "ratio_extrapolated_over_timed": est["extrapolated_step_s"] / full, "sample": est["sample"]}
+
+
 def peak_in_flight(intervals):
     ev = sorted([(a, 1) for a, _ in intervals] + [(d, -1) for _, d in intervals], key=lambda e: (e[0], e[1]))
     cur = peak = 0
@@ -391,9 +415,15 @@ def main():
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--accuracy-workload", default="si64",
                     help="cell of the mixed-vs-FP64 comparison at convergence ('none' to skip)")
+    ap.add_argument("--validate-cpu-baseline", default=None, metavar="WORKLOAD",
+                    help="CPU only: time one full oracle step of WORKLOAD beside the extrapolation and exit")
     ap.add_argument("--filter-only", action="store_true",
                     help="set up the workload, run one degree-m filter step and exit (for counter runs)")
     args = ap.parse_args()
+    if args.validate_cpu_baseline:
+        print(json.dumps({"cpu_baseline_validation": validate_cpu_baseline(args.validate_cpu_baseline,
+                                                                           args.degree)}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
