@@ -406,8 +406,8 @@ def main():
     ap.add_argument("--no-lobpcg", action="store_true", help="skip the LOBPCG step timing")
     ap.add_argument("--flags", type=int, default=None,
                     help="mixed-precision product flags (bit 2: bf16 Gram, 4: bf16 projectors, 8: bf16 rotation)")
-    ap.add_argument("--serving-requests", type=int, default=64,
-                    help="requests in the serving mix (0 = skip; the full recipe has 200)")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests in the serving mix (0 = skip; the recipe has 200)")
     ap.add_argument("--serving-rate", type=float, default=20.0)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-only", action="store_true")

@@ -187,7 +187,9 @@ pw_status pw_apply_h_noalloc(pw_handle *h, const void *X_dev, void *HX_dev, int 
  * (unnormalised inverse transform, no volume factor; the caller scales).  occ_host: nb finite
  * band weights on the host (e.g. 2 for each doubly occupied band), copied during the call.
  * rho_dev: N1 N2 N3 doubles on the device, layout [j3][j2][j1] (j1 fastest), overwritten.
- * Accumulated in FP64 over bands in index order (deterministic).  Uses the handle's work
+ * Accumulated in FP64 in a fixed order (deterministic): over bands in index order, or, on
+ * 128 x 128 FP32 planes, within consecutive band groups in index order and then over the groups
+ * in order (the fused form, which writes one grid per group).  Uses the handle's work
  * buffers; returns after rho is complete.  PW_EINVAL for bad sizes, null pointers or
  * non-finite weights.
  */

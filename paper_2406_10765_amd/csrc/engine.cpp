@@ -27,6 +27,7 @@
 
 #include "../../include/pw.h"
 #include "kernels.hpp"
+#include "slots.hpp"
 #include "plan.hpp"
 
 using namespace pw;
@@ -74,6 +75,7 @@ struct pw_handle_s {
   double bmax_cached = NAN;
   // lambda_1 and lambda_nb of the last successful pw_eig_step on this handle (NaN before one)
   double last_lo = NAN, last_hi = NAN;
+  bool lent = false;            // rocBLAS handle, second stream and events belong to a request-loop slot
   int solve_retries = 0;        // steps of the last pw_solve taken again after a failed Cholesky
   std::string solve_retry_msg;  // the text of that failure
   // PW_PROGRESS=1 in the environment: report each completed filter block of a band-blocked
@@ -161,10 +163,10 @@ struct pw_handle_s {
   ~pw_handle_s() {
     if (aux) {
       hipStreamSynchronize(aux);
-      hipStreamDestroy(aux);
+      if (!lent) hipStreamDestroy(aux);
     }
-    if (ev_fork) hipEventDestroy(ev_fork);
-    if (ev_join) hipEventDestroy(ev_join);
+    if (ev_fork && !lent) hipEventDestroy(ev_fork);
+    if (ev_join && !lent) hipEventDestroy(ev_join);
     for (const Rec& r : pending) {
       hipEventDestroy(r.a);
       hipEventDestroy(r.b);
@@ -457,8 +459,31 @@ struct Engine {
     const cplx<T>* tw2 = h->at<cplx<T>>(P.lay.tw2);
     const cplx<T>* tw3 = h->at<cplx<T>>(P.lay.tw3);
     T* psq = h->at<T>(P.lay.u0);
-    // bands per pass: the stick batch, and as many |psi|^2 grids as u0 holds
     const long u0_elems = 2L * P.ldw * P.nbb;
+    if constexpr (std::is_same<T, float>::value) {
+      if (P.fl.fused && density128_supported(g, P.real_bytes)) {
+        // fused: one FP64 grid per band group (about two groups per compute unit in all), summed
+        // into rho per batch
+        int cus = 256;
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        int ngroups = std::max(1, (cus + g.n3 - 1) / g.n3);
+        double* part = reinterpret_cast<double*>(psq);  // ngroups grids of nr doubles
+        if ((long)ngroups * nr * 2 > u0_elems) {
+          ngroups = 1;  // the group sums do not fit the work buffer: one group, straight into rho
+          part = nullptr;
+        }
+        for (int b0 = 0; b0 < nb; b0 += P.fft_batch) {
+          const int nbt = std::min(P.fft_batch, nb - b0);
+          PW_TIMED(PW_PH_STICKS_INV,
+                   launch_sticks_inv<T>(X + (long)b0 * ld, ld, SB, nbt, st, g, tw3, P.fl, h->stream));
+          PW_TIMED(PW_PH_PLANE, launch_density128(SB, cs, g, tw1, occ + b0, nbt, ngroups, part, rho, b0 == 0,
+                                                  h->stream));
+        }
+        return PW_OK;
+      }
+    }
+    // bands per pass: the stick batch, and as many |psi|^2 grids as u0 holds
     const int per = (int)std::min<long>(P.fft_batch, u0_elems / nr);
     if (per < 1) return fail(h, PW_EINVAL, "density: the work buffer cannot hold one real-space grid");
     for (int b0 = 0; b0 < nb; b0 += per) {
@@ -1209,6 +1234,42 @@ pw_status pw_plan_gvectors(const pw_cell_desc* desc, int* miller) {
 
 pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes, void* hip_stream,
                    pw_handle** out) {
+  return pw::setup_handle(desc, arena_dev, arena_bytes, hip_stream, nullptr, out);
+}
+
+}  // extern "C"
+
+namespace pw {
+
+pw_status slot_resources_create(hipStream_t stream, SlotResources* r) {
+  *r = SlotResources{};
+  if (rocblas_create_handle(&r->blas) != rocblas_status_success) {
+    r->blas = nullptr;
+    return fail(nullptr, PW_EDEVICE, "rocblas_create_handle failed");
+  }
+  rocblas_set_stream(r->blas, stream);
+  if (hipStreamCreateWithFlags(&r->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess) {
+    slot_resources_destroy(r);
+    return fail(nullptr, PW_EDEVICE, "stream or event creation failed");
+  }
+  return PW_OK;
+}
+
+void slot_resources_destroy(SlotResources* r) {
+  if (r->aux) {
+    hipStreamSynchronize(r->aux);
+    hipStreamDestroy(r->aux);
+  }
+  if (r->ev_fork) hipEventDestroy(r->ev_fork);
+  if (r->ev_join) hipEventDestroy(r->ev_join);
+  if (r->blas) rocblas_destroy_handle(r->blas);
+  *r = SlotResources{};
+}
+
+pw_status setup_handle(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes, void* hip_stream,
+                       const SlotResources* res, pw_handle** out) {
   if (!out) return fail(nullptr, PW_EINVAL, "null handle pointer");
   *out = nullptr;
   if (!arena_dev) return fail(nullptr, PW_EINVAL, "null arena");
@@ -1255,17 +1316,26 @@ pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes
   h->arena = static_cast<unsigned char*>(arena_dev);
   h->arena_bytes = arena_bytes;
   h->stream = static_cast<hipStream_t>(hip_stream);
-  if (rocblas_create_handle(&h->blas) != rocblas_status_success) {
-    delete h;
-    return fail(nullptr, PW_EDEVICE, "rocblas_create_handle failed");
-  }
-  rocblas_set_stream(h->blas, h->stream);
-  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
-    rocblas_destroy_handle(h->blas);
-    delete h;
-    return fail(nullptr, PW_EDEVICE, "stream or event creation failed");
+  if (res) {
+    // lent by a request-loop slot (same stream): no creation, no destruction per request
+    h->lent = true;
+    h->blas = res->blas;
+    h->aux = res->aux;
+    h->ev_fork = res->ev_fork;
+    h->ev_join = res->ev_join;
+  } else {
+    if (rocblas_create_handle(&h->blas) != rocblas_status_success) {
+      delete h;
+      return fail(nullptr, PW_EDEVICE, "rocblas_create_handle failed");
+    }
+    rocblas_set_stream(h->blas, h->stream);
+    if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+      rocblas_destroy_handle(h->blas);
+      delete h;
+      return fail(nullptr, PW_EDEVICE, "stream or event creation failed");
+    }
   }
   if (h->plan.fl.fused) {
     // allow large dynamic LDS for the fused plane kernels: once per process, so that no thread
@@ -1279,13 +1349,17 @@ pw_status pw_setup(const pw_cell_desc* desc, void* arena_dev, size_t arena_bytes
   s = h->plan.prec == PW_FP64 ? Engine<double>(h).setup() : Engine<float>(h).setup();
   if (s != PW_OK) {
     g_last_error = h->err;
-    rocblas_destroy_handle(h->blas);
+    if (!h->lent) rocblas_destroy_handle(h->blas);
     delete h;
     return s;
   }
   *out = h;
   return PW_OK;
 }
+
+}  // namespace pw
+
+extern "C" {
 
 pw_status pw_query(const pw_handle* h, pw_info* out) {
   if (!h || !out) return fail(nullptr, PW_EINVAL, "null argument");
@@ -1604,7 +1678,7 @@ pw_status pw_reset_stats(pw_handle* h) {
 pw_status pw_destroy(pw_handle* h) {
   if (!h) return PW_OK;
   if (h->stream) hipStreamSynchronize(h->stream);
-  if (h->blas) rocblas_destroy_handle(h->blas);
+  if (h->blas && !h->lent) rocblas_destroy_handle(h->blas);
   delete h;
   return PW_OK;
 }

@@ -510,6 +510,189 @@ __global__ __launch_bounds__(1024) void k_plane128(float2* __restrict__ SB, cons
   }
 }
 
+namespace p128 {
+constexpr int N = 128, A = 8, B = 16, LPW = 8;
+
+__device__ __forceinline__ void yinv_load(const float2* __restrict__ sb, const int* __restrict__ colstart, int n1a,
+                                          int grp, int l, int t, float2 (&r)[2][A]) {
+  const int xa = grp * LPW + l;
+  int cs = 0, m = -1;
+  if (xa < n1a) {
+    cs = colstart[xa];
+    m = (colstart[xa + 1] - cs - 1) >> 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) {
+      const int y = B * n1 + t + 8 * i;
+      const int n2 = y < N / 2 ? y : y - N;
+      r[i][n1] = (n2 <= m && -n2 <= m) ? sb[cs + n2 + m] : make_float2(0.f, 0.f);
+    }
+}
+
+__device__ __forceinline__ void yinv_compute(float2* plane, const float2* tw, int n1a, int grp, int l, int t,
+                                             float2 (&r1)[2][A]) {
+  const int xa = grp * LPW + l;
+  const bool act = xa < n1a;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int n2 = t + 8 * i;
+    SmallDft<float, A, +1>::run(r1[i]);
+#pragma unroll
+    for (int k1 = 1; k1 < A; ++k1) {
+      float2 w = tw[(n2 * k1) % N];
+      w.y = -w.y;
+      r1[i][k1] = cmul<float>(r1[i][k1], w);
+    }
+    if (act)
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        const int e = B * k1 + n2;
+        plane[e * N + p128_col(e, xa)] = r1[i][k1];
+      }
+  }
+  wave_sync();
+  float2 r2[B];
+#pragma unroll
+  for (int n2 = 0; n2 < B; ++n2) {
+    const int e = B * t + n2;
+    r2[n2] = plane[e * N + p128_col(e, xa)];
+  }
+  SmallDft<float, B, +1>::run(r2);
+  wave_sync();
+  if (act)
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) {
+      const int e = t + A * k2;
+      plane[e * N + p128_col(e, xa)] = r2[k2];
+    }
+}
+}  // namespace p128
+
+// Charge density on 128 x 128 FP32 planes, fused: a workgroup takes one z plane and a group of the
+// batch's bands, runs the inverse y pass (as k_plane128) and the inverse x pass of each band, and
+// adds occ_b |psi_b(r)|^2 to FP64 registers of its rows' grid points, bands in order; the group's
+// sum goes out once (part[group][z][y][x]) instead of one |psi|^2 grid per band.  8 waves; each
+// wave owns two rows per line (y0 = 8 w + l,
+// y1 = 8 (w + 8) + l), so a thread keeps 32 sums.
+__device__ __forceinline__ void xinv_row_acc(float2* plane, const float2* tw, int y, int t, int n1max, double occ,
+                                             double (&acc)[16]) {
+  constexpr int N = 128, A = 8, B = 16;
+  const int sy = (((y >> 4) ^ y) & 1) << 3, py = (y & 1) << 3;
+  float2* row = plane + y * N;
+  float2 r1[2][A];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) {
+      const int x = B * n1 + t + 8 * i;
+      const int k = x < N / 2 ? x : x - N;
+      r1[i][n1] = (k <= n1max && -k <= n1max) ? row[(k + n1max) ^ sy] : make_float2(0.f, 0.f);
+    }
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int n2 = t + 8 * i;
+    SmallDft<float, A, +1>::run(r1[i]);
+#pragma unroll
+    for (int k1 = 1; k1 < A; ++k1) {
+      float2 w = tw[(n2 * k1) % N];
+      w.y = -w.y;
+      r1[i][k1] = cmul<float>(r1[i][k1], w);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) row[B * k1 + (n2 ^ k1 ^ py)] = r1[i][k1];
+  }
+  wave_sync();
+  float2 r2[B];
+#pragma unroll
+  for (int n2 = 0; n2 < B; ++n2) r2[n2] = row[B * t + (n2 ^ t ^ py)];
+  SmallDft<float, B, +1>::run(r2);  // r2[k2] = psi at x = t + 8 k2
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) acc[k2] += occ * ((double)r2[k2].x * r2[k2].x + (double)r2[k2].y * r2[k2].y);
+}
+
+__global__ __launch_bounds__(512) void k_density128(const float2* __restrict__ SB, const int* __restrict__ colstart,
+                                                    GridDesc g, const float2* __restrict__ twg,
+                                                    const double* __restrict__ occ, int nbt, int per,
+                                                    double* __restrict__ part, int add) {
+  constexpr int N = 128, A = 8, LPW = 8, NW = 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* plane = reinterpret_cast<float2*>(smem_raw);
+  float2* tw = plane + N * N;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l = lane >> 3, t = lane & 7;
+  const int z = blockIdx.x, grp = blockIdx.y;
+  const int n1max = g.n1max, n1a = g.n1a;
+  const int ngrp = (n1a + LPW - 1) / LPW;
+  const int y0 = wv * LPW + l, y1 = (wv + NW) * LPW + l;
+  const int b_lo = grp * per, b_hi = min(nbt, b_lo + per);
+  for (int i = tid; i < N; i += 64 * NW) tw[i] = twg[i];
+  double acc0[16], acc1[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc0[k] = acc1[k] = 0.0;
+  __syncthreads();
+  for (int b = b_lo; b < b_hi; ++b) {
+    const float2* sb = SB + ((long)b * g.n3 + z) * g.nst;
+    for (int cg = wv; cg < ngrp; cg += NW) {
+      float2 r[2][A];
+      p128::yinv_load(sb, colstart, n1a, cg, l, t, r);
+      p128::yinv_compute(plane, tw, n1a, cg, l, t, r);
+    }
+    __syncthreads();
+    const double o = occ[b];
+    xinv_row_acc(plane, tw, y0, t, n1max, o, acc0);
+    __builtin_amdgcn_sched_barrier(0);
+    xinv_row_acc(plane, tw, y1, t, n1max, o, acc1);
+    __syncthreads();
+  }
+  double* pz = part + ((long)grp * g.n3 + z) * N * N;
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    double* q0 = pz + (long)y0 * N + t + A * k2;
+    double* q1 = pz + (long)y1 * N + t + A * k2;
+    *q0 = add ? *q0 + acc0[k2] : acc0[k2];
+    *q1 = add ? *q1 + acc1[k2] : acc1[k2];
+  }
+}
+
+// rho[r] = (first ? 0 : rho[r]) + sum over groups of part[group][r], groups in order
+__global__ void k_density_groups(const double* __restrict__ part, int ngroups, long nr, double* __restrict__ rho,
+                                 int first) {
+  PW_GRID_STRIDE(r, nr) {
+    double s = first ? 0.0 : rho[r];
+    for (int q = 0; q < ngroups; ++q) s += part[(long)q * nr + r];
+    rho[r] = s;
+  }
+}
+
+bool density128_supported(const GridDesc& g, int real_bytes) {
+  return real_bytes == 4 && g.n1 == 128 && g.n2 == 128 && g.n1a <= 128;
+}
+
+hipError_t launch_density128(const float2* SB, const int* colstart, const GridDesc& g, const float2* tw,
+                             const double* occ, int nbt, int ngroups, double* part, double* rho, bool first,
+                             hipStream_t s) {
+  if (nbt <= 0) return hipSuccess;
+  const size_t lds = (size_t)(128 * 128 + 128) * sizeof(float2);
+  if (!part || ngroups <= 1) {
+    // one group per plane: its sum goes straight into rho
+    hipLaunchKernelGGL(k_density128, dim3(g.n3, 1), dim3(512), lds, s, SB, colstart, g, tw, occ, nbt, nbt, rho,
+                       first ? 0 : 1);
+    return hipGetLastError();
+  }
+  if (ngroups > nbt) ngroups = nbt;
+  const int per = (nbt + ngroups - 1) / ngroups;
+  ngroups = (nbt + per - 1) / per;
+  hipLaunchKernelGGL(k_density128, dim3(g.n3, ngroups), dim3(512), lds, s, SB, colstart, g, tw, occ, nbt, per, part,
+                     0);
+  const long nr = 128L * 128 * g.n3;
+  hipLaunchKernelGGL(k_density_groups, dim3(stride_blocks(nr)), dim3(256), 0, s, part, ngroups, nr, rho,
+                     first ? 1 : 0);
+  return hipGetLastError();
+}
+
 // ---- z transforms of the sticks with compile-time N = A B ---------------------------------
 // gcd(A, B) threads share a stick; a block takes SPW sticks of one band (at most 256 threads and
 // 48 KB of LDS).  Stick element i (0 <= i < len, h = (len - 1) / 2) sits at z = i - h mod N.
@@ -792,6 +975,8 @@ void pw_allow_large_lds_plane_n() {
   PW_ALLOW(8, 16, 1024)
 #undef PW_ALLOW
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_plane128), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_density128), hipFuncAttributeMaxDynamicSharedMemorySize,
                             bytes);
 }
 

@@ -46,6 +46,14 @@ template <typename T>
 hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const int* colstart,
                           const GridDesc& g, const cplx<T>* tw, T scale, hipStream_t s);
 void pw_allow_large_lds_plane_n();
+// Fused charge density of nbt bands on 128 x 128 FP32 planes (sticks in SB as for the plane
+// pass): ngroups band groups per z plane, each group's FP64 sum of occ_b |psi_b|^2 in part
+// (ngroups x 128 x 128 x n3 doubles), then rho = (first ? 0 : rho) + the group sums in order;
+// with part == nullptr (or one group) the single group's sum goes straight into rho.
+bool density128_supported(const GridDesc& g, int real_bytes);
+hipError_t launch_density128(const float2* SB, const int* colstart, const GridDesc& g, const float2* tw,
+                             const double* occ, int nbt, int ngroups, double* part, double* rho, bool first,
+                             hipStream_t s);
 // Pencil form: y inverse (sticks -> G1), x rows (inverse, * V, forward; mode 1: inverse only to vout),
 // y forward (G1 -> sticks * scale).
 template <typename T>

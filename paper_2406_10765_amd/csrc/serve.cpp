@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/pw.h"
+#include "slots.hpp"
 
 namespace {
 
@@ -100,7 +101,7 @@ struct pw_server_s {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   void worker(int slot);
-  void run(Request* q, hipStream_t stream);
+  void run(Request* q, hipStream_t stream, const pw::SlotResources* res);
   Request* admit_locked();
 };
 
@@ -124,7 +125,7 @@ Request* pw_server_s::admit_locked() {
   return nullptr;
 }
 
-void pw_server_s::run(Request* q, hipStream_t stream) {
+void pw_server_s::run(Request* q, hipStream_t stream, const pw::SlotResources* res) {
   pw_request& r = q->r;
   const int nb = r.cell.nbands;
   q->eig.assign(nb, NAN);
@@ -143,7 +144,7 @@ void pw_server_s::run(Request* q, hipStream_t stream) {
   }
   unsigned char* base = static_cast<unsigned char*>(cfg.arena_dev) + q->off;
   pw_handle* h = nullptr;
-  pw_status s = pw_setup(&r.cell, base, q->plan_bytes, stream, &h);
+  pw_status s = pw::setup_handle(&r.cell, base, q->plan_bytes, stream, res, &h);
   if (s != PW_OK) {
     q->status = s;
     q->message = std::string("pw_setup: ") + pw_last_error(nullptr);
@@ -183,9 +184,13 @@ void pw_server_s::run(Request* q, hipStream_t stream) {
 void pw_server_s::worker(int slot) {
   (void)hipSetDevice(device);
   hipStream_t stream = nullptr;
+  pw::SlotResources res;
+  bool have_res = false;
   if (!(cfg.flags & PW_SERVER_DRY_RUN)) {
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
     if (start_ev) (void)hipStreamWaitEvent(stream, start_ev, 0);
+    // one rocBLAS handle, second stream and event pair per slot, lent to each request's handle
+    have_res = pw::slot_resources_create(stream, &res) == PW_OK;
   }
   for (;;) {
     Request* q = nullptr;
@@ -200,7 +205,7 @@ void pw_server_s::worker(int slot) {
       if (!q) break;
       q->t_admit = now();
     }
-    run(q, stream);
+    run(q, stream, have_res ? &res : nullptr);
     {
       std::lock_guard<std::mutex> lk(mu);
       mem->release(q->off, q->need);
@@ -209,6 +214,7 @@ void pw_server_s::worker(int slot) {
     }
     cv.notify_all();
   }
+  if (have_res) pw::slot_resources_destroy(&res);
   if (stream) hipStreamDestroy(stream);
 }
 

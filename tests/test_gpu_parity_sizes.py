@@ -166,3 +166,25 @@ def test_si512_rayleigh_ritz_step_vs_oracle(si512_rr, prec, flags, etol):
         say("  largest per-cluster sin angle", worst)
         assert worst < 1e-8
     h.close()
+
+
+# --- the fused density on 128 x 128 FP32 planes (band groups summed in order) --------------------
+@pytest.mark.parametrize("name,nb", [("si8", 1), ("si8", 37), ("si8", 80), ("si64", 144)])
+def test_density_forced_grid_128(name, nb):
+    """Grid forced to 128^3 in mixed precision: the fused density kernel against the oracle, 1e-5 of
+    max rho.  Si8: one band group per plane written straight into rho (the work buffer cannot hold
+    group sums), one or several batches; Si64: two band groups per plane summed in order, in more
+    than one batch."""
+    cell = synth.make_cell(name, modes=True)
+    n = 128
+    model = O.model_from_cell(cell, grid=(n, n, n), with_projectors=False)
+    h = pw.Handle(cell, pw.PW_MIXED, nbands=max(nb, cell.nbands), fft_n=(n, n, n))
+    assert h.info.fused_planes == 1
+    p = pw.permutation_to(model.miller, h.gvectors())
+    X = synth.random_block(model.npw, nb, 1300 + nb).astype(np.complex64).astype(np.complex128)
+    occ = np.where(np.arange(nb) % 5 == 4, 0.0, 2.0) - 0.01 * np.arange(nb)
+    ref = O.density(X, occ, model.miller, model.grid).transpose(2, 1, 0)
+    rho = h.density(h.to_device(X[p]), occ).cpu().numpy()
+    err = float(np.abs(rho - ref).max() / np.abs(ref).max())
+    say("density 128^3 nb", nb, "rel err", err)
+    assert err < 1e-5
