@@ -146,7 +146,9 @@ pw_status pw_plan_gvectors(const pw_cell_desc *desc, int *miller_host);
 
 /*
  * Build a handle: plane-wave sphere (stick order: n1, then n2, then n3 ascending), grid,
- * V(r) on the device (V(G) -> inverse FFT), projector table, work buffers.
+ * V(r) on the device (V(G) -> inverse FFT), projector table, work buffers.  The basis is the
+ * cutoff sphere of Section II-A; the grid is the alias-free one (reading of the Section II-A
+ * grid rule); the projectors act atom by atom as in Section III-A.
  * arena_dev: caller device memory of arena_bytes >= pw_plan(...).footprint_bytes
  * (PW_ENOMEM otherwise).  hip_stream: a hipStream_t (NULL = default stream).
  * Synchronises the stream before returning.
@@ -159,7 +161,10 @@ pw_status pw_get_gvectors(const pw_handle *h, int *miller_host);
 
 /*
  * HX = H X for nb bands (1 <= nb <= nbands), device arrays with leading dimension ld >= npw
- * (same ld for both).  X and HX must not overlap.  Asynchronous on the handle's stream.
+ * (same ld for both): the Hamiltonian of Section II-A, Eq. 1 (kinetic |G|^2/2, local potential
+ * through the band-local 3D FFTs of the column partition, Section II-B, and the nonlocal
+ * pseudopotential of Section III-A).  X and HX must not overlap.  Asynchronous on the handle's
+ * stream.
  */
 pw_status pw_apply_h(pw_handle *h, const void *X_dev, void *HX_dev, int nb, int ld);
 
@@ -247,7 +252,9 @@ pw_status pw_ppcg_step(pw_handle *h, void *X_dev, void *P_dev, int nb, int ld, i
                        double *resid);
 
 /*
- * One block-eigensolver step on X (in/out, nb columns, ld >= npw):
+ * One block-eigensolver step on X (in/out, nb columns, ld >= npw): the iterative eigensolver of
+ * Section II-A, with the subspace products S = Psi^*(H Psi) of Section II-B and the FP64 dense
+ * eigensolve ("Syevd", Sections II-B and III-D):
  *   Y = T_m((H - c)/e) X / T_m((a_lo - c)/e), e = (b - a)/2, c = (b + a)/2 (m = degree;
  *       three-term recurrence, one H application per degree);
  *   W = H Y; S = Y^H Y, H_s = Y^H W (Hermitian parts); S = L L^H (FP64 Cholesky);
@@ -390,9 +397,13 @@ typedef struct pw_server_s pw_server;
 pw_status pw_server_create(const pw_server_cfg *cfg, pw_server **s);
 /* Seconds since the server was created (monotonic clock). */
 double pw_server_clock(const pw_server *s);
-/* Queue a request; t_arrive on the server clock (NaN = now).  *ticket identifies it. */
+/* Queue a request (one eigen-solve of Section II-A, run as pw_solve does); t_arrive on the server
+ * clock (NaN = now).  *ticket identifies it.  PW_ENOMEM when the request can never fit the arena,
+ * PW_EINVAL for bad parameters or a bad cell. */
 pw_status pw_submit(pw_server *s, const pw_request *r, double t_arrive, unsigned long long *ticket);
-/* PW_PENDING while queued or running; otherwise copies the result (once) and returns PW_OK. */
+/* The result of a request (the eigenvalues and residual norms of its solve, Section II-A):
+ * PW_PENDING while queued or running; otherwise copies it into *out (once; the eig and resid
+ * buffers are the caller's) and returns PW_OK.  PW_EINVAL for an unknown or consumed ticket. */
 pw_status pw_poll(pw_server *s, unsigned long long ticket, pw_result *out);
 /* Waits for running requests to finish; queued requests are dropped. */
 pw_status pw_server_destroy(pw_server *s);
