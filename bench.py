@@ -66,8 +66,18 @@ def phase_work(name: str, info, nb: int, m: int, steps: int, real_bytes: int, n1
     return None, None
 
 
-# flops the kernels execute per algorithmic flop: the Gram kernel forms all of S
+# flops the kernels execute per algorithmic flop: the Gram kernel forms all of S, except that its
+# pipelined form (blocks of 256 x 128 entries, used from nb x 2 nb >= 2^20 entries on) skips the
+# blocks of S wholly below the diagonal
 EXECUTED_PER_ALGORITHMIC = {"gram": 16.0 / 12.0}
+
+
+def gram_executed_per_algorithmic(nb: int) -> float:
+    if nb * 2 * nb < (1 << 20):
+        return 16.0 / 12.0
+    tm, tn = -(-nb // 256), -(-(2 * nb) // 128)
+    skipped = sum(1 for i in range(tm) for j in range(tn) if (j + 1) * 128 <= nb and i * 256 > j * 128 + 127)
+    return 16.0 / 12.0 * (tm * tn - skipped) / (tm * tn)
 
 
 def measured_traffic(workload, flags, phase):
@@ -90,7 +100,7 @@ def measured_traffic(workload, flags, phase):
     return 1024.0 * (k["FETCH_SIZE_KiB"] * d["scale"]["FETCH_SIZE"] + k["WRITE_SIZE_KiB"] * d["scale"]["WRITE_SIZE"])
 
 
-def phase_table(stats, info, nb, m, steps, real_bytes, n1a, nterm, fp64=False):
+def phase_table(stats, info, nb, m, steps, real_bytes, n1a, nterm, fp64=False, mixed_flags=0):
     """Per-phase rates over the timed steps and the roofline entry of the longest phase."""
     mfma_peak = PEAK_MFMA_TFLOPS["fp64" if fp64 else "fp32"]
     phases = {}
@@ -105,7 +115,10 @@ def phase_table(stats, info, nb, m, steps, real_bytes, n1a, nterm, fp64=False):
             if kind == "flop":
                 entry["tflops"] = round(amount / (st["ms"] * 1e-3) / 1e12, 2)
                 if name in nterm:
-                    ex = entry["tflops"] * nterm[name] * EXECUTED_PER_ALGORITHMIC.get(name, 1.0)
+                    ratio = EXECUTED_PER_ALGORITHMIC.get(name, 1.0)
+                    if name == "gram" and (mixed_flags & 14) == 14:
+                        ratio = gram_executed_per_algorithmic(nb)
+                    ex = entry["tflops"] * nterm[name] * ratio
                     entry["dtype"] = "bf16x%d" % nterm[name]
                     entry["tflops_bf16_executed"] = round(ex, 2)
                     entry["frac_peak"] = round(entry["tflops"] / PEAK_BF16_TFLOPS, 4)
@@ -544,7 +557,7 @@ def main():
         nterm["gram"] = 4
     if mflags & 8:
         nterm["rotate"] = 3
-    phases, dom, roofline = phase_table(stats, hm.info, nb, m, args.steps, 4, n1a, nterm)
+    phases, dom, roofline = phase_table(stats, hm.info, nb, m, args.steps, 4, n1a, nterm, mixed_flags=mflags)
     if roofline is not None:
         roofline["traffic"] = measured_traffic(args.workload, mflags, dom)
         if roofline["traffic"] is not None:

@@ -666,12 +666,14 @@ struct Engine {
   pw_status project_solve(const cplx<T>* Y, long ldy, const cplx<T>* W, long ldw, int nb) {
     double2* parts = h->at<double2>(P.lay.parts);
     double2* SH = h->at<double2>(P.lay.sh);
-    if (gram_planes() && planes_of(Y, nb) && h->wp_src == static_cast<const void*>(W))
+    if (gram_planes() && planes_of(Y, nb) && h->wp_src == static_cast<const void*>(W)) {
+      // S = Y^H Y is Hermitian: its tiles below the diagonal are skipped and mirrored afterwards
       PW_TIMED(PW_PH_GRAM, launch_gemm_cn_bf16x3_planes(yp_hi(), yp_lo(), P.ldw, yp_hi(), yp_lo(), P.ldw, nb, 2 * nb,
-                                                        P.npw, P.nsplit_gram, parts, h->stream, 4));
-    else
-      PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
-                              parts, 4));
+                                                        P.npw, P.nsplit_gram, parts, h->stream, 4, nb));
+      return dense_solve(nb, P.nsplit_gram, 0.0, true);
+    }
+    PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
+                            parts, 4));
     return dense_solve(nb, P.nsplit_gram);
   }
 
@@ -679,7 +681,8 @@ struct Engine {
   // H_s C = S C diag(lambda), C^H S C = I in FP64 (C in the H_s storage, lambda ascending).
   // With min_pivot > 0 a factor whose smallest pivot keeps no more than min_pivot of its diagonal
   // entry (|L_ii|^2 <= min_pivot S_ii) counts as a failed factorisation (PW_ENOTPD).
-  pw_status dense_solve(int nb, int nsplit, double min_pivot = 0.0) {
+  // s_upper: only S's upper triangle was computed (the lower one is taken from it).
+  pw_status dense_solve(int nb, int nsplit, double min_pivot = 0.0, bool s_upper = false) {
     double2* parts = h->at<double2>(P.lay.parts);
     double2* SH = h->at<double2>(P.lay.sh);
     double2* S = SH;
@@ -687,7 +690,10 @@ struct Engine {
     h->tbegin();
     PW_HIP(launch_reduce_parts<T>(parts, nsplit, nb, 2 * nb, nullptr, 0, SH, nb, (cplx<T>*)nullptr, 0,
                                   h->stream));
-    PW_HIP(launch_hermitize(S, nb, nb, h->stream));
+    if (s_upper)
+      PW_HIP(launch_mirror_upper(S, nb, nb, h->stream));
+    else
+      PW_HIP(launch_hermitize(S, nb, nb, h->stream));
     PW_HIP(launch_hermitize(Hs, nb, nb, h->stream));
     h->tend(PW_PH_GRAM_REDUCE);
     // Hs C = S C diag(lambda), C^H S C = I: S = L L^H, A = L^{-1} Hs L^{-H} by two triangular

@@ -965,11 +965,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
 // range is covered by whole tiles of 16: the words of each column from K up to its leading
 // dimension must be zero in both operands (the launcher checks that the leading dimensions reach
 // K rounded up to 16; the planes this library writes hold zeros there).
+// herm > 0: the first herm columns of B are A itself (a Gram matrix A^H A in them); tiles of those
+// columns that lie wholly below the diagonal are not computed (their partials are left as they
+// are: the caller takes that block from its upper triangle).
 template <int NTERM>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_cn_pipe(
     const unsigned int* __restrict__ Ah, const unsigned int* __restrict__ Al, long lda,
     const unsigned int* __restrict__ Bh, const unsigned int* __restrict__ Bl, long ldb, int M, int N, int K,
-    int kchunk, int tiles_m, int tiles_n, double2* __restrict__ part) {
+    int kchunk, int tiles_m, int tiles_n, double2* __restrict__ part, int herm) {
   constexpr int NW = 8, AT = 4;
   constexpr int AB = TileFrags<AT, true>::AB, SB = AB + pBbytes;
   constexpr int LPW = KTile<pTM, NW>::Q + KTile<pTN, NW>::Q;
@@ -980,6 +983,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int tr = t - sp * tiles_m * tiles_n;
   const int tm = tr / tiles_n, tn = tr - tm * tiles_n;
   const int i0 = tm * pTM, j0 = tn * pTN;
+  if (j0 + pTN <= herm && i0 > j0 + pTN - 1) return;  // strictly lower tile of the Gram block
   const int kb = sp * kchunk, ke = min(K, kb + kchunk);
   const int ra0 = (wave & 3) * 64, cb0 = (wave >> 2) * 64;
   const int ntiles = ke > kb ? (ke - kb + hBK - 1) / hBK : 0;
@@ -1214,7 +1218,7 @@ static bool use_pipe(const void* a, const void* a2, long lda, const void* b, con
 
 hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
                                         const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
-                                        int nsplit, double2* part, hipStream_t s, int nterm) {
+                                        int nsplit, double2* part, hipStream_t s, int nterm, int herm_cols) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int kchunk = cn_chunk(K, nsplit);
   const long kpad = (long)ceil_div(K, hBK) * hBK;  // the last tile reads the zero words up to here
@@ -1223,10 +1227,10 @@ hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned 
     dim3 grid(tm * tn * nsplit);
     if (nterm == 4)
       hipLaunchKernelGGL(k_gemm_cn_pipe<4>, grid, dim3(512), 0, s, Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, kchunk, tm,
-                         tn, part);
+                         tn, part, herm_cols);
     else
       hipLaunchKernelGGL(k_gemm_cn_pipe<3>, grid, dim3(512), 0, s, Ahi, Alo, lda, Bhi, Blo, ldb, M, N, K, kchunk, tm,
-                         tn, part);
+                         tn, part, herm_cols);
     return hipGetLastError();
   }
   const bool vec = ok_planes(Ahi, Alo, lda) && ok_planes(Bhi, Blo, ldb);

@@ -146,9 +146,12 @@ hipError_t launch_gemm_nn_bf16x3(const float2* A, long lda, const float2* B, lon
 // The same products with pre-split bf16 planes (launch_beta_planes layout): cn with A and B given
 // as planes of M and N columns of length K, nn with A = planes of K columns of length M.  Leading
 // dimensions of planes count 32-bit words.
+// herm_cols > 0: B's first herm_cols columns are A itself; the pipelined form may then skip the
+// tiles of that Gram block that lie wholly below its diagonal (their partials are not written), so
+// the caller must take the block's lower triangle from its upper one (launch_mirror_upper).
 hipError_t launch_gemm_cn_bf16x3_planes(const unsigned int* Ahi, const unsigned int* Alo, long lda,
                                         const unsigned int* Bhi, const unsigned int* Blo, long ldb, int M, int N, int K,
-                                        int nsplit, double2* part, hipStream_t s, int nterm = 3);
+                                        int nsplit, double2* part, hipStream_t s, int nterm = 3, int herm_cols = 0);
 // The cn form on planes reads the words of each column from K up to the next multiple of 16 when
 // both leading dimensions reach that far: those words must be zero.  The projector planes are
 // written with zeros there; the block planes are cleared once (at set-up, or by
@@ -242,6 +245,8 @@ hipError_t launch_scale_cols_lam(const double2* in, long ldi, cplx<T>* out, long
                                  double s, hipStream_t st);
 // Hermitian part: A <- (A + A^H)/2, n x n complex double
 hipError_t launch_hermitize(double2* A, long lda, int n, hipStream_t s);
+// Hermitian matrix from its upper triangle: A(i, j) <- conj(A(j, i)) for i > j, Im A(i, i) <- 0
+hipError_t launch_mirror_upper(double2* A, long lda, int n, hipStream_t s);
 // r_j = || W_j - lam_j X_j ||_2 with double accumulation; flag[0] |= non-finite seen
 template <typename T>
 hipError_t launch_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, const double* lam, int rows,

@@ -508,6 +508,26 @@ hipError_t launch_density_acc(const T* psq, int nbt, long nr, const double* occ,
 template hipError_t launch_density_acc<float>(const float*, int, long, const double*, double*, bool, hipStream_t);
 template hipError_t launch_density_acc<double>(const double*, int, long, const double*, double*, bool, hipStream_t);
 
+__global__ void k_mirror_upper(double2* A, long lda, int n) {
+  PW_GRID_STRIDE(idx, (long)n * n) {
+    const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
+    if (i < j) continue;
+    if (i == j) {
+      A[(long)j * lda + i].y = 0.0;
+      continue;
+    }
+    const double2 u = A[(long)i * lda + j];  // (j, i), upper
+    A[(long)j * lda + i] = make_double2(u.x, -u.y);
+  }
+}
+
+hipError_t launch_mirror_upper(double2* A, long lda, int n, hipStream_t s) {
+  const long m = (long)n * n;
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mirror_upper, dim3(stride_blocks(m)), dim3(256), 0, s, A, lda, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_hermitize(double2* A, long lda, int n, hipStream_t s) {
   const long m = (long)n * n;
   if (m <= 0) return hipSuccess;
