@@ -17,7 +17,11 @@ What it computes, and where the paper fixes it:
   subspace part forms S = Psi^* (H Psi) and solves a dense Hermitian
   eigenproblem ("Syevd", Sections II-B and III-D).
 * The pseudopotential acts atom by atom on every wavefunction
-  (Section III-A); here as Kleinman-Bylander projectors B D B^H.
+  (Section III-A); here as Kleinman-Bylander projectors B D B^H.  A second
+  projector family (PROJ_LOCALIZED: a Gaussian and a Gaussian times x, y, z in
+  real space) vanishes a few widths from its atom, so V_NL can also be applied
+  on the real-space grid over a ball around each atom
+  (apply_nonlocal_realspace), touching only the grid points near the atom.
 
 Where the paper is silent the readings are: a Chebyshev-filtered subspace
 step (degree m; m = 0 is plain Rayleigh-Ritz), an alias-free FFT grid, a
@@ -25,7 +29,9 @@ potential band-limited to the wavefunction sphere, real spherical harmonics,
 structure factors exp(-i G.tau), and the unnormalised inverse FFT
 psi(r) = sum_G c_G exp(+i G.r).
 
-Every function below is pinned by tests in tests/test_oracle_pins.py.
+Every function below is pinned by tests in tests/test_oracle_pins.py and the
+other tests/test_oracle_*_pins.py files (the localized projectors and the
+real-space route in tests/test_oracle_realspace_pins.py).
 """
 from __future__ import annotations
 
@@ -194,19 +200,36 @@ def real_harmonics_l01(G: np.ndarray) -> np.ndarray:
     return out
 
 
+PROJ_GSPACE = 0      # projectors exp(-sigma^2 |G|^2/2) Y_lm(G/|G|) (reading A7)
+PROJ_LOCALIZED = 1   # projectors that are Gaussians times r^l Y_lm in real space
+
+
 def projector_matrix(miller: np.ndarray, L: np.ndarray, tau: np.ndarray, sigma: float,
-                     sf_sign: float = -1.0) -> np.ndarray:
+                     sf_sign: float = -1.0, form: int = PROJ_GSPACE) -> np.ndarray:
     """B[G, 4a+m] = (c/sqrt(Omega)) exp(-sigma^2 |G|^2/2) Y_m(G) exp(sf_sign i G.tau_a).
 
     c = sqrt(32 pi^(5/2) sigma^3) gives unit norm in the continuum limit.
     Projector order per atom: l=0, then l=1 x, y, z.
+
+    form PROJ_LOCALIZED keeps l = 0 and replaces the l = 1 direction factor sqrt(3/(4 pi)) G_m/|G|
+    by -i sigma G_m / sqrt(2 pi): the columns are then (1/sqrt(Omega)) times the continuum Fourier
+    transforms, integral p(r - tau) exp(-i G.r) d^3r, of the unit-norm real-space functions of
+    `localized_projector_values` (a Gaussian and a Gaussian times x, y, z), so that each
+    projector vanishes beyond a few sigma of its atom (Section III-A: a projector acts near its
+    atom only).
     """
     G = gvectors(miller, L)
     g2 = (G * G).sum(axis=1)
     omega = float(np.prod(L))
     c = math.sqrt(32.0 * math.pi ** 2.5 * sigma ** 3)
     radial = (c / math.sqrt(omega)) * np.exp(-0.5 * sigma * sigma * g2)
-    ylm = real_harmonics_l01(G)
+    if form == PROJ_LOCALIZED:
+        ylm = np.empty((G.shape[0], 4), complex)
+        ylm[:, 0] = 0.5 / math.sqrt(math.pi)
+        for a in range(3):
+            ylm[:, 1 + a] = -1j * sigma * G[:, a] / math.sqrt(2.0 * math.pi)
+    else:
+        ylm = real_harmonics_l01(G)
     natoms = tau.shape[0]
     B = np.empty((G.shape[0], 4 * natoms), complex)
     for a in range(natoms):
@@ -214,6 +237,70 @@ def projector_matrix(miller: np.ndarray, L: np.ndarray, tau: np.ndarray, sigma: 
         for m in range(4):
             B[:, 4 * a + m] = radial * ylm[:, m] * sf
     return B
+
+
+def localized_projector_values(d: np.ndarray, sigma: float) -> np.ndarray:
+    """The four real-space projector functions of one atom at displacements d (..., 3) from it,
+    shape (4, ...): p_0 = pi^(-3/4) sigma^(-3/2) e^(-|d|^2/(2 sigma^2)) and
+    p_m = sqrt(2) pi^(-3/4) sigma^(-5/2) d_m e^(-|d|^2/(2 sigma^2)) (m = x, y, z), each of unit
+    norm over all space."""
+    g = np.exp(-0.5 * (d * d).sum(axis=-1) / (sigma * sigma))
+    c0 = math.pi ** -0.75 * sigma ** -1.5
+    c1 = math.sqrt(2.0) * math.pi ** -0.75 * sigma ** -2.5
+    return np.stack([c0 * g, c1 * d[..., 0] * g, c1 * d[..., 1] * g, c1 * d[..., 2] * g])
+
+
+def ball_points(L: np.ndarray, grid: Sequence[int], tau: np.ndarray, radius: float):
+    """Grid points within `radius` of tau (nearest periodic image): (flat indices into the
+    (N1, N2, N3) grid, displacements r_j - tau of shape (npts, 3)).  Needs 2 radius < min L, so
+    that no point is near two images of the atom."""
+    L = np.asarray(L, float)
+    assert 2.0 * radius < L.min(), "ball radius must stay below half the cell"
+    h = L / np.asarray(grid, float)
+    rng = []
+    for i in range(3):
+        lo = int(math.ceil((tau[i] - radius) / h[i]))
+        hi = int(math.floor((tau[i] + radius) / h[i]))
+        rng.append(np.arange(lo, hi + 1))
+    j1, j2, j3 = np.meshgrid(rng[0], rng[1], rng[2], indexing="ij")
+    j = np.stack([j1.ravel(), j2.ravel(), j3.ravel()], axis=1)
+    d = j * h - tau
+    keep = (d * d).sum(axis=1) <= radius * radius
+    j, d = j[keep], d[keep]
+    N = np.asarray(grid)
+    jw = np.mod(j, N)
+    flat = (jw[:, 0] * N[1] + jw[:, 1]) * N[2] + jw[:, 2]
+    return flat, d
+
+
+def apply_nonlocal_realspace(model: "Model", X: np.ndarray, radius: float) -> np.ndarray:
+    """V_NL X with the localized projectors applied on the real-space grid, each truncated to the
+    ball of `radius` around its atom (the one-GPU form of Section III-A's atom-by-atom
+    pseudopotential: a projector touches only the grid points near its atom):
+
+        psi_n(r)       = (1/sqrt(Omega)) sum_G X[G, n] e^{i G.r}        (normalised wavefunction)
+        P[a, m, n]     = dV sum_{r in ball a} p_m(r - tau_a) psi_n(r)      (dV = Omega / N_r)
+        NL_n(r)        = sum_a sum_m p_m(r - tau_a) D_m P[a, m, n]
+        (V_NL X)[G, n] = (1/sqrt(Omega)) dV sum_r NL_n(r) e^{-i G.r}
+
+    Without truncation this equals B D B^H X of the PROJ_LOCALIZED columns up to aliasing of the
+    projectors beyond the grid's reciprocal box."""
+    omega = model.omega
+    grid = model.grid
+    nr = int(np.prod(grid))
+    dv = omega / nr
+    X = np.asarray(X, complex)
+    psi = to_real_space(X, model.miller, grid).reshape(X.shape[1], nr) / math.sqrt(omega)
+    nl = np.zeros_like(psi)
+    d = model.D[:4]
+    for a in range(model.tau.shape[0]):
+        flat, disp = ball_points(model.L, grid, model.tau[a], radius)
+        p = localized_projector_values(disp, model.sigma)          # (4, npts)
+        Pa = dv * (psi[:, flat] @ p.T)                              # (nb, 4)
+        nl[:, flat] += (Pa * d[None, :]) @ p                        # (nb, npts)
+    nl = nl.reshape((X.shape[1],) + tuple(grid))
+    # to_g_space includes 1/N_r; (1/sqrt(Omega)) dV N_r = sqrt(Omega)
+    return math.sqrt(omega) * to_g_space(nl, model.miller)
 
 
 def scatter_to_grid(x: np.ndarray, miller: np.ndarray, grid: Sequence[int]) -> np.ndarray:
@@ -271,7 +358,10 @@ def build_model(L: Sequence[float], tau: np.ndarray, ecut: float, zval: float = 
                 d1: float = -0.7, mode_miller: Optional[np.ndarray] = None,
                 mode_amp: Optional[np.ndarray] = None, mode_phase: Optional[np.ndarray] = None,
                 grid: Optional[Sequence[int]] = None, sf_sign: float = -1.0,
-                with_projectors: bool = True) -> Model:
+                with_projectors: bool = True, proj_form: int = PROJ_GSPACE,
+                rs_radius: float = 0.0) -> Model:
+    """rs_radius > 0 (PROJ_LOCALIZED only) makes apply_h take the nonlocal part in real space on
+    balls of that radius (apply_nonlocal_realspace); B still holds the reciprocal-space columns."""
     L = np.asarray(L, float)
     tau = np.asarray(tau, float)
     mm = np.zeros((0, 3), np.int64) if mode_miller is None else np.asarray(mode_miller, np.int64)
@@ -286,7 +376,7 @@ def build_model(L: Sequence[float], tau: np.ndarray, ecut: float, zval: float = 
     scale = max(1.0, float(np.abs(vr_c).max()))
     assert float(np.abs(vr_c.imag).max()) <= 1e-12 * scale, "V(r) must be real"
     have = (d0 != 0 or d1 != 0) and tau.shape[0] > 0
-    B = projector_matrix(miller, L, tau, sigma, sf_sign) if (have and with_projectors) else \
+    B = projector_matrix(miller, L, tau, sigma, sf_sign, proj_form) if (have and with_projectors) else \
         np.zeros((miller.shape[0], 0), complex)
     D = np.tile(np.array([d0, d1, d1, d1]), tau.shape[0]) if have else np.zeros(0)
     m = Model(L=L, ecut=ecut, tau=tau, miller=miller, G=G, kin=kin, grid=grid,
@@ -294,6 +384,10 @@ def build_model(L: Sequence[float], tau: np.ndarray, ecut: float, zval: float = 
               mode_miller=mm, mode_amp=ma, mode_phase=mp, sf_sign=sf_sign)
     m.sigma = sigma
     m.atomwise = have and not with_projectors
+    if rs_radius > 0.0:
+        assert proj_form == PROJ_LOCALIZED, "real-space projectors need the localized form"
+    m.proj_form = proj_form
+    m.rs_radius = rs_radius if have else 0.0
     return m
 
 
@@ -345,7 +439,8 @@ def apply_nonlocal_atomwise(model: Model, X: np.ndarray,
     out = np.zeros_like(X)
     d = model.D[:4]
     for a in range(model.tau.shape[0]):
-        Ba = projector_matrix(model.miller, model.L, model.tau[a:a + 1], model.sigma, model.sf_sign)
+        Ba = projector_matrix(model.miller, model.L, model.tau[a:a + 1], model.sigma, model.sf_sign,
+                               getattr(model, "proj_form", PROJ_GSPACE))
         out += Ba @ (d[:, None] * (Ba.conj().T @ X))
         if progress is not None and (a + 1) % 64 == 0:
             progress(a + 1)
@@ -362,7 +457,9 @@ def apply_h(model: Model, X: np.ndarray) -> np.ndarray:
     for j in range(0, Xb.shape[1], chunk):
         psi = to_real_space(Xb[:, j:j + chunk], model.miller, model.grid)
         out[:, j:j + chunk] += to_g_space(model.vr[None] * psi, model.miller)
-    if model.B.shape[1]:
+    if getattr(model, "rs_radius", 0.0) > 0.0:
+        out = out + apply_nonlocal_realspace(model, Xb, model.rs_radius)
+    elif model.B.shape[1]:
         P = model.B.conj().T @ Xb
         out = out + model.B @ (model.D[:, None] * P)
     elif getattr(model, "atomwise", False):
