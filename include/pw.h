@@ -76,6 +76,25 @@ typedef enum {
 /* Plan the buffers of pw_lobpcg_step (the three-block basis and its Gram matrix); unblocked
    plans only (PW_EINVAL when the bands would be filtered in blocks). */
 #define PW_FLAG_LOBPCG 32u
+/* Apply the projectors in real space (Section III-A: a projector acts only near its atom):
+   each projector is truncated to the grid points within rs_radius of its atom, the projections
+   are summed over those points inside the inverse FFT plane pass (one partial per atom and z
+   plane), and D P is added back at the same points inside the plane pass of V(r), before the
+   forward transforms: O(N_atoms N_b) work per grid plane instead of the O(N_pw N_atoms N_b)
+   projector GEMMs.  Needs proj_form = PW_PROJ_LOCALIZED, PW_MIXED, a 128 x 128 (x n3) grid whose
+   planes fit in LDS, and 0 < rs_radius with 2 rs_radius < every cell length; not combinable with
+   PW_FLAG_BF16_KB or PW_FLAG_BETA_OTF (PW_EINVAL otherwise).  Phase timers: the inverse pass with
+   the projections counts as PW_PH_PROJ, their sum over planes as PW_PH_PROJ_REDUCE, the plane
+   pass with V(r) and D P as PW_PH_PLANE, the kinetic + Chebyshev update as PW_PH_NL. */
+#define PW_FLAG_RSPACE_KB 64u
+
+/* Projector families (pw_cell_desc.proj_form). */
+#define PW_PROJ_GSPACE 0    /* beta = (c/sqrt(Omega)) e^{-sigma^2 G^2/2} Y_m(G^) (see below) */
+#define PW_PROJ_LOCALIZED 1 /* the l = 1 factor Y_m(G^) becomes -i sigma G_m / sqrt(2 pi): beta is
+                               the transform of unit-norm real-space functions p_0 = pi^{-3/4}
+                               sigma^{-3/2} e^{-r^2/(2 sigma^2)} and p_m = sqrt(2) pi^{-3/4}
+                               sigma^{-5/2} r_m e^{-r^2/(2 sigma^2)}, which vanish a few sigma from
+                               the atom */
 
 typedef enum {
   PW_FP64 = 0,  /* every product and FFT in double precision */
@@ -114,6 +133,8 @@ typedef struct {
   int filter_block;          /* bands per block of the filter and of H applications; 0 = all bands
                                 while three full-size work blocks take <= 64 GiB, else blocks whose
                                 three work blocks take <= 16 GiB (a multiple of 64 bands) */
+  int proj_form;             /* PW_PROJ_GSPACE (0) or PW_PROJ_LOCALIZED */
+  double rs_radius;          /* PW_FLAG_RSPACE_KB: truncation radius of the projectors (bohr) */
 } pw_cell_desc;
 
 typedef struct {

@@ -46,6 +46,29 @@ struct Stick {
   int n2;
 };
 
+// Real-space projectors: one (atom, z plane) pair, the plane's z displacement from the atom (bohr).
+struct RsEnt {
+  int atom;
+  float dz;
+};
+
+// Tables of the real-space projectors on a 128 x 128 x n3 grid (PW_FLAG_RSPACE_KB).
+struct RsDesc {
+  const float4* atoms;  // per atom: x, y, z (bohr, inside the cell), w unused
+  const int* zoff;      // entries of plane z: zent[zoff[z] .. zoff[z + 1]); entry index = partial slot
+  const RsEnt* zent;
+  const int* boff;      // entries of plane z and row band w (rows 8w .. 8w+7): bent[boff[16z+w] ..)
+  const RsEnt* bent;
+  const int* aoff;      // the zent indices of atom a, in plane order: aent[aoff[a] .. aoff[a + 1])
+  const int* aent;
+  int nent, natoms;
+  float hx, hy;         // grid steps along x and y (bohr)
+  float ihx, ihy;       // their inverses
+  float r2;             // truncation radius squared (bohr^2)
+  float inv2s2;         // 1 / (2 sigma^2)
+  float c0, c1;         // sqrt(Omega) times the unit-norm prefactors of p_0 and p_m
+};
+
 // Radix plan of one 1D FFT length (radices in order of application).
 struct FftPlan {
   int n;

@@ -238,6 +238,28 @@ struct Engine {
     bg.natoms = P.natoms;
     return bg;
   }
+  RsDesc rs_desc() const {
+    RsDesc d{};
+    d.atoms = h->at<float4>(P.lay.rsat);
+    d.zoff = h->at<int>(P.lay.rszo);
+    d.zent = h->at<RsEnt>(P.lay.rsze);
+    d.boff = h->at<int>(P.lay.rsbo);
+    d.bent = h->at<RsEnt>(P.lay.rsbe);
+    d.aoff = h->at<int>(P.lay.rsao);
+    d.aent = h->at<int>(P.lay.rsae);
+    d.nent = (int)P.rs_zent.size();
+    d.natoms = P.natoms;
+    d.hx = (float)(P.L[0] / P.g.n1);
+    d.hy = (float)(P.L[1] / P.g.n2);
+    d.ihx = (float)(P.g.n1 / P.L[0]);
+    d.ihy = (float)(P.g.n2 / P.L[1]);
+    d.r2 = (float)(P.rs_radius * P.rs_radius);
+    d.inv2s2 = (float)(0.5 / (P.beta_sigma * P.beta_sigma));
+    const double so = std::sqrt(P.L[0] * P.L[1] * P.L[2]);
+    d.c0 = (float)(so * std::pow(3.14159265358979323846, -0.75) * std::pow(P.beta_sigma, -1.5));
+    d.c1 = (float)(so * std::sqrt(2.0) * std::pow(3.14159265358979323846, -0.75) * std::pow(P.beta_sigma, -2.5));
+    return d;
+  }
   unsigned int* beta_hi() const { return h->at<unsigned int>(P.lay.beta); }
   unsigned int* beta_lo() const { return beta_hi() + (size_t)P.ldw * P.nproj; }
   // Work buffers of an H application: the arena's, or the static work array's during
@@ -353,6 +375,44 @@ struct Engine {
     return PW_OK;
   }
 
+  // Local part and real-space projectors (PW_FLAG_RSPACE_KB), per FFT batch: sticks, then the
+  // inverse plane pass with the projections (SB only read), their sum over planes into D P (the
+  // batch's columns of PT), then the plane pass adding D P at the atoms' points to V psi before the
+  // forward transforms, then the forward sticks.  Zl receives V psi + V_NL psi on the sphere.
+  pw_status local_part_rs(const cplx<T>* Y, long ldy, cplx<T>* Z, long ldz, int nb, hipStream_t sm) {
+    if constexpr (std::is_same<T, float>::value) {
+      const GridDesc& g = P.g;
+      const float scale = (float)(1.0 / ((double)g.n1 * g.n2 * g.n3));
+      cplx<T>* SB = sb_buf();
+      const Stick* st = h->at<Stick>(P.lay.sticks);
+      const int* cs = h->at<int>(P.lay.colstart);
+      const T* V = h->at<T>(P.lay.vr);
+      const cplx<T>* tw1 = h->at<cplx<T>>(P.lay.tw1);
+      const cplx<T>* tw3 = h->at<cplx<T>>(P.lay.tw3);
+      const RsDesc rd = rs_desc();
+      float2* part = h->at<float2>(P.lay.rsp);
+      cplx<T>* PT = h->at<cplx<T>>(P.lay.pt);
+      const double* dsc = h->at<double>(P.lay.dscale);
+      const double inv_nr = 1.0 / ((double)g.n1 * g.n2 * g.n3);
+      const int fb = P.fft_batch;
+      for (int b0 = 0; b0 < nb; b0 += fb) {
+        const int nbt = std::min(fb, nb - b0);
+        PW_TIMED_ON(PW_PH_STICKS_INV, sm,
+                    launch_sticks_inv<T>(Y + (long)b0 * ldy, ldy, SB, nbt, st, g, tw3, P.fl, sm));
+        PW_TIMED_ON(PW_PH_PROJ, sm, launch_rs_proj128(SB, cs, g, tw1, rd, nbt, part, sm));
+        PW_TIMED_ON(PW_PH_PROJ_REDUCE, sm,
+                    launch_rs_reduce(part, rd, nbt, dsc, inv_nr, PT + (long)b0 * P.nproj, P.nproj, sm));
+        PW_TIMED_ON(PW_PH_PLANE, sm,
+                    launch_plane128_nl(SB, V, nbt, cs, g, tw1, scale, rd, PT + (long)b0 * P.nproj, P.nproj, sm));
+        PW_TIMED_ON(PW_PH_STICKS_FWD, sm,
+                    launch_sticks_fwd<T>(SB, Z + (long)b0 * ldz, ldz, nbt, st, g, tw3, P.fl, sm));
+      }
+      return PW_OK;
+    } else {
+      return fail(h, PW_EINVAL, "real-space projectors need PW_MIXED");
+    }
+  }
+
   // out = alpha ((kin - c) Y + Zl + B D B^H Y) - beta Yp, where Zl is first filled with the
   // local potential part.  Zl may equal out (apply_h); Yp may equal out (in-place update).
   // planes_out (split-precision projectors): PLANES_NEXT writes the bf16 planes of out for a
@@ -366,16 +426,22 @@ struct Engine {
     // phase timing on, everything stays on the caller's stream so that phase times are not
     // inflated by sharing the device.
     // Small blocks (serving-size cells) gain nothing from it and would only add streams.
-    const bool overlap = !h->timing && (double)P.npw * nb >= (double)(1 << 26);
+    const bool overlap = !P.rspace && !h->timing && (double)P.npw * nb >= (double)(1 << 26);
+    if (P.rspace) {
+      pw_status s = local_part_rs(Y, ldy, Zl, ldz, nb, h->stream);
+      if (s != PW_OK) return s;
+    }
     if (overlap) {
       PW_HIP(hipEventRecord(h->ev_fork, h->stream));
       PW_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
     }
-    pw_status s = local_part(Y, ldy, Zl, ldz, nb, overlap ? h->aux : h->stream);
-    if (s != PW_OK) return s;
+    if (!P.rspace) {
+      pw_status s = local_part(Y, ldy, Zl, ldz, nb, overlap ? h->aux : h->stream);
+      if (s != PW_OK) return s;
+    }
     if (overlap) PW_HIP(hipEventRecord(h->ev_join, h->aux));
     cplx<T>* PT = work<cplx<T>>(P.lay.pt, h->ws_pt);
-    if (P.nproj > 0) {
+    if (P.nproj > 0 && !P.rspace) {
       double2* parts = parts_buf();
       if constexpr (std::is_same<T, float>::value) {
         if (beta_planes()) {
@@ -441,7 +507,8 @@ struct Engine {
       PW_TIMED(PW_PH_NL, launch_gemm_nn_beta<T>(beta_gen(), PT, P.nproj, nb, out, ldo, e, h->stream));
       return PW_OK;
     }
-    PW_TIMED(PW_PH_NL, nn(false, beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e));
+    // real-space projectors: V_NL Y is already in Zl, the product only applies the epilogue (K = 0)
+    PW_TIMED(PW_PH_NL, nn(false, beta(), P.ldw, PT, P.nproj, P.npw, nb, P.rspace ? 0 : P.nproj, out, ldo, e));
     return PW_OK;
   }
 
@@ -1145,10 +1212,22 @@ struct Engine {
                                     h->at<double>(p.lay.brad), h->at<double2>(p.lay.bph), st));
     else if (p.nproj && beta_planes())
       PW_HIP(launch_beta_planes(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), p.natoms, p.L,
-                                p.beta_sigma, beta_hi(), beta_lo(), p.ldw, st));
-    else if (p.nproj)
+                                p.beta_sigma, p.proj_form, beta_hi(), beta_lo(), p.ldw, st));
+    else if (p.nproj && !p.rspace)
       PW_HIP(launch_beta_table<T>(h->at<int>(p.lay.miller), p.npw, h->at<double>(p.lay.frac), p.natoms, p.L,
-                                  p.beta_sigma, beta(), p.ldw, st));
+                                  p.beta_sigma, p.proj_form, beta(), p.ldw, st));
+    if (p.rspace) {
+      auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(h->at<char>(off), src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+      };
+      PW_HIP(up(p.lay.rsat, p.rs_atoms.data(), sizeof(float) * p.rs_atoms.size()));
+      PW_HIP(up(p.lay.rszo, p.rs_zoff.data(), sizeof(int) * p.rs_zoff.size()));
+      PW_HIP(up(p.lay.rsze, p.rs_zent.data(), sizeof(RsEnt) * p.rs_zent.size()));
+      PW_HIP(up(p.lay.rsbo, p.rs_boff.data(), sizeof(int) * p.rs_boff.size()));
+      PW_HIP(up(p.lay.rsbe, p.rs_bent.data(), sizeof(RsEnt) * p.rs_bent.size()));
+      PW_HIP(up(p.lay.rsao, p.rs_aoff.data(), sizeof(int) * p.rs_aoff.size()));
+      PW_HIP(up(p.lay.rsae, p.rs_aent.data(), sizeof(int) * p.rs_aent.size()));
+    }
     // the block planes' words past the last plane wave stay zero from here on (the cn products read them)
     if (p.yp_cols > 0) PW_HIP(launch_zero_plane_rows(yp_hi(), yp_lo(), p.ldw, p.npw, p.yp_cols, st));
     PW_HIP(hipStreamSynchronize(st));
@@ -1448,6 +1527,8 @@ pw_status pw_apply_h_noalloc(pw_handle* h, const void* X, void* HX, int nb, int 
   const size_t span = ((size_t)(nb - 1) * ld + h->plan.npw) * cb;
   if (x0 < y0 + span && y0 < x0 + span) return fail(h, PW_EINVAL, "X and HX overlap");
   if (!h->scratch) return fail(h, PW_EDEVICE, "no static work array on this device");
+  if (h->plan.rspace)
+    return fail(h, PW_EINVAL, "pw_apply_h_noalloc does not take handles with PW_FLAG_RSPACE_KB");
   const int w = noalloc_layout(h, nb);
   if (w < 1)
     return fail(h, PW_ENOMEM, "one band of this cell needs more than the " + std::to_string(kScratchBytes >> 20) +

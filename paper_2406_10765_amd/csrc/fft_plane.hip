@@ -303,6 +303,109 @@ __global__ __launch_bounds__(NT) void k_plane_n(cplx<T>* __restrict__ SB, const 
   }
 }
 
+// ---- real-space projectors on 128 x 128 FP32 planes --------------------------------------------
+// The projectors are truncated to the grid points within a radius R of their atom (Section III-A:
+// a projector acts only near its atom).  Entry (atom, plane) covers the rows y0 .. y0+ny-1 and
+// columns x0 .. x0+nx-1 (unwrapped grid indices) of the disc of radius sqrt(R^2 - dz^2); a point
+// belongs to the ball when its distance squared, computed by rs_point, is <= R^2.  Both passes
+// enumerate points through rs_range and rs_point, so they see the same points and the same values.
+// In the projector passes the plane holds row y in natural x order at word x ^ rs_swz(y).
+__device__ __forceinline__ int rs_swz(int y) { return (y & 15) << 3; }
+
+struct RsRange {
+  int x0, nx, y0, ny;
+  float tx, ty, dz2;
+};
+
+__device__ __forceinline__ RsRange rs_range(const RsDesc& d, int atom, float dz) {
+  const float4 t = d.atoms[atom];
+  RsRange r;
+  r.tx = t.x;
+  r.ty = t.y;
+  r.dz2 = dz * dz;
+  const float rho2 = d.r2 - r.dz2;
+  if (!(rho2 >= 0.f)) {
+    r.x0 = r.y0 = 0;
+    r.nx = r.ny = 0;
+    return r;
+  }
+  const float rho = sqrtf(rho2);
+  r.x0 = (int)ceilf((t.x - rho) * d.ihx);
+  r.nx = (int)floorf((t.x + rho) * d.ihx) - r.x0 + 1;
+  r.y0 = (int)ceilf((t.y - rho) * d.ihy);
+  r.ny = (int)floorf((t.y + rho) * d.ihy) - r.y0 + 1;
+  if (r.nx < 0) r.nx = 0;
+  if (r.ny < 0) r.ny = 0;
+  return r;
+}
+
+// sqrt(Omega) p_m(r - tau) at the point (ix, iy) of the entry; false outside the ball.
+__device__ __forceinline__ bool rs_point(const RsDesc& d, const RsRange& r, int ix, int iy, float dz, float (&p)[4]) {
+  const float dx = fmaf((float)ix, d.hx, -r.tx);
+  const float dy = fmaf((float)iy, d.hy, -r.ty);
+  const float q = fmaf(dx, dx, fmaf(dy, dy, r.dz2));
+  if (q > d.r2) return false;
+  const float g = __expf(-q * d.inv2s2);
+  const float g1 = d.c1 * g;
+  p[0] = d.c0 * g;
+  p[1] = g1 * dx;
+  p[2] = g1 * dy;
+  p[3] = g1 * dz;
+  return true;
+}
+
+// i = q n + r with 0 <= r < n, for 0 <= i < 2^15 and 1 <= n <= 128 (float quotient, one correction)
+__device__ __forceinline__ void rs_divmod(int i, int n, float inv, int& q, int& r) {
+  q = (int)((float)i * inv);
+  r = i - q * n;
+  if (r < 0) {
+    --q;
+    r += n;
+  } else if (r >= n) {
+    ++q;
+    r -= n;
+  }
+}
+
+__device__ __forceinline__ float rs_wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Adds sum_a sum_m sqrt(Omega) p_m(r - tau_a) dp_{a,m} to the rows 8w .. 8w+7 of the plane (held in
+// natural order), atoms in the order of the band's entry list.  Only the calling wave touches these
+// rows, and its LDS accesses complete in program order, so the sums at each point are taken in a
+// fixed order without atomics.
+__device__ __forceinline__ void rs_add_band(float2* plane, const RsDesc& rd, int z, int w, const float2* dp,
+                                            int lane) {
+  constexpr int N = 128;
+  const int e0 = rd.boff[16 * z + w], e1 = rd.boff[16 * z + w + 1];
+  for (int e = e0; e < e1; ++e) {
+    const RsEnt en = rd.bent[e];
+    const RsRange rr = rs_range(rd, en.atom, en.dz);
+    if (rr.nx <= 0 || rr.ny <= 0) continue;
+    const float2 c0 = dp[4 * en.atom], c1 = dp[4 * en.atom + 1], c2 = dp[4 * en.atom + 2], c3 = dp[4 * en.atom + 3];
+    const int np = 8 * rr.nx;
+    const float inv = 1.0f / (float)rr.nx;
+    for (int i = lane; i < np; i += 64) {
+      int q, r;
+      rs_divmod(i, rr.nx, inv, q, r);
+      const int y = 8 * w + q;
+      const int iy = rr.y0 + ((y - rr.y0) & (N - 1));  // the unwrapped row of y in y0 .. y0 + 127
+      if (iy - rr.y0 >= rr.ny) continue;
+      const int ix = rr.x0 + r;
+      float p[4];
+      if (!rs_point(rd, rr, ix, iy, en.dz, p)) continue;
+      float2* v = plane + y * N + ((ix & (N - 1)) ^ rs_swz(y));
+      float2 u = *v;
+      u.x += fmaf(p[0], c0.x, fmaf(p[1], c1.x, fmaf(p[2], c2.x, p[3] * c3.x)));
+      u.y += fmaf(p[0], c0.y, fmaf(p[1], c1.y, fmaf(p[2], c2.y, p[3] * c3.y)));
+      *v = u;
+    }
+  }
+}
+
 // ---- 128 x 128 FP32 planes with wave-local lines ---------------------------------------------
 // The same transform as k_plane_n (inverse along y on the active columns, inverse along x, * V,
 // forward along x, forward along y on the active columns), arranged so that the 8 threads of a
@@ -323,9 +426,13 @@ __device__ __forceinline__ void wave_sync() {
 }
 __device__ __forceinline__ int p128_col(int row, int xa) { return xa ^ ((((row >> 4) ^ row) & 1) << 3); }
 
+// NL: the real-space projectors' D P term is added to V psi between the x passes (rs_add_band;
+// the plane then holds each wave's rows in natural order for that step).
+template <bool NL>
 __global__ __launch_bounds__(1024) void k_plane128(float2* __restrict__ SB, const float* __restrict__ V,
                                                    const int* __restrict__ colstart, GridDesc g,
-                                                   const float2* __restrict__ twg, float scale) {
+                                                   const float2* __restrict__ twg, float scale, RsDesc rd,
+                                                   const float2* __restrict__ dp, int nproj) {
   using T = float;
   constexpr int N = 128, A = 8, B = 16, LPW = 8, NW = 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -434,6 +541,17 @@ __global__ __launch_bounds__(1024) void k_plane128(float2* __restrict__ SB, cons
     SmallDft<T, B, +1>::run(r2);  // r2[k2] = value at x = t + 8 k2
 #pragma unroll
     for (int k2 = 0; k2 < B; ++k2) r2[k2] = cscale<T>(r2[k2], vr[k2]);
+    if constexpr (NL) {
+      const int sw = rs_swz(y);
+      wave_sync();
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) row[(t + A * k2) ^ sw] = r2[k2];
+      wave_sync();
+      rs_add_band(plane, rd, z, wv, dp + (long)b * nproj, lane);
+      wave_sync();
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) r2[k2] = row[(t + A * k2) ^ sw];
+    }
     SmallDft<T, B, -1>::run(r2);  // over m2, output q2
 #pragma unroll
     for (int q2 = 1; q2 < B; ++q2) r2[q2] = cmul<T>(r2[q2], tw[(t * q2) % N]);
@@ -693,6 +811,162 @@ hipError_t launch_density128(const float2* SB, const int* colstart, const GridDe
   return hipGetLastError();
 }
 
+// Inverse x pass of row y (as in xinv_row_acc); the row then holds psi in natural x order.
+__device__ __forceinline__ void xinv_row_store(float2* plane, const float2* tw, int y, int t, int n1max) {
+  constexpr int N = 128, A = 8, B = 16;
+  const int sy = (((y >> 4) ^ y) & 1) << 3, py = (y & 1) << 3;
+  float2* row = plane + y * N;
+  float2 r1[2][A];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) {
+      const int x = B * n1 + t + 8 * i;
+      const int k = x < N / 2 ? x : x - N;
+      r1[i][n1] = (k <= n1max && -k <= n1max) ? row[(k + n1max) ^ sy] : make_float2(0.f, 0.f);
+    }
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int n2 = t + 8 * i;
+    SmallDft<float, A, +1>::run(r1[i]);
+#pragma unroll
+    for (int k1 = 1; k1 < A; ++k1) {
+      float2 w = tw[(n2 * k1) % N];
+      w.y = -w.y;
+      r1[i][k1] = cmul<float>(r1[i][k1], w);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) row[B * k1 + (n2 ^ k1 ^ py)] = r1[i][k1];
+  }
+  wave_sync();
+  float2 r2[B];
+#pragma unroll
+  for (int n2 = 0; n2 < B; ++n2) r2[n2] = row[B * t + (n2 ^ t ^ py)];
+  SmallDft<float, B, +1>::run(r2);  // r2[k2] = psi at x = t + 8 k2
+  wave_sync();
+  const int sw = rs_swz(y);
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) row[(t + A * k2) ^ sw] = r2[k2];
+}
+
+// Inverse pass with the projections: a workgroup takes plane z of band b, transforms it inside LDS
+// (inverse y on the active columns, inverse x on every row), then each wave takes entries of the
+// plane (one atom each), sums p_m(r - tau) psi(r) over the entry's points with its 64 lanes and
+// writes the four sums, reduced across the wave in a fixed order, to part[(b nent + e) 4 + m].
+__global__ __launch_bounds__(1024) void k_rs_proj128(const float2* __restrict__ SB, const int* __restrict__ colstart,
+                                                     GridDesc g, const float2* __restrict__ twg, RsDesc rd,
+                                                     float2* __restrict__ part) {
+  constexpr int N = 128, LPW = 8, NW = 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* plane = reinterpret_cast<float2*>(smem_raw);
+  float2* tw = plane + N * N;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l = lane >> 3, t = lane & 7;
+  const int z = blockIdx.x, b = blockIdx.y;
+  const int e0 = rd.zoff[z], e1 = rd.zoff[z + 1];
+  if (e0 == e1) return;  // no atom within reach of this plane (uniform over the workgroup)
+  const int n1a = g.n1a;
+  const int ngrp = (n1a + LPW - 1) / LPW;
+  for (int i = tid; i < N; i += 1024) tw[i] = twg[i];
+  const float2* sb = SB + ((long)b * g.n3 + z) * g.nst;
+  __syncthreads();
+  for (int cg = wv; cg < ngrp; cg += NW) {
+    float2 r[2][8];
+    p128::yinv_load(sb, colstart, n1a, cg, l, t, r);
+    p128::yinv_compute(plane, tw, n1a, cg, l, t, r);
+  }
+  __syncthreads();
+  xinv_row_store(plane, tw, wv * LPW + l, t, g.n1max);
+  __syncthreads();
+  float2* pb = part + (long)b * rd.nent * 4;
+  for (int e = e0 + wv; e < e1; e += NW) {
+    const RsEnt en = rd.zent[e];
+    const RsRange rr = rs_range(rd, en.atom, en.dz);
+    float acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+    const int np = rr.nx * rr.ny;
+    const float inv = rr.nx > 0 ? 1.0f / (float)rr.nx : 0.f;
+    for (int i = lane; i < np; i += 64) {
+      int q, r;
+      rs_divmod(i, rr.nx, inv, q, r);
+      const int ix = rr.x0 + r, iy = rr.y0 + q;
+      float p[4];
+      if (rs_point(rd, rr, ix, iy, en.dz, p)) {
+        const int y = iy & (N - 1);
+        const float2 v = plane[y * N + ((ix & (N - 1)) ^ rs_swz(y))];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          acc[2 * m] = fmaf(p[m], v.x, acc[2 * m]);
+          acc[2 * m + 1] = fmaf(p[m], v.y, acc[2 * m + 1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = rs_wave_sum(acc[k]);
+    if (lane == 0) {
+      float4* o = reinterpret_cast<float4*>(pb + (long)e * 4);
+      o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+    }
+  }
+}
+
+// dp[b nproj + 4a + m] = dscale[m] inv_nr sum over atom a's entries (plane order) of part, in FP64.
+__global__ void k_rs_reduce(const float2* __restrict__ part, RsDesc rd, int nbt, const double* __restrict__ dscale,
+                            double inv_nr, float2* __restrict__ dp, int nproj) {
+  PW_GRID_STRIDE(idx, (long)nbt * rd.natoms) {
+    const int j = (int)(idx / rd.natoms), a = (int)(idx - (long)j * rd.natoms);
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = rd.aoff[a]; k < rd.aoff[a + 1]; ++k) {
+      const float4* q = reinterpret_cast<const float4*>(part + ((long)j * rd.nent + rd.aent[k]) * 4);
+      const float4 u = q[0], v = q[1];
+      s[0] += u.x;
+      s[1] += u.y;
+      s[2] += u.z;
+      s[3] += u.w;
+      s[4] += v.x;
+      s[5] += v.y;
+      s[6] += v.z;
+      s[7] += v.w;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const double f = dscale[m] * inv_nr;
+      dp[(long)j * nproj + 4 * a + m] = make_float2((float)(s[2 * m] * f), (float)(s[2 * m + 1] * f));
+    }
+  }
+}
+
+hipError_t launch_rs_proj128(const float2* SB, const int* colstart, const GridDesc& g, const float2* tw,
+                             const RsDesc& rd, int nbatch, float2* part, hipStream_t s) {
+  if (nbatch <= 0 || rd.nent <= 0) return hipSuccess;
+  if (g.n1 != 128 || g.n2 != 128 || g.n1a > 128) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(128 * 128 + 128) * sizeof(float2);
+  hipLaunchKernelGGL(k_rs_proj128, dim3(g.n3, nbatch), dim3(1024), lds, s, SB, colstart, g, tw, rd, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_rs_reduce(const float2* part, const RsDesc& rd, int nbt, const double* dscale, double inv_nr,
+                            float2* dp, int nproj, hipStream_t s) {
+  if (nbt <= 0 || rd.natoms <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rs_reduce, dim3(stride_blocks((long)nbt * rd.natoms)), dim3(256), 0, s, part, rd, nbt, dscale,
+                     inv_nr, dp, nproj);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane128_nl(float2* SB, const float* V, int nbatch, const int* colstart, const GridDesc& g,
+                              const float2* tw, float scale, const RsDesc& rd, const float2* dp, int nproj,
+                              hipStream_t s) {
+  if (nbatch <= 0) return hipSuccess;
+  if (g.n1 != 128 || g.n2 != 128 || g.n1a > 128) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(128 * 128 + 128) * sizeof(float2);
+  hipLaunchKernelGGL(k_plane128<true>, dim3(g.n3, nbatch), dim3(1024), lds, s, SB, V, colstart, g, tw, scale, rd, dp,
+                     nproj);
+  return hipGetLastError();
+}
+
 // ---- z transforms of the sticks with compile-time N = A B ---------------------------------
 // gcd(A, B) threads share a stick; a block takes SPW sticks of one band (at most 256 threads and
 // 48 KB of LDS).  Stick element i (0 <= i < len, h = (len - 1) / 2) sits at z = i - h mod N.
@@ -948,7 +1222,8 @@ hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, 
   if constexpr (std::is_same<T, float>::value) {
     if (g.n1 == 128 && g.n2 == 128 && g.n1a <= 128) {
       const size_t lds = (size_t)(128 * 128 + 128) * sizeof(float2);
-      hipLaunchKernelGGL(k_plane128, dim3(g.n3, nbatch), dim3(1024), lds, s, SB, V, colstart, g, tw, scale);
+      hipLaunchKernelGGL(k_plane128<false>, dim3(g.n3, nbatch), dim3(1024), lds, s, SB, V, colstart, g, tw, scale,
+                         RsDesc{}, (const float2*)nullptr, 0);
       return hipGetLastError();
     }
   }
@@ -974,7 +1249,11 @@ void pw_allow_large_lds_plane_n() {
   PW_ALLOW(8, 12, 512)
   PW_ALLOW(8, 16, 1024)
 #undef PW_ALLOW
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_plane128), hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_plane128<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_plane128<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rs_proj128), hipFuncAttributeMaxDynamicSharedMemorySize,
                             bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_density128), hipFuncAttributeMaxDynamicSharedMemorySize,
                             bytes);

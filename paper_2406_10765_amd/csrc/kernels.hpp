@@ -46,6 +46,19 @@ template <typename T>
 hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, const int* colstart,
                           const GridDesc& g, const cplx<T>* tw, T scale, hipStream_t s);
 void pw_allow_large_lds_plane_n();
+// Real-space projectors on 128 x 128 FP32 planes (sticks in SB as for the plane pass).
+// Inverse pass: the projections of nbatch bands, one partial of 4 complex sums per band and
+// entry: part[(b nent + e) 4 + m].  SB is only read.
+hipError_t launch_rs_proj128(const float2* SB, const int* colstart, const GridDesc& g, const float2* tw,
+                             const RsDesc& rd, int nbatch, float2* part, hipStream_t s);
+// dp[b nproj + 4a + m] = dscale[m] inv_nr (sum over atom a's entries of part), b < nbt.
+hipError_t launch_rs_reduce(const float2* part, const RsDesc& rd, int nbt, const double* dscale, double inv_nr,
+                            float2* dp, int nproj, hipStream_t s);
+// The plane pass of k_plane128 with sum_a p_m(r - tau_a) dp[b nproj + 4a + m] added to V psi at the
+// atoms' points before the forward transforms.
+hipError_t launch_plane128_nl(float2* SB, const float* V, int nbatch, const int* colstart, const GridDesc& g,
+                              const float2* tw, float scale, const RsDesc& rd, const float2* dp, int nproj,
+                              hipStream_t s);
 // Fused charge density of nbt bands on 128 x 128 FP32 planes (sticks in SB as for the plane
 // pass): ngroups band groups per z plane, each group's FP64 sum of occ_b |psi_b|^2 in part
 // (ngroups x 128 x 128 x n3 doubles), then rho = (first ? 0 : rho) + the group sums in order;
@@ -228,11 +241,11 @@ hipError_t launch_vg_sphere(const int* miller, int npw, const double* frac, cons
 // beta[g, 4a+m] table (column-major, ld)
 template <typename T>
 hipError_t launch_beta_table(const int* miller, int npw, const double* frac, int natoms, const double* L,
-                             double sigma, cplx<T>* beta, long ld, hipStream_t s);
+                             double sigma, int form, cplx<T>* beta, long ld, hipStream_t s);
 // Projector table as bf16 hi/lo planes (one 32-bit (re, im) word per entry, column-major, leading
 // dimension ld; rows npw..ld-1 zero), for the split-precision projector GEMMs.
 hipError_t launch_beta_planes(const int* miller, int npw, const double* frac, int natoms, const double* L,
-                              double sigma, unsigned int* hi, unsigned int* lo, long ld, hipStream_t s);
+                              double sigma, int form, unsigned int* hi, unsigned int* lo, long ld, hipStream_t s);
 template <typename T>
 hipError_t launch_convert_c64_to(const double2* in, long ldi, cplx<T>* out, long ldo, int rows, int cols,
                                  hipStream_t s);

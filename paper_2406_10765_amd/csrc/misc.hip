@@ -3,6 +3,7 @@
 
 #include <cmath>
 
+#include "../../include/pw.h"
 #include "bf16split.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -76,8 +77,10 @@ __global__ void k_vg_sphere(const int* __restrict__ miller, int npw, const doubl
 
 // beta[g, 4a+m] = (c/sqrt(Omega)) e^{-sigma^2 |G|^2/2} Y_m(G) e^{-i G.tau_a},
 // c = sqrt(32 pi^{5/2} sigma^3); Y_0 = 1/(2 sqrt(pi)), Y_{1x,y,z} = sqrt(3/(4 pi)) G_{x,y,z}/|G| (0 at G=0).
+// form PW_PROJ_LOCALIZED: Y_{1m} = -i sigma G_m / sqrt(2 pi) (the transform of a Gaussian times r_m).
 __device__ __forceinline__ void beta_values(const int* __restrict__ miller, int g, const double* __restrict__ frac,
-                                            int a, double L0, double L1, double L2, double sigma, double2 out[4]) {
+                                            int a, double L0, double L1, double L2, double sigma, int form,
+                                            double2 out[4]) {
   const int n1 = miller[3 * g], n2 = miller[3 * g + 1], n3 = miller[3 * g + 2];
   const double gx = 2.0 * kPi * n1 / L0, gy = 2.0 * kPi * n2 / L1, gz = 2.0 * kPi * n3 / L2;
   const double g2 = gx * gx + gy * gy + gz * gz;
@@ -89,6 +92,17 @@ __device__ __forceinline__ void beta_values(const int* __restrict__ miller, int 
   const double gn = sqrt(g2);
   const double inv = gn > 0.0 ? c1 / gn : 0.0;
   const double2 e = expm2pi(n1 * frac[3 * a] + n2 * frac[3 * a + 1] + n3 * frac[3 * a + 2]);
+  if (form == PW_PROJ_LOCALIZED) {
+    const double c2 = sigma / sqrt(2.0 * kPi);
+    const double ym[4] = {y0, gx * c2, gy * c2, gz * c2};
+    out[0] = make_double2(radial * y0 * e.x, radial * y0 * e.y);
+#pragma unroll
+    for (int m = 1; m < 4; ++m) {
+      const double sc = radial * ym[m];
+      out[m] = make_double2(sc * e.y, -sc * e.x);  // -i (e.x + i e.y)
+    }
+    return;
+  }
   const double ym[4] = {y0, gx * inv, gy * inv, gz * inv};
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -99,12 +113,12 @@ __device__ __forceinline__ void beta_values(const int* __restrict__ miller, int 
 
 template <typename T>
 __global__ void k_beta_table(const int* __restrict__ miller, int npw, const double* __restrict__ frac, double L0,
-                             double L1, double L2, double sigma, cplx<T>* __restrict__ beta, long ld) {
+                             double L1, double L2, double sigma, int form, cplx<T>* __restrict__ beta, long ld) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
   if (g >= npw) return;
   double2 v[4];
-  beta_values(miller, g, frac, a, L0, L1, L2, sigma, v);
+  beta_values(miller, g, frac, a, L0, L1, L2, sigma, form, v);
 #pragma unroll
   for (int m = 0; m < 4; ++m) beta[(long)(4 * a + m) * ld + g] = mk<T>((T)v[m].x, (T)v[m].y);
 }
@@ -112,13 +126,13 @@ __global__ void k_beta_table(const int* __restrict__ miller, int npw, const doub
 // The fp32 table stored as two bf16 planes: word (re, im) of hi = bf16(x) and of lo = bf16(x - hi),
 // x the fp32 value; rows npw..ld-1 of every column are zero.
 __global__ void k_beta_planes(const int* __restrict__ miller, int npw, const double* __restrict__ frac, double L0,
-                              double L1, double L2, double sigma, unsigned int* __restrict__ hi,
+                              double L1, double L2, double sigma, int form, unsigned int* __restrict__ hi,
                               unsigned int* __restrict__ lo, long ld) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = blockIdx.y;
   if (g >= ld) return;
   double2 v[4] = {};
-  if (g < npw) beta_values(miller, g, frac, a, L0, L1, L2, sigma, v);
+  if (g < npw) beta_values(miller, g, frac, a, L0, L1, L2, sigma, form, v);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const Split2 re = split((float)v[m].x), im = split((float)v[m].y);
@@ -374,18 +388,18 @@ hipError_t launch_vg_sphere(const int* miller, int npw, const double* frac, cons
 
 template <typename T>
 hipError_t launch_beta_table(const int* miller, int npw, const double* frac, int natoms, const double* L,
-                             double sigma, cplx<T>* beta, long ld, hipStream_t s) {
+                             double sigma, int form, cplx<T>* beta, long ld, hipStream_t s) {
   if (natoms <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_beta_table<T>, dim3(ceil_div(npw, 256), natoms), dim3(256), 0, s, miller, npw, frac, L[0], L[1],
-                     L[2], sigma, beta, ld);
+                     L[2], sigma, form, beta, ld);
   return hipGetLastError();
 }
 
 hipError_t launch_beta_planes(const int* miller, int npw, const double* frac, int natoms, const double* L,
-                              double sigma, unsigned int* hi, unsigned int* lo, long ld, hipStream_t s) {
+                              double sigma, int form, unsigned int* hi, unsigned int* lo, long ld, hipStream_t s) {
   if (natoms <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_beta_planes, dim3(ceil_div(ld, 256), natoms), dim3(256), 0, s, miller, npw, frac, L[0], L[1],
-                     L[2], sigma, hi, lo, ld);
+                     L[2], sigma, form, hi, lo, ld);
   return hipGetLastError();
 }
 
@@ -545,8 +559,8 @@ hipError_t launch_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, 
 
 #define PW_INST_MISC(T)                                                                                         \
   template hipError_t launch_fill_zero<T>(cplx<T>*, long, hipStream_t);                                         \
-  template hipError_t launch_beta_table<T>(const int*, int, const double*, int, const double*, double, cplx<T>*, \
-                                           long, hipStream_t);                                                  \
+  template hipError_t launch_beta_table<T>(const int*, int, const double*, int, const double*, double, int,      \
+                                           cplx<T>*, long, hipStream_t);                                        \
   template hipError_t launch_convert_c64_to<T>(const double2*, long, cplx<T>*, long, int, int, hipStream_t);    \
   template hipError_t launch_copy_cols<T>(const cplx<T>*, long, cplx<T>*, long, int, int, hipStream_t);         \
   template hipError_t launch_lanczos_step<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, double, int, double*, \

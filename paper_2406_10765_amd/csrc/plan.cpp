@@ -44,6 +44,79 @@ static int smallest_23_at_least(int need) {
 
 static size_t align_up(size_t x) { return (x + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
 
+// Tables of the real-space projectors.  Atom a (position wrapped into the cell) reaches the planes
+// iz = ceil((z_a - R) / h_z) .. floor((z_a + R) / h_z) (unwrapped; plane iz mod n3), and within
+// plane iz the rows of the disc of radius sqrt(R^2 - dz^2), dz = iz h_z - z_a.  The host lists use
+// a radius enlarged by a relative 1e-4 so that they hold every (atom, plane) and (atom, band) pair
+// the kernels' FP32 ranges can reach; the kernels themselves decide which points lie in the ball.
+static void build_rspace_tables(Plan& P) {
+  const GridDesc& g = P.g;
+  const int n3 = g.n3, nbands_rows = 16;  // 128 rows in bands of 8
+  const double h[3] = {P.L[0] / g.n1, P.L[1] / g.n2, P.L[2] / g.n3};
+  const double R = P.rs_radius, Rs = R * (1.0 + 1e-4);
+  P.rs_atoms.assign(4 * (size_t)P.natoms, 0.f);
+  std::vector<std::vector<RsEnt>> per_z(n3), per_band((size_t)n3 * nbands_rows);
+  std::vector<std::vector<int>> atom_planes(P.natoms);  // plane of each of the atom's entries, in order
+  for (int a = 0; a < P.natoms; ++a) {
+    double t[3];
+    for (int i = 0; i < 3; ++i) {
+      double v = std::fmod(P.tau[3 * a + i], P.L[i]);
+      if (v < 0) v += P.L[i];
+      t[i] = v;
+      P.rs_atoms[4 * a + i] = (float)v;
+    }
+    const int z0 = (int)std::ceil((t[2] - Rs) / h[2]), z1 = (int)std::floor((t[2] + Rs) / h[2]);
+    for (int iz = z0; iz <= z1; ++iz) {
+      const int z = ((iz % n3) + n3) % n3;
+      const float dz = (float)(iz * h[2] - t[2]);
+      per_z[z].push_back(RsEnt{a, dz});
+      atom_planes[a].push_back(z);
+      const double rho2 = Rs * Rs - (double)dz * dz;
+      if (rho2 < 0) continue;
+      const double rho = std::sqrt(rho2);
+      const int y0 = (int)std::ceil((t[1] - rho) / h[1]), y1 = (int)std::floor((t[1] + rho) / h[1]);
+      std::vector<char> hit(nbands_rows, 0);
+      for (int iy = y0; iy <= y1; ++iy) hit[(((iy % 128) + 128) % 128) / 8] = 1;
+      for (int w = 0; w < nbands_rows; ++w)
+        if (hit[w]) per_band[(size_t)z * nbands_rows + w].push_back(RsEnt{a, dz});
+    }
+  }
+  P.rs_zoff.assign(n3 + 1, 0);
+  P.rs_zent.clear();
+  std::vector<std::vector<int>> slot(P.natoms);  // zent index of each of the atom's entries
+  for (int z = 0; z < n3; ++z) {
+    P.rs_zoff[z] = (int)P.rs_zent.size();
+    for (const RsEnt& e : per_z[z]) {
+      slot[e.atom].push_back((int)P.rs_zent.size());
+      P.rs_zent.push_back(e);
+    }
+  }
+  P.rs_zoff[n3] = (int)P.rs_zent.size();
+  // each atom's entries in the order of its planes iz (ascending unwrapped z)
+  P.rs_aoff.assign(P.natoms + 1, 0);
+  P.rs_aent.clear();
+  for (int a = 0; a < P.natoms; ++a) {
+    P.rs_aoff[a] = (int)P.rs_aent.size();
+    std::vector<int> zs = atom_planes[a];
+    std::vector<int> sl = slot[a];  // in increasing wrapped z, one per plane (planes are distinct)
+    std::vector<int> by_plane(n3, -1);
+    {
+      std::vector<int> sorted_z = zs;
+      std::sort(sorted_z.begin(), sorted_z.end());
+      for (size_t k = 0; k < sorted_z.size(); ++k) by_plane[sorted_z[k]] = sl[k];
+    }
+    for (int z : zs) P.rs_aent.push_back(by_plane[z]);
+  }
+  P.rs_aoff[P.natoms] = (int)P.rs_aent.size();
+  P.rs_boff.assign((size_t)n3 * nbands_rows + 1, 0);
+  P.rs_bent.clear();
+  for (size_t k = 0; k < per_band.size(); ++k) {
+    P.rs_boff[k] = (int)P.rs_bent.size();
+    for (const RsEnt& e : per_band[k]) P.rs_bent.push_back(e);
+  }
+  P.rs_boff[per_band.size()] = (int)P.rs_bent.size();
+}
+
 pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string* err) {
   if (!d) { *err = "null description"; return PW_EINVAL; }
   for (int i = 0; i < 3; ++i)
@@ -52,8 +125,8 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   if (d->natoms < 0 || (d->natoms > 0 && !d->tau)) { *err = "bad atoms"; return PW_EINVAL; }
   if (d->nbands < 1) { *err = "nbands must be >= 1"; return PW_EINVAL; }
   if (d->prec != PW_FP64 && d->prec != PW_MIXED) { *err = "unknown precision"; return PW_EINVAL; }
-  const unsigned known =
-      PW_FLAG_PENCIL_FFT | PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT | PW_FLAG_BETA_OTF | PW_FLAG_LOBPCG;
+  const unsigned known = PW_FLAG_PENCIL_FFT | PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT |
+                         PW_FLAG_BETA_OTF | PW_FLAG_LOBPCG | PW_FLAG_RSPACE_KB;
   if (d->flags & ~known) { *err = "unknown flag bits"; return PW_EINVAL; }
   if ((d->flags & PW_FLAG_BETA_OTF) && (d->flags & PW_FLAG_BF16_KB)) {
     *err = "PW_FLAG_BETA_OTF cannot be combined with PW_FLAG_BF16_KB";
@@ -79,6 +152,36 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   }
   const bool have_proj = (d->d0 != 0.0 || d->d1 != 0.0) && d->natoms > 0;
   if (have_proj && !(d->beta_sigma > 0.0)) { *err = "beta_sigma must be positive"; return PW_EINVAL; }
+  if (d->proj_form != PW_PROJ_GSPACE && d->proj_form != PW_PROJ_LOCALIZED) {
+    *err = "unknown projector form";
+    return PW_EINVAL;
+  }
+  if (d->proj_form == PW_PROJ_LOCALIZED && (d->flags & PW_FLAG_BETA_OTF)) {
+    *err = "PW_FLAG_BETA_OTF generates the PW_PROJ_GSPACE projectors only";
+    return PW_EINVAL;
+  }
+  const bool rspace = (d->flags & PW_FLAG_RSPACE_KB) != 0;
+  if (rspace) {
+    if (d->proj_form != PW_PROJ_LOCALIZED) {
+      *err = "PW_FLAG_RSPACE_KB needs proj_form = PW_PROJ_LOCALIZED";
+      return PW_EINVAL;
+    }
+    if (d->prec != PW_MIXED) { *err = "PW_FLAG_RSPACE_KB needs PW_MIXED"; return PW_EINVAL; }
+    if (d->flags & (PW_FLAG_BF16_KB | PW_FLAG_BETA_OTF | PW_FLAG_PENCIL_FFT)) {
+      *err = "PW_FLAG_RSPACE_KB cannot be combined with PW_FLAG_BF16_KB, PW_FLAG_BETA_OTF or PW_FLAG_PENCIL_FFT";
+      return PW_EINVAL;
+    }
+    if (!have_proj) { *err = "PW_FLAG_RSPACE_KB needs projectors (atoms and d0 or d1 nonzero)"; return PW_EINVAL; }
+    if (!(d->rs_radius > 0.0) || !std::isfinite(d->rs_radius)) {
+      *err = "PW_FLAG_RSPACE_KB needs rs_radius > 0";
+      return PW_EINVAL;
+    }
+    for (int i = 0; i < 3; ++i)
+      if (!(2.0 * d->rs_radius * (1.0 + 1e-4) < d->L[i])) {
+        *err = "rs_radius must stay below half of every cell length";
+        return PW_EINVAL;
+      }
+  }
   if (d->natoms > 0 && d->zval != 0.0 && !(d->rc > 0.0)) { *err = "rc must be positive"; return PW_EINVAL; }
 
   Plan& P = *p;
@@ -106,6 +209,9 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   P.mode_phase.assign(d->mode_phase ? d->mode_phase : nullptr, d->mode_phase ? d->mode_phase + d->nmodes : nullptr);
   P.prec = d->prec;
   P.flags = d->flags;
+  P.proj_form = d->proj_form;
+  P.rspace = rspace;
+  P.rs_radius = rspace ? d->rs_radius : 0.0;
   P.real_bytes = d->prec == PW_FP64 ? 8 : 4;
 
   // --- sphere in stick order: n1, then n2, then n3 ascending -------------------
@@ -186,6 +292,13 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   if (!fft_plan_launch(g, P.real_bytes, (d->flags & PW_FLAG_PENCIL_FFT) ? 0 : max_lds, &P.fl)) {
     *err = "no FFT launch shape fits this grid";
     return PW_EINVAL;
+  }
+  if (P.rspace) {
+    if (!P.fl.sized || g.n1 != 128 || g.n2 != 128 || g.n1a > 128) {
+      *err = "PW_FLAG_RSPACE_KB needs a 128 x 128 x n3 grid whose planes fit in LDS";
+      return PW_EINVAL;
+    }
+    build_rspace_tables(P);
   }
 
   // --- filter blocking -------------------------------------------------------------
@@ -276,7 +389,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   for (int gi = 0; gi < P.npw; ++gi)
     for (int i = 0; i < 3; ++i) P.hmax[i] = std::max(P.hmax[i], std::abs(P.miller[3 * gi + i]));
   P.bwidth = (2 * P.hmax[0] + 1) + (2 * P.hmax[1] + 1) + (2 * P.hmax[2] + 1);
-  L.beta = take(otf ? 0 : cb * P.ldw * P.nproj);
+  L.beta = take(otf || P.rspace ? 0 : cb * P.ldw * P.nproj);
   L.brad = take(otf ? sizeof(double) * 4 * P.npw : 0);
   L.bph = take(otf ? 16 * (size_t)P.natoms * P.bwidth : 0);
   const bool blocked = P.nbb < P.nbands;
@@ -304,6 +417,15 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   L.occ = take(sizeof(double) * nb);  // band weights of the charge density
   // LOBPCG basis Z = [X R P] and HZ = [HX HR HP] (3 nbands columns each)
   L.lz = take(lob ? 2 * cb * P.ldw * 3 * nb : 0);
+  const size_t nent = P.rs_zent.size();
+  L.rsat = take(sizeof(float) * P.rs_atoms.size());
+  L.rszo = take(sizeof(int) * P.rs_zoff.size());
+  L.rsze = take(sizeof(RsEnt) * nent);
+  L.rsbo = take(sizeof(int) * P.rs_boff.size());
+  L.rsbe = take(sizeof(RsEnt) * P.rs_bent.size());
+  L.rsao = take(sizeof(int) * P.rs_aoff.size());
+  L.rsae = take(sizeof(int) * P.rs_aent.size());
+  L.rsp = take(32 * nent * (size_t)(P.rspace ? P.fft_batch : 0));  // 4 complex FP32 per band and entry
   L.total = off;
   return PW_OK;
 }

@@ -17,6 +17,7 @@ struct ArenaLayout {
   size_t miller, sticks, colstart, kin, tw1, tw2, tw3, vr, frac, mmil, mamp, mpha, vg, dscale;
   size_t beta, brad, bph, yp, u0, u1, zb, wf, sb, g1, pt, parts, sh, ct, ct2, eig, ework, resid, info, scal, lanc,
       occ, lz;
+  size_t rsat, rszo, rsze, rsbo, rsbe, rsao, rsae, rsp;  // real-space projector tables and partials
   size_t total;
 };
 
@@ -54,6 +55,14 @@ struct Plan {
   int yp_cols;
   int hmax[3];                 // max |n_d| over the sphere (projector generator tables)
   int bwidth;                  // per-atom axis-factor table length
+  int proj_form;               // PW_PROJ_GSPACE or PW_PROJ_LOCALIZED
+  // real-space projectors (PW_FLAG_RSPACE_KB): per-atom positions, the (atom, plane) entries
+  // per plane and per (plane, 8-row band), and each atom's entries; see RsDesc
+  bool rspace;
+  double rs_radius;
+  std::vector<float> rs_atoms;  // 4 per atom
+  std::vector<int> rs_zoff, rs_boff, rs_aoff, rs_aent;
+  std::vector<RsEnt> rs_zent, rs_bent;
   ArenaLayout lay;
 };
 

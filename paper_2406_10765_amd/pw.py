@@ -48,6 +48,8 @@ class CellDesc(ctypes.Structure):
         ("prec", ctypes.c_int),
         ("flags", ctypes.c_uint),
         ("filter_block", ctypes.c_int),
+        ("proj_form", ctypes.c_int),
+        ("rs_radius", ctypes.c_double),
     ]
 
 
@@ -186,13 +188,16 @@ PW_FLAG_BF16_ROT = 8
 PW_FLAG_BF16_ALL = PW_FLAG_BF16_GRAM | PW_FLAG_BF16_KB | PW_FLAG_BF16_ROT
 PW_FLAG_BETA_OTF = 16
 PW_FLAG_LOBPCG = 32
+PW_FLAG_RSPACE_KB = 64
+PW_PROJ_GSPACE, PW_PROJ_LOCALIZED = 0, 1
 # fraction of the largest scaled Gram eigenvalue below which basis directions are dropped
 PW_DROP_TOL_FP64 = 1e-10
 PW_DROP_TOL_MIXED = 1e-5
 
 
 def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,
-              fft_n: Sequence[int] = (0, 0, 0), flags: int = 0, filter_block: int = 0):
+              fft_n: Sequence[int] = (0, 0, 0), flags: int = 0, filter_block: int = 0,
+              proj_form: int = PW_PROJ_GSPACE, rs_radius: float = 0.0):
     """CellDesc from a synth.Cell; returns (desc, keepalive)."""
     p = cell.pseudo
     tau = np.ascontiguousarray(np.asarray(cell.tau, np.float64).reshape(-1))
@@ -215,12 +220,14 @@ def make_desc(cell, prec: int = PW_FP64, nbands: Optional[int] = None,
     d.prec = int(prec)
     d.flags = int(flags)
     d.filter_block = int(filter_block)
+    d.proj_form = int(proj_form)
+    d.rs_radius = float(rs_radius)
     return d, (tau, mm, ma, mp)
 
 
 def plan(cell, prec: int = PW_FP64, nbands: Optional[int] = None, fft_n=(0, 0, 0), flags: int = 0,
-         filter_block: int = 0) -> Info:
-    d, keep = make_desc(cell, prec, nbands, fft_n, flags, filter_block)
+         filter_block: int = 0, proj_form: int = PW_PROJ_GSPACE, rs_radius: float = 0.0) -> Info:
+    d, keep = make_desc(cell, prec, nbands, fft_n, flags, filter_block, proj_form, rs_radius)
     info = Info()
     _check(lib().pw_plan(ctypes.byref(d), ctypes.byref(info)))
     return info
@@ -238,13 +245,14 @@ class Handle:
     """A set-up cell on the current torch CUDA device and stream."""
 
     def __init__(self, cell, prec: int = PW_FP64, nbands: Optional[int] = None, fft_n=(0, 0, 0),
-                 device=None, stream=None, flags: int = 0, filter_block: int = 0):
+                 device=None, stream=None, flags: int = 0, filter_block: int = 0,
+                 proj_form: int = PW_PROJ_GSPACE, rs_radius: float = 0.0):
         import torch
 
         self._torch = torch
         self.prec = prec
         self.dtype = torch.complex128 if prec == PW_FP64 else torch.complex64
-        d, self._keep = make_desc(cell, prec, nbands, fft_n, flags, filter_block)
+        d, self._keep = make_desc(cell, prec, nbands, fft_n, flags, filter_block, proj_form, rs_radius)
         self.info = Info()
         _check(lib().pw_plan(ctypes.byref(d), ctypes.byref(self.info)))
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
