@@ -346,6 +346,56 @@ def peak_in_flight(intervals):
     return peak
 
 
+def rspace_leg(pw, synth, torch, cell, m, steps):
+    """The localized projector family on the bench cell, filtered with the reciprocal-space projector
+    GEMMs (bf16 planes, the headline's flags) and with the real-space projectors (PW_FLAG_RSPACE_KB;
+    the other products as in the headline), from the same block and bounds: ms per step, per-phase
+    times, and the occupied eigenvalues of the first degree-m step of each.  Radius 5.5 sigma: the
+    truncation then changes H X by less than FP32 rounding does (4.7e-8 relative on Si64)."""
+    nb = cell.nbands
+    R = 5.5 * cell.pseudo.beta_sigma
+    seed = synth.SEED_X0 + 17
+    out = {"radius_bohr": R, "projectors": "PW_PROJ_LOCALIZED",
+           "what": "degree-%d filter steps, the same cell with the localized projectors applied by the "
+                   "reciprocal-space GEMMs and in real space" % m}
+    eigs = {}
+    b = bounds = None
+    routes = (("gspace", DEFAULT_MIXED_FLAGS, 0.0),
+              ("rspace", (DEFAULT_MIXED_FLAGS & ~pw.PW_FLAG_BF16_KB) | pw.PW_FLAG_RSPACE_KB, R))
+    for name, flags, rad in routes:
+        h = pw.Handle(cell, pw.PW_MIXED, flags=flags, proj_form=pw.PW_PROJ_LOCALIZED, rs_radius=rad)
+        if b is None:
+            b = h.spectrum_bound(20, 1)
+        X = h.random_block(nb, seed)
+        _, _, bnd = h.eig_step(X, 0, b=b)
+        if bounds is None:
+            bounds = (bnd[0], bnd[1])
+        e1, _, _ = h.eig_step(X, m, bounds[0], bounds[1], b)
+        eigs[name] = e1
+        run_steps(h, X, m, 1, bounds, b)
+        torch.cuda.synchronize()
+        ts = []
+        t0 = time.perf_counter()
+        run_steps(h, X, m, steps, bounds, b, times=ts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h.reset_stats()
+        h.set_timing(True)
+        run_steps(h, X, m, 1, bounds, b)
+        st = h.stats()
+        h.set_timing(False)
+        out[name] = {"ms_per_step": round(1000.0 * dt / steps, 2), "flags": flags,
+                     "footprint_gb": round(h.info.footprint_bytes / 1e9, 2),
+                     "phases_ms_per_step": {k: round(v["ms"], 3) for k, v in st.items() if v["launches"]},
+                     "phases_launches_per_step": {k: v["launches"] for k, v in st.items() if v["launches"]}}
+        log(f"{name} (localized projectors): {out[name]['ms_per_step']:.1f} ms/step")
+        del h, X
+        torch.cuda.empty_cache()
+    out["max_abs_deig_occ_Ha"] = float(np.abs(eigs["gspace"][: cell.nocc] - eigs["rspace"][: cell.nocc]).max())
+    out["speedup"] = round(out["gspace"]["ms_per_step"] / out["rspace"]["ms_per_step"], 3)
+    return out
+
+
 def serving_leg(n, rate, slots, flags, degree):
     """Poisson stream of eigen-solves (mixed precision) through the request loop."""
     import threading
@@ -417,6 +467,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-lobpcg", action="store_true", help="skip the LOBPCG step timing")
+    ap.add_argument("--no-rspace", action="store_true", help="skip the real-space projector comparison")
     ap.add_argument("--flags", type=int, default=None,
                     help="mixed-precision product flags (bit 2: bf16 Gram, 4: bf16 projectors, 8: bf16 rotation)")
     ap.add_argument("--serving-requests", type=int, default=200,
@@ -615,6 +666,17 @@ def main():
             lobpcg = {"error": str(exc)}
             log(f"lobpcg/ppcg measurement failed: {exc}")
 
+    # ---- real-space projectors (localized family): reciprocal-space GEMMs vs real space ------
+    rspace = None
+    if not big and not args.no_rspace and pw.plan(cell, pw.PW_MIXED).fft_n[0] == 128:
+        try:
+            rspace = rspace_leg(pw, synth, torch, cell, m, args.steps)
+            log(f"rspace: {rspace['rspace']['ms_per_step']:.1f} vs gspace {rspace['gspace']['ms_per_step']:.1f} "
+                f"ms/step, one-step |de| {rspace['max_abs_deig_occ_Ha']:.2e} Ha")
+        except Exception as exc:  # a failed side measurement must not lose the headline line
+            rspace = {"error": str(exc)}
+            log(f"rspace measurement failed: {exc}")
+
     # ---- FP64 form from the same block and bounds -----------------------------------------
     fp64 = None
     accuracy = None
@@ -733,7 +795,7 @@ def main():
         "band_apps_per_sec": band_apps,
         "apply_h_band_apps_per_sec": apply_rate,
         "density": density,
-        "lobpcg": lobpcg, "ppcg": ppcg,
+        "lobpcg": lobpcg, "ppcg": ppcg, "rspace_projectors": rspace,
         "device": device_info(torch, minfo),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -82,10 +82,12 @@ typedef enum {
    plane), and D P is added back at the same points inside the plane pass of V(r), before the
    forward transforms: O(N_atoms N_b) work per grid plane instead of the O(N_pw N_atoms N_b)
    projector GEMMs.  Needs proj_form = PW_PROJ_LOCALIZED, PW_MIXED, a 128 x 128 (x n3) grid whose
-   planes fit in LDS, and 0 < rs_radius with 2 rs_radius < every cell length; not combinable with
-   PW_FLAG_BF16_KB or PW_FLAG_BETA_OTF (PW_EINVAL otherwise).  Phase timers: the inverse pass with
-   the projections counts as PW_PH_PROJ, their sum over planes as PW_PH_PROJ_REDUCE, the plane
-   pass with V(r) and D P as PW_PH_PLANE, the kinetic + Chebyshev update as PW_PH_NL. */
+   planes fit in LDS, and 0 < rs_radius with 2 rs_radius (1 + 1e-4) < every cell length; not combinable with
+   PW_FLAG_BF16_KB, PW_FLAG_BETA_OTF or PW_FLAG_PENCIL_FFT (PW_EINVAL otherwise); handles with it
+   are refused by pw_apply_h_noalloc.  Phase timers: the inverse pass with the projections counts
+   as PW_PH_PROJ, their sum over planes as PW_PH_PROJ_REDUCE, the plane pass with V(r) and D P as
+   PW_PH_PLANE, and the forward stick pass, which also applies the kinetic term and the Chebyshev
+   update, as PW_PH_STICKS_FWD. */
 #define PW_FLAG_RSPACE_KB 64u
 
 /* Projector families (pw_cell_desc.proj_form). */

@@ -46,10 +46,13 @@ struct Stick {
   int n2;
 };
 
-// Real-space projectors: one (atom, z plane) pair, the plane's z displacement from the atom (bohr).
+// Real-space projectors: one (atom, z plane) pair, or (atom, z plane, 8-row band) triple: the plane's
+// z displacement from the atom (bohr), and unwrapped grid ranges that hold every point of the disc
+// the ball cuts from the plane: columns x0 .. x0+nx-1, rows y0 .. y0+ny-1.
 struct RsEnt {
   int atom;
   float dz;
+  short x0, nx, y0, ny;
 };
 
 // Tables of the real-space projectors on a 128 x 128 x n3 grid (PW_FLAG_RSPACE_KB).
@@ -61,12 +64,22 @@ struct RsDesc {
   const RsEnt* bent;
   const int* aoff;      // the zent indices of atom a, in plane order: aent[aoff[a] .. aoff[a + 1])
   const int* aent;
-  int nent, natoms;
+  int nent, natoms;     // nent: zent entries
   float hx, hy;         // grid steps along x and y (bohr)
-  float ihx, ihy;       // their inverses
   float r2;             // truncation radius squared (bohr^2)
   float inv2s2;         // 1 / (2 sigma^2)
   float c0, c1;         // sqrt(Omega) times the unit-norm prefactors of p_0 and p_m
+};
+
+// Chebyshev update fused into the forward stick pass: out = alpha ((kin - c) Y + z) - beta Yp, z the
+// transform written at a sphere position (Yp may be null).
+struct StickUpd {
+  const float* kin;
+  const float2* Y;
+  long ldy;
+  const float2* Yp;
+  long ldp;
+  float alpha, c, beta;
 };
 
 // Radix plan of one 1D FFT length (radices in order of application).

@@ -251,8 +251,6 @@ struct Engine {
     d.natoms = P.natoms;
     d.hx = (float)(P.L[0] / P.g.n1);
     d.hy = (float)(P.L[1] / P.g.n2);
-    d.ihx = (float)(P.g.n1 / P.L[0]);
-    d.ihy = (float)(P.g.n2 / P.L[1]);
     d.r2 = (float)(P.rs_radius * P.rs_radius);
     d.inv2s2 = (float)(0.5 / (P.beta_sigma * P.beta_sigma));
     const double so = std::sqrt(P.L[0] * P.L[1] * P.L[2]);
@@ -375,11 +373,13 @@ struct Engine {
     return PW_OK;
   }
 
-  // Local part and real-space projectors (PW_FLAG_RSPACE_KB), per FFT batch: sticks, then the
-  // inverse plane pass with the projections (SB only read), their sum over planes into D P (the
-  // batch's columns of PT), then the plane pass adding D P at the atoms' points to V psi before the
-  // forward transforms, then the forward sticks.  Zl receives V psi + V_NL psi on the sphere.
-  pw_status local_part_rs(const cplx<T>* Y, long ldy, cplx<T>* Z, long ldz, int nb, hipStream_t sm) {
+  // The whole H application with real-space projectors (PW_FLAG_RSPACE_KB), per FFT batch: sticks,
+  // then the inverse plane pass with the projections (SB only read), their sum over planes into
+  // D P (the batch's columns of PT), then the plane pass adding D P at the atoms' points to V psi
+  // before the forward transforms, then the forward sticks, which apply the Chebyshev update
+  // out = alpha ((kin - c) Y + V psi + V_NL psi) - beta Yp as they write the sphere.
+  pw_status local_part_rs(const cplx<T>* Y, long ldy, cplx<T>* out, long ldo, int nb, double alpha, double c,
+                          double beta_c, const cplx<T>* Yp, long ldp, hipStream_t sm) {
     if constexpr (std::is_same<T, float>::value) {
       const GridDesc& g = P.g;
       const float scale = (float)(1.0 / ((double)g.n1 * g.n2 * g.n3));
@@ -404,8 +404,17 @@ struct Engine {
                     launch_rs_reduce(part, rd, nbt, dsc, inv_nr, PT + (long)b0 * P.nproj, P.nproj, sm));
         PW_TIMED_ON(PW_PH_PLANE, sm,
                     launch_plane128_nl(SB, V, nbt, cs, g, tw1, scale, rd, PT + (long)b0 * P.nproj, P.nproj, sm));
+        StickUpd u;
+        u.kin = h->at<float>(P.lay.kin);
+        u.Y = Y + (long)b0 * ldy;
+        u.ldy = ldy;
+        u.Yp = Yp ? Yp + (long)b0 * ldp : nullptr;
+        u.ldp = ldp;
+        u.alpha = (float)alpha;
+        u.c = (float)c;
+        u.beta = (float)beta_c;
         PW_TIMED_ON(PW_PH_STICKS_FWD, sm,
-                    launch_sticks_fwd<T>(SB, Z + (long)b0 * ldz, ldz, nbt, st, g, tw3, P.fl, sm));
+                    launch_sticks_fwd_upd(SB, out + (long)b0 * ldo, ldo, nbt, st, g, tw3, u, sm));
       }
       return PW_OK;
     } else {
@@ -428,8 +437,9 @@ struct Engine {
     // Small blocks (serving-size cells) gain nothing from it and would only add streams.
     const bool overlap = !P.rspace && !h->timing && (double)P.npw * nb >= (double)(1 << 26);
     if (P.rspace) {
-      pw_status s = local_part_rs(Y, ldy, Zl, ldz, nb, h->stream);
-      if (s != PW_OK) return s;
+      // the forward sticks write the updated block: nothing else to do
+      set_planes(nullptr, 0);
+      return local_part_rs(Y, ldy, out, ldo, nb, alpha, c, beta_c, Yp, ldp, h->stream);
     }
     if (overlap) {
       PW_HIP(hipEventRecord(h->ev_fork, h->stream));
@@ -507,8 +517,7 @@ struct Engine {
       PW_TIMED(PW_PH_NL, launch_gemm_nn_beta<T>(beta_gen(), PT, P.nproj, nb, out, ldo, e, h->stream));
       return PW_OK;
     }
-    // real-space projectors: V_NL Y is already in Zl, the product only applies the epilogue (K = 0)
-    PW_TIMED(PW_PH_NL, nn(false, beta(), P.ldw, PT, P.nproj, P.npw, nb, P.rspace ? 0 : P.nproj, out, ldo, e));
+    PW_TIMED(PW_PH_NL, nn(false, beta(), P.ldw, PT, P.nproj, P.npw, nb, P.nproj, out, ldo, e));
     return PW_OK;
   }
 

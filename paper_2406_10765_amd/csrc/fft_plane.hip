@@ -305,66 +305,100 @@ __global__ __launch_bounds__(NT) void k_plane_n(cplx<T>* __restrict__ SB, const 
 
 // ---- real-space projectors on 128 x 128 FP32 planes --------------------------------------------
 // The projectors are truncated to the grid points within a radius R of their atom (Section III-A:
-// a projector acts only near its atom).  Entry (atom, plane) covers the rows y0 .. y0+ny-1 and
-// columns x0 .. x0+nx-1 (unwrapped grid indices) of the disc of radius sqrt(R^2 - dz^2); a point
-// belongs to the ball when its distance squared, computed by rs_point, is <= R^2.  Both passes
-// enumerate points through rs_range and rs_point, so they see the same points and the same values.
-// In the projector passes the plane holds row y in natural x order at word x ^ rs_swz(y).
+// a projector acts only near its atom).  An entry (atom, plane) holds unwrapped ranges of columns
+// x0 .. x0+nx-1 and rows y0 .. y0+ny-1 (mod 128 on the plane) that contain every point of the disc
+// the ball cuts from the plane; a point lies in the ball when dx^2 + (dy^2 + dz^2) <= R^2.  The
+// Gaussian factors as e^{-dx^2/(2 s^2)} e^{-(dy^2 + dz^2)/(2 s^2)}.  Both passes evaluate points
+// through rs_colpart / rs_row / rs_in, so they see the same points and the same values.
+//  * The projection pass holds the plane in LDS (row y in natural x order at word x ^ rs_swz(y)) and
+//    gives each wave whole (atom, plane) entries: its lanes cover the disc, 16, 32 or 64 columns
+//    at a time, and one reduction across the wave ends each entry.
+//  * The pass of V(r) adds D P on the x pass itself, where lane (l, t) of wave w holds the 16 values
+//    of row y = 8w + l at x = t + 8k in registers: the wave walks the entries of its 8-row band and
+//    visits only the 8-column blocks that an entry's columns meet (a wave-uniform mask).
 __device__ __forceinline__ int rs_swz(int y) { return (y & 15) << 3; }
 
-struct RsRange {
-  int x0, nx, y0, ny;
-  float tx, ty, dz2;
+// value of lane k of v (k uniform over the wave)
+__device__ __forceinline__ float rs_lane(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ int rs_lane(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+
+// One entry's data, loaded by lane k of the wave, then read by the whole wave with rs_entry.
+struct RsLaneEnt {
+  float tx, ty, dz;
+  int xr, yr;  // x0 | nx << 16 and y0 | ny << 16 (x0, y0 as 16-bit two's complement)
 };
-
-__device__ __forceinline__ RsRange rs_range(const RsDesc& d, int atom, float dz) {
-  const float4 t = d.atoms[atom];
-  RsRange r;
-  r.tx = t.x;
-  r.ty = t.y;
-  r.dz2 = dz * dz;
-  const float rho2 = d.r2 - r.dz2;
-  if (!(rho2 >= 0.f)) {
-    r.x0 = r.y0 = 0;
-    r.nx = r.ny = 0;
-    return r;
-  }
-  const float rho = sqrtf(rho2);
-  r.x0 = (int)ceilf((t.x - rho) * d.ihx);
-  r.nx = (int)floorf((t.x + rho) * d.ihx) - r.x0 + 1;
-  r.y0 = (int)ceilf((t.y - rho) * d.ihy);
-  r.ny = (int)floorf((t.y + rho) * d.ihy) - r.y0 + 1;
-  if (r.nx < 0) r.nx = 0;
-  if (r.ny < 0) r.ny = 0;
-  return r;
+__device__ __forceinline__ RsLaneEnt rs_load(const RsDesc& d, const RsEnt& en) {
+  const float4 t = d.atoms[en.atom];
+  RsLaneEnt l;
+  l.tx = t.x;
+  l.ty = t.y;
+  l.dz = en.dz;
+  l.xr = (int)(unsigned short)en.x0 | ((int)en.nx << 16);
+  l.yr = (int)(unsigned short)en.y0 | ((int)en.ny << 16);
+  return l;
+}
+__device__ __forceinline__ RsLaneEnt rs_empty() {
+  RsLaneEnt l;
+  l.tx = l.ty = l.dz = 0.f;
+  l.xr = l.yr = 0;
+  return l;
 }
 
-// sqrt(Omega) p_m(r - tau) at the point (ix, iy) of the entry; false outside the ball.
-__device__ __forceinline__ bool rs_point(const RsDesc& d, const RsRange& r, int ix, int iy, float dz, float (&p)[4]) {
-  const float dx = fmaf((float)ix, d.hx, -r.tx);
-  const float dy = fmaf((float)iy, d.hy, -r.ty);
-  const float q = fmaf(dx, dx, fmaf(dy, dy, r.dz2));
-  if (q > d.r2) return false;
-  const float g = __expf(-q * d.inv2s2);
-  const float g1 = d.c1 * g;
-  p[0] = d.c0 * g;
-  p[1] = g1 * dx;
-  p[2] = g1 * dy;
-  p[3] = g1 * dz;
-  return true;
+struct RsEntry {
+  float tx, ty, dz, dz2;
+  int x0, nx, y0, ny;
+  unsigned mask;  // bit k: columns 8k .. 8k+7 meet x0 .. x0+nx-1 (mod 128)
+};
+__device__ __forceinline__ RsEntry rs_entry(const RsLaneEnt& l, int k) {
+  RsEntry e;
+  e.tx = rs_lane(l.tx, k);
+  e.ty = rs_lane(l.ty, k);
+  e.dz = rs_lane(l.dz, k);
+  e.dz2 = e.dz * e.dz;
+  const int xr = rs_lane(l.xr, k), yr = rs_lane(l.yr, k);
+  e.x0 = (int)(short)(xr & 0xffff);
+  e.nx = xr >> 16;
+  e.y0 = (int)(short)(yr & 0xffff);
+  e.ny = yr >> 16;
+  const int xs = e.x0 & 127, b0 = xs >> 3, nblk = ((xs + e.nx - 1) >> 3) - b0 + 1;
+  const unsigned m = nblk >= 16 ? 0xffffu : ((1u << nblk) - 1u);
+  e.mask = e.nx <= 0 ? 0u : ((m << b0) | (m >> (16 - b0))) & 0xffffu;
+  return e;
 }
 
-// i = q n + r with 0 <= r < n, for 0 <= i < 2^15 and 1 <= n <= 128 (float quotient, one correction)
-__device__ __forceinline__ void rs_divmod(int i, int n, float inv, int& q, int& r) {
-  q = (int)((float)i * inv);
-  r = i - q * n;
-  if (r < 0) {
-    --q;
-    r += n;
-  } else if (r >= n) {
-    ++q;
-    r -= n;
-  }
+// Row part of row y (0 .. 127): whether it is in the entry's rows, dy, dy^2 + dz^2 and
+// e^{-(dy^2 + dz^2)/(2 s^2)}.
+struct RsRow {
+  bool ok;
+  float dy, s, gyz;
+};
+__device__ __forceinline__ RsRow rs_row(const RsDesc& d, const RsEntry& e, int y) {
+  RsRow w;
+  const int oy = (y - e.y0) & 127;
+  w.ok = oy < e.ny;
+  w.dy = fmaf((float)(e.y0 + oy), d.hy, -e.ty);
+  w.s = fmaf(w.dy, w.dy, e.dz2);
+  w.gyz = __expf(-w.s * d.inv2s2);
+  return w;
+}
+// Column part of column x (0 .. 127): whether it is in the entry's columns, dx, dx^2, e^{-dx^2/(2 s^2)}.
+struct RsCol {
+  bool ok;
+  float dx, dx2, gx;
+};
+__device__ __forceinline__ RsCol rs_colpart(const RsDesc& d, const RsEntry& e, int x) {
+  RsCol c;
+  const int ox = (x - e.x0) & 127;
+  c.ok = ox < e.nx;
+  c.dx = fmaf((float)(e.x0 + ox), d.hx, -e.tx);
+  c.dx2 = c.dx * c.dx;
+  c.gx = __expf(-c.dx2 * d.inv2s2);
+  return c;
+}
+__device__ __forceinline__ bool rs_in(const RsDesc& d, const RsCol& c, const RsRow& w) {
+  return c.ok && w.ok && c.dx2 + w.s <= d.r2;
 }
 
 __device__ __forceinline__ float rs_wave_sum(float v) {
@@ -373,35 +407,43 @@ __device__ __forceinline__ float rs_wave_sum(float v) {
   return v;
 }
 
-// Adds sum_a sum_m sqrt(Omega) p_m(r - tau_a) dp_{a,m} to the rows 8w .. 8w+7 of the plane (held in
-// natural order), atoms in the order of the band's entry list.  Only the calling wave touches these
-// rows, and its LDS accesses complete in program order, so the sums at each point are taken in a
-// fixed order without atomics.
-__device__ __forceinline__ void rs_add_band(float2* plane, const RsDesc& rd, int z, int w, const float2* dp,
-                                            int lane) {
-  constexpr int N = 128;
+// Adds sum_a sum_m sqrt(Omega) p_m(r - tau_a) dp_{a,m} to this lane's 16 values of row y (x = t + 8k),
+// atoms in the order of the band's entry list.  With p_0 = c0 g, p_m = c1 d_m g and g = gx gyz the
+// term is gx (w0 + dx w1), w0 = gyz (c0 dp_0 + c1 (dy dp_y + dz dp_z)), w1 = gyz c1 dp_x.
+__device__ __forceinline__ void rs_add_regs(float2 (&r)[16], const RsDesc& rd, int z, int w, int y, int t,
+                                            const float2* dp, int lane) {
   const int e0 = rd.boff[16 * z + w], e1 = rd.boff[16 * z + w + 1];
-  for (int e = e0; e < e1; ++e) {
-    const RsEnt en = rd.bent[e];
-    const RsRange rr = rs_range(rd, en.atom, en.dz);
-    if (rr.nx <= 0 || rr.ny <= 0) continue;
-    const float2 c0 = dp[4 * en.atom], c1 = dp[4 * en.atom + 1], c2 = dp[4 * en.atom + 2], c3 = dp[4 * en.atom + 3];
-    const int np = 8 * rr.nx;
-    const float inv = 1.0f / (float)rr.nx;
-    for (int i = lane; i < np; i += 64) {
-      int q, r;
-      rs_divmod(i, rr.nx, inv, q, r);
-      const int y = 8 * w + q;
-      const int iy = rr.y0 + ((y - rr.y0) & (N - 1));  // the unwrapped row of y in y0 .. y0 + 127
-      if (iy - rr.y0 >= rr.ny) continue;
-      const int ix = rr.x0 + r;
-      float p[4];
-      if (!rs_point(rd, rr, ix, iy, en.dz, p)) continue;
-      float2* v = plane + y * N + ((ix & (N - 1)) ^ rs_swz(y));
-      float2 u = *v;
-      u.x += fmaf(p[0], c0.x, fmaf(p[1], c1.x, fmaf(p[2], c2.x, p[3] * c3.x)));
-      u.y += fmaf(p[0], c0.y, fmaf(p[1], c1.y, fmaf(p[2], c2.y, p[3] * c3.y)));
-      *v = u;
+  for (int base = e0; base < e1; base += 64) {
+    RsLaneEnt le = rs_empty();
+    float2 q0 = make_float2(0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
+    if (base + lane < e1) {
+      const RsEnt en = rd.bent[base + lane];
+      le = rs_load(rd, en);
+      const float2* c = dp + 4 * en.atom;
+      q0 = c[0];
+      q1 = c[1];
+      q2 = c[2];
+      q3 = c[3];
+    }
+    const int cnt = min(64, e1 - base);
+    for (int k = 0; k < cnt; ++k) {
+      const RsEntry e = rs_entry(le, k);
+      const RsRow rw = rs_row(rd, e, y);
+      const float c0 = rd.c0, c1 = rd.c1;
+      const float ax = fmaf(c0, rs_lane(q0.x, k), c1 * e.dz * rs_lane(q3.x, k));
+      const float ay = fmaf(c0, rs_lane(q0.y, k), c1 * e.dz * rs_lane(q3.y, k));
+      const float w0x = rw.gyz * fmaf(rw.dy, c1 * rs_lane(q2.x, k), ax);
+      const float w0y = rw.gyz * fmaf(rw.dy, c1 * rs_lane(q2.y, k), ay);
+      const float w1x = rw.gyz * c1 * rs_lane(q1.x, k), w1y = rw.gyz * c1 * rs_lane(q1.y, k);
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        if (e.mask & (1u << kk)) {
+          const RsCol cc = rs_colpart(rd, e, t + 8 * kk);
+          const float gx = rs_in(rd, cc, rw) ? cc.gx : 0.f;
+          r[kk].x += gx * fmaf(cc.dx, w1x, w0x);
+          r[kk].y += gx * fmaf(cc.dx, w1y, w0y);
+        }
+      }
     }
   }
 }
@@ -426,8 +468,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 __device__ __forceinline__ int p128_col(int row, int xa) { return xa ^ ((((row >> 4) ^ row) & 1) << 3); }
 
-// NL: the real-space projectors' D P term is added to V psi between the x passes (rs_add_band;
-// the plane then holds each wave's rows in natural order for that step).
+// NL: the real-space projectors' D P term is added to V psi between the x passes (rs_add_regs).
 template <bool NL>
 __global__ __launch_bounds__(1024) void k_plane128(float2* __restrict__ SB, const float* __restrict__ V,
                                                    const int* __restrict__ colstart, GridDesc g,
@@ -541,17 +582,7 @@ __global__ __launch_bounds__(1024) void k_plane128(float2* __restrict__ SB, cons
     SmallDft<T, B, +1>::run(r2);  // r2[k2] = value at x = t + 8 k2
 #pragma unroll
     for (int k2 = 0; k2 < B; ++k2) r2[k2] = cscale<T>(r2[k2], vr[k2]);
-    if constexpr (NL) {
-      const int sw = rs_swz(y);
-      wave_sync();
-#pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) row[(t + A * k2) ^ sw] = r2[k2];
-      wave_sync();
-      rs_add_band(plane, rd, z, wv, dp + (long)b * nproj, lane);
-      wave_sync();
-#pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) r2[k2] = row[(t + A * k2) ^ sw];
-    }
+    if constexpr (NL) rs_add_regs(r2, rd, z, wv, y, t, dp + (long)b * nproj, lane);
     SmallDft<T, B, -1>::run(r2);  // over m2, output q2
 #pragma unroll
     for (int q2 = 1; q2 < B; ++q2) r2[q2] = cmul<T>(r2[q2], tw[(t * q2) % N]);
@@ -850,10 +881,14 @@ __device__ __forceinline__ void xinv_row_store(float2* plane, const float2* tw, 
   for (int k2 = 0; k2 < B; ++k2) row[(t + A * k2) ^ sw] = r2[k2];
 }
 
+// log2 of the lanes per row of an entry: 16, 32 or 64 columns at a time (64 / lx rows per step).
+__device__ __forceinline__ int rs_lxs(int nx) { return nx <= 16 ? 4 : (nx <= 32 ? 5 : 6); }
+
 // Inverse pass with the projections: a workgroup takes plane z of band b, transforms it inside LDS
 // (inverse y on the active columns, inverse x on every row), then each wave takes entries of the
-// plane (one atom each), sums p_m(r - tau) psi(r) over the entry's points with its 64 lanes and
-// writes the four sums, reduced across the wave in a fixed order, to part[(b nent + e) 4 + m].
+// plane (one atom each), sums g psi, g dx psi and g dy psi over the entry's points with its 64
+// lanes (p_z = c1 dz g needs no sum of its own) and writes the four projector sums, reduced
+// across the wave in a fixed order, to part[(b nent + e) 4 + m].
 __global__ __launch_bounds__(1024) void k_rs_proj128(const float2* __restrict__ SB, const int* __restrict__ colstart,
                                                      GridDesc g, const float2* __restrict__ twg, RsDesc rd,
                                                      float2* __restrict__ part) {
@@ -880,35 +915,47 @@ __global__ __launch_bounds__(1024) void k_rs_proj128(const float2* __restrict__ 
   xinv_row_store(plane, tw, wv * LPW + l, t, g.n1max);
   __syncthreads();
   float2* pb = part + (long)b * rd.nent * 4;
-  for (int e = e0 + wv; e < e1; e += NW) {
-    const RsEnt en = rd.zent[e];
-    const RsRange rr = rs_range(rd, en.atom, en.dz);
-    float acc[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = 0.f;
-    const int np = rr.nx * rr.ny;
-    const float inv = rr.nx > 0 ? 1.0f / (float)rr.nx : 0.f;
-    for (int i = lane; i < np; i += 64) {
-      int q, r;
-      rs_divmod(i, rr.nx, inv, q, r);
-      const int ix = rr.x0 + r, iy = rr.y0 + q;
-      float p[4];
-      if (rs_point(rd, rr, ix, iy, en.dz, p)) {
-        const int y = iy & (N - 1);
-        const float2 v = plane[y * N + ((ix & (N - 1)) ^ rs_swz(y))];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          acc[2 * m] = fmaf(p[m], v.x, acc[2 * m]);
-          acc[2 * m + 1] = fmaf(p[m], v.y, acc[2 * m + 1]);
+  // this wave's entries e0 + wv + 16 k, their data loaded one entry per lane
+  for (int base = e0 + wv; base < e1; base += NW * 64) {
+    RsLaneEnt le = rs_empty();
+    if (base + NW * lane < e1) le = rs_load(rd, rd.zent[base + NW * lane]);
+    const int cnt = min(64, (e1 - base + NW - 1) / NW);
+    for (int k = 0; k < cnt; ++k) {
+      const int e = base + NW * k;
+      const RsEntry en = rs_entry(le, k);
+      float s0x = 0.f, s0y = 0.f, sxx = 0.f, sxy = 0.f, syx = 0.f, syy = 0.f;
+      const int lxs = rs_lxs(en.nx), lx = 1 << lxs, rps = 64 >> lxs;
+      const int lr = lane >> lxs, lc = lane & (lx - 1);
+      for (int xc = 0; xc < en.nx; xc += lx) {
+        const int x = (en.x0 + xc + lc) & (N - 1);
+        const RsCol cc = rs_colpart(rd, en, x);
+        const bool colok = cc.ok && xc + lc < en.nx;
+        for (int q = lr; q < en.ny; q += rps) {
+          const int y = (en.y0 + q) & (N - 1);
+          const RsRow rw = rs_row(rd, en, y);
+          const float gg = (colok && rs_in(rd, cc, rw)) ? cc.gx * rw.gyz : 0.f;
+          const float2 v = plane[y * N + (x ^ rs_swz(y))];
+          const float gxv = gg * cc.dx, gyv = gg * rw.dy;
+          s0x = fmaf(gg, v.x, s0x);
+          s0y = fmaf(gg, v.y, s0y);
+          sxx = fmaf(gxv, v.x, sxx);
+          sxy = fmaf(gxv, v.y, sxy);
+          syx = fmaf(gyv, v.x, syx);
+          syy = fmaf(gyv, v.y, syy);
         }
       }
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = rs_wave_sum(acc[k]);
-    if (lane == 0) {
-      float4* o = reinterpret_cast<float4*>(pb + (long)e * 4);
-      o[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-      o[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+      s0x = rs_wave_sum(s0x);
+      s0y = rs_wave_sum(s0y);
+      sxx = rs_wave_sum(sxx);
+      sxy = rs_wave_sum(sxy);
+      syx = rs_wave_sum(syx);
+      syy = rs_wave_sum(syy);
+      if (lane == 0) {
+        const float c0 = rd.c0, c1 = rd.c1, c1z = rd.c1 * en.dz;
+        float4* o = reinterpret_cast<float4*>(pb + (long)e * 4);
+        o[0] = make_float4(c0 * s0x, c0 * s0y, c1 * sxx, c1 * sxy);
+        o[1] = make_float4(c1 * syx, c1 * syy, c1z * s0x, c1z * s0y);
+      }
     }
   }
 }
@@ -1064,11 +1111,12 @@ __global__ __launch_bounds__(256) void k_sticks_inv_n(const cplx<T>* __restrict_
   }
 }
 
-// sticks -> sphere, forward FFT along z.
-template <typename T, int A, int B>
+// sticks -> sphere, forward FFT along z.  UPD (FP32): the Chebyshev update of StickUpd is applied to
+// each value as it is written (Z is then the updated block).
+template <typename T, int A, int B, bool UPD = false>
 __global__ __launch_bounds__(256) void k_sticks_fwd_n(const cplx<T>* __restrict__ SB, cplx<T>* __restrict__ Z,
                                                       long ldz, const Stick* __restrict__ st, GridDesc g,
-                                                      const cplx<T>* __restrict__ twg) {
+                                                      const cplx<T>* __restrict__ twg, StickUpd u) {
   using SS = StickShape<T, A, B>;
   constexpr int N = A * B, TT = SS::TT, SPW = SS::SPW, NT = SS::NT, I1 = B / TT, J2 = A / TT;
   __shared__ cplx<T> buf[N * SPW];
@@ -1116,7 +1164,24 @@ __global__ __launch_bounds__(256) void k_sticks_fwd_n(const cplx<T>* __restrict_
 #pragma unroll
     for (int k2 = 0; k2 < B; ++k2) {
       const int e = stick_index(k1 + A * k2, h, N);
-      if (e >= 0) zs[e] = r2[k2];
+      if (e >= 0) {
+        if constexpr (UPD) {
+          const long i = (long)sk.off + e;
+          const float2 y = u.Y[(long)b * u.ldy + i];
+          const float kc = u.kin[i] - u.c;
+          float2 v;
+          v.x = u.alpha * (kc * y.x + r2[k2].x);
+          v.y = u.alpha * (kc * y.y + r2[k2].y);
+          if (u.Yp) {
+            const float2 p = u.Yp[(long)b * u.ldp + i];
+            v.x -= u.beta * p.x;
+            v.y -= u.beta * p.y;
+          }
+          zs[e] = v;
+        } else {
+          zs[e] = r2[k2];
+        }
+      }
     }
   }
 }
@@ -1159,7 +1224,23 @@ hipError_t launch_sticks_fwd_n(const cplx<T>* SB, cplx<T>* Z, long ldz, int nbat
 #define PW_CASE(NN, AA, BB)                                                                                   \
   case NN:                                                                                                    \
     hipLaunchKernelGGL((k_sticks_fwd_n<T, AA, BB>), dim3(ceil_div(g.nst, StickShape<T, AA, BB>::SPW), nbatch),  \
-                       dim3(StickShape<T, AA, BB>::NT), 0, s, SB, Z, ldz, st, g, tw3);                         \
+                       dim3(StickShape<T, AA, BB>::NT), 0, s, SB, Z, ldz, st, g, tw3, StickUpd{});             \
+    return hipGetLastError();
+    PW_STICK_SIZES(PW_CASE)
+#undef PW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sticks_fwd_upd(const float2* SB, float2* out, long ldo, int nbatch, const Stick* st,
+                                 const GridDesc& g, const float2* tw3, const StickUpd& u, hipStream_t s) {
+  switch (g.n3) {
+#define PW_CASE(NN, AA, BB)                                                                                     \
+  case NN:                                                                                                      \
+    hipLaunchKernelGGL((k_sticks_fwd_n<float, AA, BB, true>),                                                   \
+                       dim3(ceil_div(g.nst, StickShape<float, AA, BB>::SPW), nbatch),                           \
+                       dim3(StickShape<float, AA, BB>::NT), 0, s, SB, out, ldo, st, g, tw3, u);                 \
     return hipGetLastError();
     PW_STICK_SIZES(PW_CASE)
 #undef PW_CASE

@@ -48,9 +48,13 @@ hipError_t launch_plane_n(cplx<T>* SB, const T* V, int nbatch, const Stick* st, 
 void pw_allow_large_lds_plane_n();
 // Real-space projectors on 128 x 128 FP32 planes (sticks in SB as for the plane pass).
 // Inverse pass: the projections of nbatch bands, one partial of 4 complex sums per band and
-// entry: part[(b nent + e) 4 + m].  SB is only read.
+// (atom, plane) entry: part[(b nent + e) 4 + m].  SB is only read.
 hipError_t launch_rs_proj128(const float2* SB, const int* colstart, const GridDesc& g, const float2* tw,
                              const RsDesc& rd, int nbatch, float2* part, hipStream_t s);
+// Forward stick pass (sized sticks) with the Chebyshev update of u applied as the sphere values are
+// written: out[b ldo + i] = alpha ((kin[i] - c) Y[b ldy + i] + z) - beta Yp[b ldp + i].
+hipError_t launch_sticks_fwd_upd(const float2* SB, float2* out, long ldo, int nbatch, const Stick* st,
+                                 const GridDesc& g, const float2* tw3, const StickUpd& u, hipStream_t s);
 // dp[b nproj + 4a + m] = dscale[m] inv_nr (sum over atom a's entries of part), b < nbt.
 hipError_t launch_rs_reduce(const float2* part, const RsDesc& rd, int nbt, const double* dscale, double inv_nr,
                             float2* dp, int nproj, hipStream_t s);

@@ -46,17 +46,18 @@ static size_t align_up(size_t x) { return (x + kArenaAlign - 1) / kArenaAlign * 
 
 // Tables of the real-space projectors.  Atom a (position wrapped into the cell) reaches the planes
 // iz = ceil((z_a - R) / h_z) .. floor((z_a + R) / h_z) (unwrapped; plane iz mod n3), and within
-// plane iz the rows of the disc of radius sqrt(R^2 - dz^2), dz = iz h_z - z_a.  The host lists use
-// a radius enlarged by a relative 1e-4 so that they hold every (atom, plane) and (atom, band) pair
-// the kernels' FP32 ranges can reach; the kernels themselves decide which points lie in the ball.
+// plane iz the columns and rows of the disc of radius sqrt(R^2 - dz^2), dz = iz h_z - z_a: one
+// per-plane entry, and one per-band entry for each 8-row band the disc's rows meet.  The ranges
+// use a radius enlarged by a relative 1e-4, so that they hold every point the kernels' FP32 test
+// can accept; the kernels decide which points lie in the ball.  Each atom's per-plane entries are
+// listed in plane order for the reduction.
 static void build_rspace_tables(Plan& P) {
   const GridDesc& g = P.g;
-  const int n3 = g.n3, nbands_rows = 16;  // 128 rows in bands of 8
+  const int n3 = g.n3, nbr = 16;  // 128 rows in bands of 8
   const double h[3] = {P.L[0] / g.n1, P.L[1] / g.n2, P.L[2] / g.n3};
   const double R = P.rs_radius, Rs = R * (1.0 + 1e-4);
   P.rs_atoms.assign(4 * (size_t)P.natoms, 0.f);
-  std::vector<std::vector<RsEnt>> per_z(n3), per_band((size_t)n3 * nbands_rows);
-  std::vector<std::vector<int>> atom_planes(P.natoms);  // plane of each of the atom's entries, in order
+  std::vector<std::vector<RsEnt>> per_z(n3), per_band((size_t)n3 * nbr);
   for (int a = 0; a < P.natoms; ++a) {
     double t[3];
     for (int i = 0; i < 3; ++i) {
@@ -69,50 +70,43 @@ static void build_rspace_tables(Plan& P) {
     for (int iz = z0; iz <= z1; ++iz) {
       const int z = ((iz % n3) + n3) % n3;
       const float dz = (float)(iz * h[2] - t[2]);
-      per_z[z].push_back(RsEnt{a, dz});
-      atom_planes[a].push_back(z);
       const double rho2 = Rs * Rs - (double)dz * dz;
       if (rho2 < 0) continue;
       const double rho = std::sqrt(rho2);
+      const int x0 = (int)std::ceil((t[0] - rho) / h[0]), x1 = (int)std::floor((t[0] + rho) / h[0]);
       const int y0 = (int)std::ceil((t[1] - rho) / h[1]), y1 = (int)std::floor((t[1] + rho) / h[1]);
-      std::vector<char> hit(nbands_rows, 0);
+      if (x1 < x0 || y1 < y0) continue;
+      const RsEnt e{a, dz, (short)x0, (short)(x1 - x0 + 1), (short)y0, (short)(y1 - y0 + 1)};
+      per_z[z].push_back(e);
+      std::vector<char> hit(nbr, 0);
       for (int iy = y0; iy <= y1; ++iy) hit[(((iy % 128) + 128) % 128) / 8] = 1;
-      for (int w = 0; w < nbands_rows; ++w)
-        if (hit[w]) per_band[(size_t)z * nbands_rows + w].push_back(RsEnt{a, dz});
+      for (int w = 0; w < nbr; ++w)
+        if (hit[w]) per_band[(size_t)z * nbr + w].push_back(e);
     }
   }
   P.rs_zoff.assign(n3 + 1, 0);
   P.rs_zent.clear();
-  std::vector<std::vector<int>> slot(P.natoms);  // zent index of each of the atom's entries
+  std::vector<std::vector<std::pair<int, int>>> of_atom(P.natoms);  // (unwrapped order key, zent index)
   for (int z = 0; z < n3; ++z) {
     P.rs_zoff[z] = (int)P.rs_zent.size();
     for (const RsEnt& e : per_z[z]) {
-      slot[e.atom].push_back((int)P.rs_zent.size());
+      of_atom[e.atom].push_back({z, (int)P.rs_zent.size()});
       P.rs_zent.push_back(e);
     }
   }
   P.rs_zoff[n3] = (int)P.rs_zent.size();
-  // each atom's entries in the order of its planes iz (ascending unwrapped z)
   P.rs_aoff.assign(P.natoms + 1, 0);
   P.rs_aent.clear();
   for (int a = 0; a < P.natoms; ++a) {
     P.rs_aoff[a] = (int)P.rs_aent.size();
-    std::vector<int> zs = atom_planes[a];
-    std::vector<int> sl = slot[a];  // in increasing wrapped z, one per plane (planes are distinct)
-    std::vector<int> by_plane(n3, -1);
-    {
-      std::vector<int> sorted_z = zs;
-      std::sort(sorted_z.begin(), sorted_z.end());
-      for (size_t k = 0; k < sorted_z.size(); ++k) by_plane[sorted_z[k]] = sl[k];
-    }
-    for (int z : zs) P.rs_aent.push_back(by_plane[z]);
+    for (const auto& pr : of_atom[a]) P.rs_aent.push_back(pr.second);
   }
   P.rs_aoff[P.natoms] = (int)P.rs_aent.size();
-  P.rs_boff.assign((size_t)n3 * nbands_rows + 1, 0);
+  P.rs_boff.assign(per_band.size() + 1, 0);
   P.rs_bent.clear();
   for (size_t k = 0; k < per_band.size(); ++k) {
     P.rs_boff[k] = (int)P.rs_bent.size();
-    for (const RsEnt& e : per_band[k]) P.rs_bent.push_back(e);
+    P.rs_bent.insert(P.rs_bent.end(), per_band[k].begin(), per_band[k].end());
   }
   P.rs_boff[per_band.size()] = (int)P.rs_bent.size();
 }

@@ -56,8 +56,8 @@ struct Plan {
   int hmax[3];                 // max |n_d| over the sphere (projector generator tables)
   int bwidth;                  // per-atom axis-factor table length
   int proj_form;               // PW_PROJ_GSPACE or PW_PROJ_LOCALIZED
-  // real-space projectors (PW_FLAG_RSPACE_KB): per-atom positions, the (atom, plane) entries
-  // per plane and per (plane, 8-row band), and each atom's entries; see RsDesc
+  // real-space projectors (PW_FLAG_RSPACE_KB): per-atom positions, the (atom, plane) entries per
+  // plane and per (plane, 8-row band), and each atom's per-plane entries; see RsDesc
   bool rspace;
   double rs_radius;
   std::vector<float> rs_atoms;  // 4 per atom

@@ -40,14 +40,14 @@ def gpu():
     return torch
 
 
-def radius_for(cell):
-    # 7 sigma where the cell allows it, else just below half the smallest cell length
-    return min(7.0 * cell.pseudo.beta_sigma, 0.49 * float(np.min(cell.L)))
+def radius_for(cell, nsigma=7.0):
+    # nsigma sigma where the cell allows it, else just below half the smallest cell length
+    return min(nsigma * cell.pseudo.beta_sigma, 0.49 * float(np.min(cell.L)))
 
 
-def rs_case(name, nb, seed, grid=(128, 128, 128), flags=0):
+def rs_case(name, nb, seed, grid=(128, 128, 128), flags=0, nsigma=7.0):
     cell = synth.make_cell(name, modes=True)
-    R = radius_for(cell)
+    R = radius_for(cell, nsigma)
     model = O.model_from_cell(cell, grid=grid, proj_form=O.PROJ_LOCALIZED, rs_radius=R)
     h = pw.Handle(cell, pw.PW_MIXED, nbands=nb, fft_n=grid, flags=RS | flags, proj_form=LOC, rs_radius=R)
     assert tuple(h.info.fft_n) == tuple(grid) and h.info.fused_planes == 1
@@ -57,9 +57,9 @@ def rs_case(name, nb, seed, grid=(128, 128, 128), flags=0):
     return cell, model, h, X, p, R, out
 
 
-@pytest.mark.parametrize("name,nb", [("si8", 20), ("si64", 9)])
-def test_rspace_apply_h_matches_oracle_realspace(name, nb):
-    cell, model, h, X, p, R, out = rs_case(name, nb, 500 + nb)
+@pytest.mark.parametrize("name,nb,nsigma", [("si8", 20, 7.0), ("si64", 9, 7.0), ("si64", 9, 5.5)])
+def test_rspace_apply_h_matches_oracle_realspace(name, nb, nsigma):
+    cell, model, h, X, p, R, out = rs_case(name, nb, 500 + nb, nsigma=nsigma)
     ref = O.apply_h(model, X)
     err = float(np.abs(out - ref[p]).max() / np.abs(ref).max())
     say("rspace apply_h", name, "R", R, "rel err vs oracle real-space route", err)
