@@ -273,7 +273,10 @@ struct Engine {
   unsigned int* yp_hi() const { return work<unsigned int>(P.lay.yp, h->ws_yp); }
   unsigned int* yp_lo() const { return yp_hi() + (size_t)P.ldw * (h->ws ? h->ws_cols : P.yp_cols); }
   // the unblocked step keeps the planes of W = H Y beside those of Y for the Gram product
-  bool gram_planes() const { return beta_planes() && P.yp_cols >= 2 * P.nbb; }
+  bool gram_planes() const {
+    return std::is_same<T, float>::value && (beta_planes() || P.rspace) && flag(PW_FLAG_BF16_GRAM) &&
+           P.yp_cols >= 2 * P.nbb;
+  }
   // with projector planes, D B^H Y is kept as the nonlocal product's B planes in the bytes of PT
   unsigned int* pt_hi() const { return work<unsigned int>(P.lay.pt, h->ws_pt); }
   unsigned int* pt_lo() const { return pt_hi() + (size_t)P.nproj * (h->ws ? h->ws_cols : P.nbb); }
@@ -747,6 +750,18 @@ struct Engine {
       PW_TIMED(PW_PH_GRAM, launch_gemm_cn_bf16x3_planes(yp_hi(), yp_lo(), P.ldw, yp_hi(), yp_lo(), P.ldw, nb, 2 * nb,
                                                         P.npw, P.nsplit_gram, parts, h->stream, 4, nb));
       return dense_solve(nb, P.nsplit_gram, 0.0, true);
+    }
+    if constexpr (std::is_same<T, float>::value) {
+      if (P.rspace && gram_planes() && nb <= P.nbb) {
+        // real-space projectors write no planes: split Y and W here for the planes' Gram product
+        const size_t pc = (size_t)P.ldw * nb;
+        PW_TIMED(PW_PH_OTHER, launch_split_planes(Y, ldy, P.npw, nb, yp_hi(), yp_lo(), P.ldw, h->stream));
+        PW_TIMED(PW_PH_OTHER, launch_split_planes(W, ldw, P.npw, nb, yp_hi() + pc, yp_lo() + pc, P.ldw, h->stream));
+        set_planes(Y, nb);
+        PW_TIMED(PW_PH_GRAM, launch_gemm_cn_bf16x3_planes(yp_hi(), yp_lo(), P.ldw, yp_hi(), yp_lo(), P.ldw, nb,
+                                                          2 * nb, P.npw, P.nsplit_gram, parts, h->stream, 4, nb));
+        return dense_solve(nb, P.nsplit_gram, 0.0, true);
+      }
     }
     PW_TIMED(PW_PH_GRAM, cn(flag(PW_FLAG_BF16_GRAM), Y, ldy, Y, ldy, W, ldw, nb, nb, 2 * nb, P.npw, P.nsplit_gram,
                             parts, 4));

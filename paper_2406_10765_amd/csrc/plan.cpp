@@ -336,8 +336,10 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   P.nsplit_proj = P.nproj ? (bkb ? pick_split(gemm_cn_bf16_planes_tiles(P.nproj, P.nbb), P.npw, 4096)
                                   : pick_split(gemm_cn_tiles(P.nproj, P.nbb, f64), P.npw))
                           : 1;
-  const bool gram_planes = bkb && bgr && P.nbb >= P.nbands;
-  P.yp_cols = bkb ? P.nbb * (gram_planes ? 2 : 1) : 0;
+  // planes of Y and W for the Gram product: written by the nonlocal product's epilogue with
+  // split-precision projectors, split from Y and W before the Gram product with real-space ones
+  const bool gram_planes = (bkb || P.rspace) && bgr && P.nbb >= P.nbands;
+  P.yp_cols = bkb ? P.nbb * (gram_planes ? 2 : 1) : (gram_planes ? 2 * P.nbb : 0);
   P.nsplit_gram = gram_planes ? pick_split(gemm_cn_bf16_planes_tiles(P.nbands, 2 * P.nbands), P.npw, 4096)
                   : pick_split(bgr ? gemm_cn_bf16_tiles(P.nbands, 2 * P.nbands)
                                    : gemm_cn_tiles(P.nbands, 2 * P.nbands, f64),
