@@ -468,6 +468,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-lobpcg", action="store_true", help="skip the LOBPCG step timing")
     ap.add_argument("--no-rspace", action="store_true", help="skip the real-space projector comparison")
+    ap.add_argument("--rspace-only", action="store_true",
+                    help="run only the real-space projector comparison on the workload (for traces)")
     ap.add_argument("--flags", type=int, default=None,
                     help="mixed-precision product flags (bit 2: bf16 Gram, 4: bf16 projectors, 8: bf16 rotation)")
     ap.add_argument("--serving-requests", type=int, default=200,
@@ -501,6 +503,11 @@ def main():
         mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
         print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate, args.serving_slots,
                                                  mflags, args.degree)}), flush=True)
+        return
+    if args.rspace_only:
+        cell = synth.make_cell(args.workload)
+        print(json.dumps({"rspace_projectors": rspace_leg(pw, synth, torch, cell, args.degree, args.steps)}),
+              flush=True)
         return
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
