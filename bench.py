@@ -470,6 +470,8 @@ def main():
     ap.add_argument("--no-rspace", action="store_true", help="skip the real-space projector comparison")
     ap.add_argument("--rspace-only", action="store_true",
                     help="run only the real-space projector comparison on the workload (for traces)")
+    ap.add_argument("--rspace-apply", action="store_true",
+                    help="two real-space H applications of the workload's block and exit (for counter runs)")
     ap.add_argument("--flags", type=int, default=None,
                     help="mixed-precision product flags (bit 2: bf16 Gram, 4: bf16 projectors, 8: bf16 rotation)")
     ap.add_argument("--serving-requests", type=int, default=200,
@@ -503,6 +505,17 @@ def main():
         mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
         print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate, args.serving_slots,
                                                  mflags, args.degree)}), flush=True)
+        return
+    if args.rspace_apply:
+        cell = synth.make_cell(args.workload)
+        h = pw.Handle(cell, pw.PW_MIXED, flags=pw.PW_FLAG_RSPACE_KB | 2 | 8, proj_form=pw.PW_PROJ_LOCALIZED,
+                      rs_radius=5.5 * cell.pseudo.beta_sigma)
+        X = h.random_block(cell.nbands, synth.SEED_X0 + 17)
+        HX = torch.empty_like(X)
+        for i in range(2):
+            h.apply_h(X, HX)
+            torch.cuda.synchronize()
+            log(f"real-space H application {i + 1} done")
         return
     if args.rspace_only:
         cell = synth.make_cell(args.workload)
