@@ -31,6 +31,7 @@ PEAK_MFMA_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 # bf16 split products: Gram / projected matrices (4 terms), projectors and rotations (3 terms)
 DEFAULT_MIXED_FLAGS = 2 | 4 | 8
 PEAK_BF16_TFLOPS = 2516.6
+PEAK_VALU_FP32_TFLOPS = 157.3  # FP32 vector ALU (256 CUs at 2.4 GHz)
 METRIC = "eig-steps/sec & HΨ band-apps/sec, mixed vs FP64 @|Δε|≤1e-5 Ha; p99 latency"
 
 
@@ -393,6 +394,31 @@ def rspace_leg(pw, synth, torch, cell, m, steps):
         torch.cuda.empty_cache()
     out["max_abs_deig_occ_Ha"] = float(np.abs(eigs["gspace"][: cell.nocc] - eigs["rspace"][: cell.nocc]).max())
     out["speedup"] = round(out["gspace"]["ms_per_step"] / out["rspace"]["ms_per_step"], 3)
+    # algorithmic work of the real-space passes: 16 flop (four real projectors times one complex
+    # value) per ball point and band in each of the two passes; the ball points are counted on the
+    # grid (nearest image), and the passes' time is the projection phase plus what the D P
+    # addition adds to the plane phase
+    n = np.asarray(pw.plan(cell, pw.PW_MIXED).fft_n)
+    h = np.asarray(cell.L, float) / n
+    nball = 0
+    for t in np.asarray(cell.tau, float):
+        t = np.mod(t, cell.L)
+        ax = [np.arange(int(np.ceil((t[i] - R) / h[i])), int(np.floor((t[i] + R) / h[i])) + 1) * h[i] - t[i]
+              for i in range(3)]
+        d2 = ax[0][:, None, None] ** 2 + ax[1][None, :, None] ** 2 + ax[2][None, None, :] ** 2
+        nball += int((d2 <= R * R).sum())
+    r, g = out["rspace"]["phases_ms_per_step"], out["gspace"]["phases_ms_per_step"]
+    t_ms = r.get("proj", 0.0) + r.get("plane", 0.0) - g.get("plane", 0.0)
+    nl_apps = out["gspace"]["phases_launches_per_step"].get("nl", 0)
+    flop = 2 * 16.0 * nball * nb * nl_apps
+    out["ball_points"] = nball
+    out["alu"] = {"flop_per_h_application": 2 * 16.0 * nball * nb, "h_applications_per_step": nl_apps,
+                  "ms_per_step": round(t_ms, 2),
+                  "tflops": round(flop / (t_ms * 1e-3) / 1e12, 2) if t_ms > 0 else None,
+                  "peak_tflops": PEAK_VALU_FP32_TFLOPS,
+                  "what": "both real-space passes against the FP32 vector peak (the GEMMs of the other route: "
+                          "2 x 8 N_pw N_proj N_b flop per H application on the matrix cores)"}
+    out["alu"]["frac"] = round(out["alu"]["tflops"] / PEAK_VALU_FP32_TFLOPS, 4) if out["alu"]["tflops"] else None
     return out
 
 
