@@ -10,7 +10,8 @@ family in reciprocal space, against the oracle.
 * The reciprocal-space GEMM route with the localized family (FP64 table, FP32 table, bf16 planes)
   against the oracle: 1e-12 / 2e-5 / 5e-5.
 * Filter steps (degree 0, then 10) with the real-space route against the oracle's steps with
-  its real-space route: occupied eigenvalues within 1e-5 Ha.
+  its real-space route, unblocked and band-blocked: occupied eigenvalues within 1e-5 Ha.
+* Grids with 96 and 192 z planes (the second on a 1 x 1 x 2 cell, unequal steps along x, y, z).
 * pw_apply_h_noalloc refuses such handles (the argument errors of the flag are host tests).
 """
 import sys
@@ -70,6 +71,51 @@ def test_rspace_apply_h_matches_oracle_realspace(name, nb, nsigma):
     err_g = float(np.abs(out - ref_g[p]).max() / np.abs(ref_g).max())
     say("  rel err vs reciprocal-space localized route", err_g)
     assert err_g < 2e-5
+    h.close()
+
+
+@pytest.mark.parametrize("ncells,grid", [((1, 1, 1), (128, 128, 96)), ((1, 1, 2), (128, 128, 192))])
+def test_rspace_apply_h_other_z_grids(ncells, grid):
+    # z planes other than 128 (and an orthorhombic cell: different steps along x, y and z)
+    cell = synth.silicon_cell(ncells, 10.0, nbands=6, disp_seed=synth.SEED_REQUEST + 11,
+                              modes_seed=synth.SEED_MODES + 5)
+    R = radius_for(cell)
+    model = O.model_from_cell(cell, grid=grid, proj_form=O.PROJ_LOCALIZED, rs_radius=R)
+    h = pw.Handle(cell, pw.PW_MIXED, nbands=6, fft_n=grid, flags=RS, proj_form=LOC, rs_radius=R)
+    assert tuple(h.info.fft_n) == grid
+    p = pw.permutation_to(model.miller, h.gvectors())
+    X = synth.random_block(model.npw, 6, 733).astype(np.complex64).astype(np.complex128)
+    out = h.to_host(h.apply_h(h.to_device(X[p])))
+    ref = O.apply_h(model, X)
+    err = float(np.abs(out - ref[p]).max() / np.abs(ref).max())
+    say("rspace apply_h grid", grid, "L", cell.L, "R", R, "rel err", err)
+    assert err < 2e-5
+    h.close()
+
+
+def test_rspace_blocked_step_matches_oracle():
+    # band-blocked filter (blocks of 8, 8, 4 bands) with the real-space route
+    cell = synth.make_cell("si8", modes=True)
+    grid = (128, 128, 128)
+    R = radius_for(cell)
+    model = O.model_from_cell(cell, grid=grid, proj_form=O.PROJ_LOCALIZED, rs_radius=R)
+    hop = lambda X: O.apply_h(model, X)
+    h = pw.Handle(cell, pw.PW_MIXED, fft_n=grid, flags=RS, proj_form=LOC, rs_radius=R, filter_block=8)
+    assert h.info.filter_block == 8
+    p = pw.permutation_to(model.miller, h.gvectors())
+    inv = np.argsort(p)
+    X0g = synth.initial_block(h.gvectors(), cell.L, cell.nbands, synth.SEED_X0 + 10)
+    X0g = X0g.astype(np.complex64).astype(np.complex128)
+    b = 1.01 * O.lanczos_max(hop, model.npw, 20, seed=3)
+    s1 = O.eig_step(hop, X0g[inv], 0, 0.0, 0.0, b)
+    s2 = O.eig_step(hop, s1.X, 10, s1.a_lo, s1.a, b)
+    Xd = h.to_device(X0g)
+    e1, _, _ = h.eig_step(Xd, 0, b=b)
+    e2, _, _ = h.eig_step(Xd, 10, s1.a_lo, s1.a, b)
+    d1 = np.abs(e1 - s1.eig)[: cell.nocc].max()
+    d2 = np.abs(e2 - s2.eig)[: cell.nocc].max()
+    say("rspace blocked steps m=0", d1, "m=10", d2)
+    assert d1 < 1e-5 and d2 < 1e-5
     h.close()
 
 
