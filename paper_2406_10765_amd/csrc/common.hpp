@@ -67,7 +67,7 @@ struct RsDesc {
   int nent, natoms;     // nent: zent entries
   float hx, hy;         // grid steps along x and y (bohr)
   float r2;             // truncation radius squared (bohr^2)
-  float inv2s2;         // 1 / (2 sigma^2)
+  float k2;             // -log2(e) / (2 sigma^2): e^{-d^2/(2 sigma^2)} = 2^{k2 d^2}
   float c0, c1;         // sqrt(Omega) times the unit-norm prefactors of p_0 and p_m
 };
 

@@ -252,7 +252,7 @@ struct Engine {
     d.hx = (float)(P.L[0] / P.g.n1);
     d.hy = (float)(P.L[1] / P.g.n2);
     d.r2 = (float)(P.rs_radius * P.rs_radius);
-    d.inv2s2 = (float)(0.5 / (P.beta_sigma * P.beta_sigma));
+    d.k2 = (float)(-1.4426950408889634 * 0.5 / (P.beta_sigma * P.beta_sigma));
     const double so = std::sqrt(P.L[0] * P.L[1] * P.L[2]);
     d.c0 = (float)(so * std::pow(3.14159265358979323846, -0.75) * std::pow(P.beta_sigma, -1.5));
     d.c1 = (float)(so * std::sqrt(2.0) * std::pow(3.14159265358979323846, -0.75) * std::pow(P.beta_sigma, -2.5));

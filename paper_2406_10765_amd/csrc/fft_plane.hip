@@ -348,10 +348,11 @@ __device__ __forceinline__ RsLaneEnt rs_empty() {
 
 struct RsEntry {
   float tx, ty, dz, dz2;
+  float bx, by;   // x0 hx - tx and y0 hy - ty: the displacement of the range's first column and row
   int x0, nx, y0, ny;
   unsigned mask;  // bit k: columns 8k .. 8k+7 meet x0 .. x0+nx-1 (mod 128)
 };
-__device__ __forceinline__ RsEntry rs_entry(const RsLaneEnt& l, int k) {
+__device__ __forceinline__ RsEntry rs_entry(const RsDesc& d, const RsLaneEnt& l, int k) {
   RsEntry e;
   e.tx = rs_lane(l.tx, k);
   e.ty = rs_lane(l.ty, k);
@@ -365,6 +366,8 @@ __device__ __forceinline__ RsEntry rs_entry(const RsLaneEnt& l, int k) {
   const int xs = e.x0 & 127, b0 = xs >> 3, nblk = ((xs + e.nx - 1) >> 3) - b0 + 1;
   const unsigned m = nblk >= 16 ? 0xffffu : ((1u << nblk) - 1u);
   e.mask = e.nx <= 0 ? 0u : ((m << b0) | (m >> (16 - b0))) & 0xffffu;
+  e.bx = fmaf((float)e.x0, d.hx, -e.tx);
+  e.by = fmaf((float)e.y0, d.hy, -e.ty);
   return e;
 }
 
@@ -378,27 +381,27 @@ __device__ __forceinline__ RsRow rs_row(const RsDesc& d, const RsEntry& e, int y
   RsRow w;
   const int oy = (y - e.y0) & 127;
   w.ok = oy < e.ny;
-  w.dy = fmaf((float)(e.y0 + oy), d.hy, -e.ty);
+  w.dy = fmaf((float)oy, d.hy, e.by);
   w.s = fmaf(w.dy, w.dy, e.dz2);
-  w.gyz = __expf(-w.s * d.inv2s2);
+  w.gyz = __builtin_amdgcn_exp2f(w.s * d.k2);
   return w;
 }
-// Column part of column x (0 .. 127): whether it is in the entry's columns, dx, dx^2, e^{-dx^2/(2 s^2)}.
+// Column part of column x (0 .. 127): dx, dx^2 and e^{-dx^2/(2 s^2)}.  A column outside the entry's
+// range needs no test of its own: its dx exceeds the disc radius of the enlarged range radius, so
+// the ball test below rejects it (by a margin of 2e-4 of R^2, far above FP32 rounding).
 struct RsCol {
-  bool ok;
   float dx, dx2, gx;
 };
 __device__ __forceinline__ RsCol rs_colpart(const RsDesc& d, const RsEntry& e, int x) {
   RsCol c;
   const int ox = (x - e.x0) & 127;
-  c.ok = ox < e.nx;
-  c.dx = fmaf((float)(e.x0 + ox), d.hx, -e.tx);
+  c.dx = fmaf((float)ox, d.hx, e.bx);
   c.dx2 = c.dx * c.dx;
-  c.gx = __expf(-c.dx2 * d.inv2s2);
+  c.gx = __builtin_amdgcn_exp2f(c.dx2 * d.k2);
   return c;
 }
 __device__ __forceinline__ bool rs_in(const RsDesc& d, const RsCol& c, const RsRow& w) {
-  return c.ok && w.ok && c.dx2 + w.s <= d.r2;
+  return w.ok && c.dx2 + w.s <= d.r2;
 }
 
 __device__ __forceinline__ float rs_wave_sum(float v) {
@@ -427,7 +430,7 @@ __device__ __forceinline__ void rs_add_regs(float2 (&r)[16], const RsDesc& rd, i
     }
     const int cnt = min(64, e1 - base);
     for (int k = 0; k < cnt; ++k) {
-      const RsEntry e = rs_entry(le, k);
+      const RsEntry e = rs_entry(rd, le, k);
       const RsRow rw = rs_row(rd, e, y);
       const float c0 = rd.c0, c1 = rd.c1;
       const float ax = fmaf(c0, rs_lane(q0.x, k), c1 * e.dz * rs_lane(q3.x, k));
@@ -922,14 +925,14 @@ __global__ __launch_bounds__(1024) void k_rs_proj128(const float2* __restrict__ 
     const int cnt = min(64, (e1 - base + NW - 1) / NW);
     for (int k = 0; k < cnt; ++k) {
       const int e = base + NW * k;
-      const RsEntry en = rs_entry(le, k);
+      const RsEntry en = rs_entry(rd, le, k);
       float s0x = 0.f, s0y = 0.f, sxx = 0.f, sxy = 0.f, syx = 0.f, syy = 0.f;
       const int lxs = rs_lxs(en.nx), lx = 1 << lxs, rps = 64 >> lxs;
       const int lr = lane >> lxs, lc = lane & (lx - 1);
       for (int xc = 0; xc < en.nx; xc += lx) {
         const int x = (en.x0 + xc + lc) & (N - 1);
         const RsCol cc = rs_colpart(rd, en, x);
-        const bool colok = cc.ok && xc + lc < en.nx;
+        const bool colok = xc + lc < en.nx;  // lanes past the range would alias its first columns
         for (int q = lr; q < en.ny; q += rps) {
           const int y = (en.y0 + q) & (N - 1);
           const RsRow rw = rs_row(rd, en, y);
