@@ -318,9 +318,15 @@ struct Engine {
         const unsigned int* hi = reinterpret_cast<const unsigned int*>(C);
         const unsigned int* ch = hi + (size_t)c0 * n;
         const unsigned int* cl = hi + (size_t)n * n + (size_t)c0 * n;
-        if (beta_planes() && planes_of(A, n))
+        if ((beta_planes() || P.rspace) && planes_of(A, n))
           return launch_gemm_nn_bf16x3_planes(yp_hi(), yp_lo(), P.ldw, ch, cl, n, P.npw, w, n, out, ldo, e,
                                               h->stream);
+        // W = H Y of the unblocked step keeps its planes beside those of Y for the Gram product
+        if (gram_planes() && A && static_cast<const void*>(A) == h->wp_src && h->yp_src && n <= h->yp_n) {
+          const size_t pc = (size_t)P.ldw * h->yp_n;
+          return launch_gemm_nn_bf16x3_planes(yp_hi() + pc, yp_lo() + pc, P.ldw, ch, cl, n, P.npw, w, n, out, ldo,
+                                              e, h->stream);
+        }
         return launch_gemm_nn_bf16x3_bplanes(A, lda, ch, cl, n, P.npw, w, n, out, ldo, e, h->stream);
       }
     }
@@ -758,6 +764,7 @@ struct Engine {
         PW_TIMED(PW_PH_OTHER, launch_split_planes(Y, ldy, P.npw, nb, yp_hi(), yp_lo(), P.ldw, h->stream));
         PW_TIMED(PW_PH_OTHER, launch_split_planes(W, ldw, P.npw, nb, yp_hi() + pc, yp_lo() + pc, P.ldw, h->stream));
         set_planes(Y, nb);
+        h->wp_src = W;
         PW_TIMED(PW_PH_GRAM, launch_gemm_cn_bf16x3_planes(yp_hi(), yp_lo(), P.ldw, yp_hi(), yp_lo(), P.ldw, nb,
                                                           2 * nb, P.npw, P.nsplit_gram, parts, h->stream, 4, nb));
         return dense_solve(nb, P.nsplit_gram, 0.0, true);
