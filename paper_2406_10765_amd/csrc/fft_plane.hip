@@ -310,14 +310,12 @@ __global__ __launch_bounds__(NT) void k_plane_n(cplx<T>* __restrict__ SB, const 
 // the ball cuts from the plane; a point lies in the ball when dx^2 + (dy^2 + dz^2) <= R^2.  The
 // Gaussian factors as e^{-dx^2/(2 s^2)} e^{-(dy^2 + dz^2)/(2 s^2)}.  Both passes evaluate points
 // through rs_colpart / rs_row / rs_in, so they see the same points and the same values.
-//  * The projection pass holds the plane in LDS (row y in natural x order at word x ^ rs_swz(y)) and
+//  * The projection pass holds the plane in LDS (row y in natural x order, word y * 128 + x) and
 //    gives each wave whole (atom, plane) entries: its lanes cover the disc, 16, 32 or 64 columns
 //    at a time, and one reduction across the wave ends each entry.
 //  * The pass of V(r) adds D P on the x pass itself, where lane (l, t) of wave w holds the 16 values
 //    of row y = 8w + l at x = t + 8k in registers: the wave walks the entries of its 8-row band and
 //    visits only the 8-column blocks that an entry's columns meet (a wave-uniform mask).
-__device__ __forceinline__ int rs_swz(int y) { return (y & 15) << 3; }
-
 // value of lane k of v (k uniform over the wave)
 __device__ __forceinline__ float rs_lane(float v, int k) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
@@ -879,9 +877,9 @@ __device__ __forceinline__ void xinv_row_store(float2* plane, const float2* tw, 
   for (int n2 = 0; n2 < B; ++n2) r2[n2] = row[B * t + (n2 ^ t ^ py)];
   SmallDft<float, B, +1>::run(r2);  // r2[k2] = psi at x = t + 8 k2
   wave_sync();
-  const int sw = rs_swz(y);
+  // natural x order (no swizzle): the projection loop then addresses a point as y * 128 + x
 #pragma unroll
-  for (int k2 = 0; k2 < B; ++k2) row[(t + A * k2) ^ sw] = r2[k2];
+  for (int k2 = 0; k2 < B; ++k2) row[t + A * k2] = r2[k2];
 }
 
 // log2 of the lanes per row of an entry: 16, 32 or 64 columns at a time (64 / lx rows per step).
@@ -937,7 +935,7 @@ __global__ __launch_bounds__(1024) void k_rs_proj128(const float2* __restrict__ 
           const int y = (en.y0 + q) & (N - 1);
           const RsRow rw = rs_row(rd, en, y);
           const float gg = (colok && rs_in(rd, cc, rw)) ? cc.gx * rw.gyz : 0.f;
-          const float2 v = plane[y * N + (x ^ rs_swz(y))];
+          const float2 v = plane[y * N + x];
           const float gxv = gg * cc.dx, gyv = gg * rw.dy;
           s0x = fmaf(gg, v.x, s0x);
           s0y = fmaf(gg, v.y, s0y);
