@@ -927,22 +927,47 @@ __global__ __launch_bounds__(1024) void k_rs_proj128(const float2* __restrict__ 
       float s0x = 0.f, s0y = 0.f, sxx = 0.f, sxy = 0.f, syx = 0.f, syy = 0.f;
       const int lxs = rs_lxs(en.nx), lx = 1 << lxs, rps = 64 >> lxs;
       const int lr = lane >> lxs, lc = lane & (lx - 1);
-      for (int xc = 0; xc < en.nx; xc += lx) {
-        const int x = (en.x0 + xc + lc) & (N - 1);
-        const RsCol cc = rs_colpart(rd, en, x);
-        const bool colok = xc + lc < en.nx;  // lanes past the range would alias its first columns
-        for (int q = lr; q < en.ny; q += rps) {
+      if (en.nx > 16 && en.nx <= 32) {
+        // 16 lanes per row, each with two columns 16 apart, four rows per step: one row factor
+        // serves two points
+        const int lr4 = lane >> 4, lc4 = lane & 15;
+        const int xa = (en.x0 + lc4) & (N - 1), xb = (en.x0 + lc4 + 16) & (N - 1);
+        const RsCol ca = rs_colpart(rd, en, xa), cb = rs_colpart(rd, en, xb);
+        const bool okb = lc4 + 16 < en.nx;  // the first column is always in the range
+        for (int q = lr4; q < en.ny; q += 4) {
           const int y = (en.y0 + q) & (N - 1);
           const RsRow rw = rs_row(rd, en, y);
-          const float gg = (colok && rs_in(rd, cc, rw)) ? cc.gx * rw.gyz : 0.f;
-          const float2 v = plane[y * N + x];
-          const float gxv = gg * cc.dx, gyv = gg * rw.dy;
-          s0x = fmaf(gg, v.x, s0x);
-          s0y = fmaf(gg, v.y, s0y);
-          sxx = fmaf(gxv, v.x, sxx);
-          sxy = fmaf(gxv, v.y, sxy);
-          syx = fmaf(gyv, v.x, syx);
-          syy = fmaf(gyv, v.y, syy);
+          const float ga = rs_in(rd, ca, rw) ? ca.gx * rw.gyz : 0.f;
+          const float gb = (okb && rs_in(rd, cb, rw)) ? cb.gx * rw.gyz : 0.f;
+          const float2 va = plane[y * N + xa], vb = plane[y * N + xb];
+          const float gxa = ga * ca.dx, gxb = gb * cb.dx;
+          s0x = fmaf(ga, va.x, fmaf(gb, vb.x, s0x));
+          s0y = fmaf(ga, va.y, fmaf(gb, vb.y, s0y));
+          sxx = fmaf(gxa, va.x, fmaf(gxb, vb.x, sxx));
+          sxy = fmaf(gxa, va.y, fmaf(gxb, vb.y, sxy));
+          // sum of g psi over the row's two points, times dy for p_y
+          const float tx = fmaf(ga, va.x, gb * vb.x), ty = fmaf(ga, va.y, gb * vb.y);
+          syx = fmaf(rw.dy, tx, syx);
+          syy = fmaf(rw.dy, ty, syy);
+        }
+      } else {
+        for (int xc = 0; xc < en.nx; xc += lx) {
+          const int x = (en.x0 + xc + lc) & (N - 1);
+          const RsCol cc = rs_colpart(rd, en, x);
+          const bool colok = xc + lc < en.nx;  // lanes past the range would alias its first columns
+          for (int q = lr; q < en.ny; q += rps) {
+            const int y = (en.y0 + q) & (N - 1);
+            const RsRow rw = rs_row(rd, en, y);
+            const float gg = (colok && rs_in(rd, cc, rw)) ? cc.gx * rw.gyz : 0.f;
+            const float2 v = plane[y * N + x];
+            const float gxv = gg * cc.dx, gyv = gg * rw.dy;
+            s0x = fmaf(gg, v.x, s0x);
+            s0y = fmaf(gg, v.y, s0y);
+            sxx = fmaf(gxv, v.x, sxx);
+            sxy = fmaf(gxv, v.y, sxy);
+            syx = fmaf(gyv, v.x, syx);
+            syy = fmaf(gyv, v.y, syy);
+          }
         }
       }
       s0x = rs_wave_sum(s0x);
