@@ -47,12 +47,15 @@ struct Stick {
 };
 
 // Real-space projectors: one (atom, z plane) pair, or (atom, z plane, 8-row band) triple: the plane's
-// z displacement from the atom (bohr), and unwrapped grid ranges that hold every point of the disc
-// the ball cuts from the plane: columns x0 .. x0+nx-1, rows y0 .. y0+ny-1.
+// z displacement from the atom (bohr); unwrapped grid ranges that hold every point of the disc the
+// ball cuts from the plane: columns x0 .. x0+nx-1, rows y0 .. y0+ny-1; the displacements of the
+// first column and row from the atom, bx = x0 hx - x_a and by = y0 hy - y_a (bohr); and the mask of
+// the 8-column blocks (columns 8k .. 8k+7 of the plane) that the columns meet.
 struct RsEnt {
   int atom;
-  float dz;
+  float dz, bx, by;
   short x0, nx, y0, ny;
+  unsigned short mask, pad;
 };
 
 // Tables of the real-space projectors on a 128 x 128 x n3 grid (PW_FLAG_RSPACE_KB).

@@ -324,48 +324,45 @@ __device__ __forceinline__ int rs_lane(int v, int k) { return __builtin_amdgcn_r
 
 // One entry's data, loaded by lane k of the wave, then read by the whole wave with rs_entry.
 struct RsLaneEnt {
-  float tx, ty, dz;
+  float dz, bx, by;
   int xr, yr;  // x0 | nx << 16 and y0 | ny << 16 (x0, y0 as 16-bit two's complement)
+  int mask;
 };
-__device__ __forceinline__ RsLaneEnt rs_load(const RsDesc& d, const RsEnt& en) {
-  const float4 t = d.atoms[en.atom];
+__device__ __forceinline__ RsLaneEnt rs_load(const RsEnt& en) {
   RsLaneEnt l;
-  l.tx = t.x;
-  l.ty = t.y;
   l.dz = en.dz;
+  l.bx = en.bx;
+  l.by = en.by;
   l.xr = (int)(unsigned short)en.x0 | ((int)en.nx << 16);
   l.yr = (int)(unsigned short)en.y0 | ((int)en.ny << 16);
+  l.mask = en.mask;
   return l;
 }
 __device__ __forceinline__ RsLaneEnt rs_empty() {
   RsLaneEnt l;
-  l.tx = l.ty = l.dz = 0.f;
+  l.dz = l.bx = l.by = 0.f;
   l.xr = l.yr = 0;
+  l.mask = 0;
   return l;
 }
 
 struct RsEntry {
-  float tx, ty, dz, dz2;
-  float bx, by;   // x0 hx - tx and y0 hy - ty: the displacement of the range's first column and row
+  float dz, dz2, bx, by;
   int x0, nx, y0, ny;
   unsigned mask;  // bit k: columns 8k .. 8k+7 meet x0 .. x0+nx-1 (mod 128)
 };
-__device__ __forceinline__ RsEntry rs_entry(const RsDesc& d, const RsLaneEnt& l, int k) {
+__device__ __forceinline__ RsEntry rs_entry(const RsLaneEnt& l, int k) {
   RsEntry e;
-  e.tx = rs_lane(l.tx, k);
-  e.ty = rs_lane(l.ty, k);
   e.dz = rs_lane(l.dz, k);
   e.dz2 = e.dz * e.dz;
+  e.bx = rs_lane(l.bx, k);
+  e.by = rs_lane(l.by, k);
   const int xr = rs_lane(l.xr, k), yr = rs_lane(l.yr, k);
   e.x0 = (int)(short)(xr & 0xffff);
   e.nx = xr >> 16;
   e.y0 = (int)(short)(yr & 0xffff);
   e.ny = yr >> 16;
-  const int xs = e.x0 & 127, b0 = xs >> 3, nblk = ((xs + e.nx - 1) >> 3) - b0 + 1;
-  const unsigned m = nblk >= 16 ? 0xffffu : ((1u << nblk) - 1u);
-  e.mask = e.nx <= 0 ? 0u : ((m << b0) | (m >> (16 - b0))) & 0xffffu;
-  e.bx = fmaf((float)e.x0, d.hx, -e.tx);
-  e.by = fmaf((float)e.y0, d.hy, -e.ty);
+  e.mask = (unsigned)rs_lane(l.mask, k);
   return e;
 }
 
@@ -419,7 +416,7 @@ __device__ __forceinline__ void rs_add_regs(float2 (&r)[16], const RsDesc& rd, i
     float2 q0 = make_float2(0.f, 0.f), q1 = q0, q2 = q0, q3 = q0;
     if (base + lane < e1) {
       const RsEnt en = rd.bent[base + lane];
-      le = rs_load(rd, en);
+      le = rs_load(en);
       const float2* c = dp + 4 * en.atom;
       q0 = c[0];
       q1 = c[1];
@@ -428,14 +425,14 @@ __device__ __forceinline__ void rs_add_regs(float2 (&r)[16], const RsDesc& rd, i
     }
     const int cnt = min(64, e1 - base);
     for (int k = 0; k < cnt; ++k) {
-      const RsEntry e = rs_entry(rd, le, k);
+      const RsEntry e = rs_entry(le, k);
       const RsRow rw = rs_row(rd, e, y);
-      const float c0 = rd.c0, c1 = rd.c1;
-      const float ax = fmaf(c0, rs_lane(q0.x, k), c1 * e.dz * rs_lane(q3.x, k));
-      const float ay = fmaf(c0, rs_lane(q0.y, k), c1 * e.dz * rs_lane(q3.y, k));
-      const float w0x = rw.gyz * fmaf(rw.dy, c1 * rs_lane(q2.x, k), ax);
-      const float w0y = rw.gyz * fmaf(rw.dy, c1 * rs_lane(q2.y, k), ay);
-      const float w1x = rw.gyz * c1 * rs_lane(q1.x, k), w1y = rw.gyz * c1 * rs_lane(q1.y, k);
+      // dp holds (c0 D P_0, c1 D P_x, c1 D P_y, c1 D P_z)
+      const float ax = fmaf(e.dz, rs_lane(q3.x, k), rs_lane(q0.x, k));
+      const float ay = fmaf(e.dz, rs_lane(q3.y, k), rs_lane(q0.y, k));
+      const float w0x = rw.gyz * fmaf(rw.dy, rs_lane(q2.x, k), ax);
+      const float w0y = rw.gyz * fmaf(rw.dy, rs_lane(q2.y, k), ay);
+      const float w1x = rw.gyz * rs_lane(q1.x, k), w1y = rw.gyz * rs_lane(q1.y, k);
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk) {
         if (e.mask & (1u << kk)) {
@@ -919,11 +916,11 @@ __global__ __launch_bounds__(1024) void k_rs_proj128(const float2* __restrict__ 
   // this wave's entries e0 + wv + 16 k, their data loaded one entry per lane
   for (int base = e0 + wv; base < e1; base += NW * 64) {
     RsLaneEnt le = rs_empty();
-    if (base + NW * lane < e1) le = rs_load(rd, rd.zent[base + NW * lane]);
+    if (base + NW * lane < e1) le = rs_load(rd.zent[base + NW * lane]);
     const int cnt = min(64, (e1 - base + NW - 1) / NW);
     for (int k = 0; k < cnt; ++k) {
       const int e = base + NW * k;
-      const RsEntry en = rs_entry(rd, le, k);
+      const RsEntry en = rs_entry(le, k);
       float s0x = 0.f, s0y = 0.f, sxx = 0.f, sxy = 0.f, syx = 0.f, syy = 0.f;
       const int lxs = rs_lxs(en.nx), lx = 1 << lxs, rps = 64 >> lxs;
       const int lr = lane >> lxs, lc = lane & (lx - 1);
@@ -986,7 +983,8 @@ __global__ __launch_bounds__(1024) void k_rs_proj128(const float2* __restrict__ 
   }
 }
 
-// dp[b nproj + 4a + m] = dscale[m] inv_nr sum over atom a's entries (plane order) of part, in FP64.
+// dp[b nproj + 4a + m] = c_m dscale[m] inv_nr sum over atom a's entries (plane order) of part, in FP64
+// (c_0 = c0, c_m = c1: the prefactor the addition would otherwise apply per point).
 __global__ void k_rs_reduce(const float2* __restrict__ part, RsDesc rd, int nbt, const double* __restrict__ dscale,
                             double inv_nr, float2* __restrict__ dp, int nproj) {
   PW_GRID_STRIDE(idx, (long)nbt * rd.natoms) {
@@ -1006,7 +1004,8 @@ __global__ void k_rs_reduce(const float2* __restrict__ part, RsDesc rd, int nbt,
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const double f = dscale[m] * inv_nr;
+      // D P times the projector prefactor, as the addition uses it
+      const double f = dscale[m] * inv_nr * (m == 0 ? (double)rd.c0 : (double)rd.c1);
       dp[(long)j * nproj + 4 * a + m] = make_float2((float)(s[2 * m] * f), (float)(s[2 * m + 1] * f));
     }
   }

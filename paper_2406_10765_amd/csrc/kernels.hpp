@@ -55,7 +55,8 @@ hipError_t launch_rs_proj128(const float2* SB, const int* colstart, const GridDe
 // written: out[b ldo + i] = alpha ((kin[i] - c) Y[b ldy + i] + z) - beta Yp[b ldp + i].
 hipError_t launch_sticks_fwd_upd(const float2* SB, float2* out, long ldo, int nbatch, const Stick* st,
                                  const GridDesc& g, const float2* tw3, const StickUpd& u, hipStream_t s);
-// dp[b nproj + 4a + m] = dscale[m] inv_nr (sum over atom a's entries of part), b < nbt.
+// dp[b nproj + 4a + m] = c_m dscale[m] inv_nr (sum over atom a's entries of part), b < nbt, with
+// c_0 = rd.c0 and c_m = rd.c1 for m = 1, 2, 3 (the form the addition of D P reads).
 hipError_t launch_rs_reduce(const float2* part, const RsDesc& rd, int nbt, const double* dscale, double inv_nr,
                             float2* dp, int nproj, hipStream_t s);
 // The plane pass of k_plane128 with sum_a p_m(r - tau_a) dp[b nproj + 4a + m] added to V psi at the

@@ -76,7 +76,9 @@ static void build_rspace_tables(Plan& P) {
       const int x0 = (int)std::ceil((t[0] - rho) / h[0]), x1 = (int)std::floor((t[0] + rho) / h[0]);
       const int y0 = (int)std::ceil((t[1] - rho) / h[1]), y1 = (int)std::floor((t[1] + rho) / h[1]);
       if (x1 < x0 || y1 < y0) continue;
-      const RsEnt e{a, dz, (short)x0, (short)(x1 - x0 + 1), (short)y0, (short)(y1 - y0 + 1)};
+      RsEnt e{a, dz, (float)(x0 * h[0] - t[0]), (float)(y0 * h[1] - t[1]),
+              (short)x0, (short)(x1 - x0 + 1), (short)y0, (short)(y1 - y0 + 1), 0, 0};
+      for (int ix = x0; ix <= x1; ++ix) e.mask |= (unsigned short)(1u << ((((ix % 128) + 128) % 128) >> 3));
       per_z[z].push_back(e);
       std::vector<char> hit(nbr, 0);
       for (int iy = y0; iy <= y1; ++iy) hit[(((iy % 128) + 128) % 128) / 8] = 1;
