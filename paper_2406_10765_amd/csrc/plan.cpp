@@ -86,6 +86,23 @@ static void build_rspace_tables(Plan& P) {
         if (hit[w]) per_band[(size_t)z * nbr + w].push_back(e);
     }
   }
+  // Balance the projection pass: wave w of a plane's workgroup takes positions w, w + 16, w + 32, ...
+  // of the plane's list, so the entries are sorted by size (columns x rows) and dealt to the waves
+  // in snake order (largest to waves 0 .. 15, the next 16 to waves 15 .. 0, ...).
+  for (int z = 0; z < n3; ++z) {
+    std::vector<RsEnt>& v = per_z[z];
+    std::stable_sort(v.begin(), v.end(), [](const RsEnt& a, const RsEnt& b) {
+      return (int)a.nx * a.ny > (int)b.nx * b.ny;
+    });
+    std::vector<RsEnt> dealt(v.size());
+    const size_t full = v.size() / 16 * 16;  // entries in whole rounds; the rest go in order
+    for (size_t r = 0; r < v.size(); ++r) {
+      const size_t k = r / 16, i = r % 16;
+      const size_t pos = r < full ? 16 * k + ((k % 2 == 0) ? i : 15 - i) : r;
+      dealt[pos] = v[r];
+    }
+    v.swap(dealt);
+  }
   P.rs_zoff.assign(n3 + 1, 0);
   P.rs_zent.clear();
   std::vector<std::vector<std::pair<int, int>>> of_atom(P.natoms);  // (unwrapped order key, zent index)
