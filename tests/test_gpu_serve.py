@@ -20,8 +20,9 @@ def say(*a):
 
 def requests():
     out = []
+    # Si8 and Si16 at each cutoff, then a Si64 and a Si216 cell (the latter on the 81-point grid)
     for i, (nc, ec) in enumerate([((1, 1, 1), 10.0), ((1, 1, 2), 10.0), ((1, 1, 1), 15.0), ((1, 1, 1), 20.0),
-                                  ((1, 1, 2), 15.0), ((1, 1, 1), 10.0)]):
+                                  ((1, 1, 2), 15.0), ((1, 1, 1), 10.0), ((2, 2, 2), 10.0), ((3, 3, 3), 15.0)]):
         out.append((synth.silicon_cell(nc, ec, disp_seed=synth.SEED_REQUEST + i), synth.SEED_REQUEST + i))
     return out
 
@@ -45,6 +46,7 @@ def test_alone_equals_mix_and_dense():
     import torch
     assert torch.cuda.is_available()
     reqs = requests()
+    say("cells", [(c.natoms, c.ecut, c.nbands) for c, _ in reqs])
     srv = pw.Server(8 << 30, max_slots=4)
     mix = run(srv, reqs)
     srv.close()
@@ -54,6 +56,7 @@ def test_alone_equals_mix_and_dense():
     for q in reqs:
         alone += run(srv1, [q])
     srv1.close()
+    say("alone steps", [r["steps"] for r in alone])
     for a, b in zip(mix, alone):
         assert a["status"] == pw.PW_OK and b["status"] == pw.PW_OK
         assert np.array_equal(a["eig"], b["eig"])
