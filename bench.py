@@ -482,6 +482,44 @@ def serving_leg(n, rate, slots, flags, degree):
     }
 
 
+def serving_solve_phases(flags, degree):
+    """One request of each serving cell and cutoff solved alone on the device (pw_solve, as the
+    request loop runs it: seeded block, Lanczos bound, a degree-0 step, then degree-m steps to
+    tol 1e-4 on the occupied bands): wall time of an untimed solve after a warm-up one, and the
+    per-phase times (HIP events, phases serialised) of a third."""
+    import torch
+
+    from paper_2406_10765_amd import pw, synth
+
+    out = {}
+    for name, nc in synth.SERVING_CELLS.items():
+        for ec in (10.0, 15.0, 20.0):
+            cell = synth.silicon_cell(nc, ec, disp_seed=synth.SEED_REQUEST)
+            h = pw.Handle(cell, pw.PW_MIXED, flags=flags)
+            try:
+                npw = h.info.npw
+                walls = []
+                for rep in range(3):
+                    X = h.random_block(cell.nbands, synth.SEED_REQUEST)
+                    if rep == 2:
+                        h.set_timing(True)
+                        h.reset_stats()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, _, steps, ok = h.solve(X, cell.nocc, 1e-4, degree=degree)
+                    torch.cuda.synchronize()
+                    walls.append(time.perf_counter() - t0)
+                st = h.stats()
+            finally:
+                h.close()
+            key = "%s_ecut%d" % (name, int(ec))
+            out[key] = {"nbands": cell.nbands, "npw": int(npw), "steps": int(steps), "converged": bool(ok),
+                        "wall_ms": round(1e3 * walls[1], 2), "timed_ms": round(1e3 * walls[2], 2),
+                        "phases_ms": {k: round(v["ms"], 2) for k, v in st.items() if v["launches"]}}
+            log(f"serving solve {key}: {steps} steps, {1e3 * walls[1]:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -505,6 +543,8 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=20.0)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--serving-solve-phases", action="store_true",
+                    help="per-phase times of one request of each serving cell and cutoff, solved alone, and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--accuracy-workload", default="si64",
@@ -527,6 +567,10 @@ def main():
     from paper_2406_10765_amd import pw, synth
 
     torch.cuda.set_device(0)
+    if args.serving_solve_phases:
+        mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
+        print(json.dumps({"serving_solve_phases": serving_solve_phases(mflags, args.degree)}), flush=True)
+        return
     if args.serving_only:
         mflags = DEFAULT_MIXED_FLAGS if args.flags is None else args.flags
         print(json.dumps({"serving": serving_leg(args.serving_requests, args.serving_rate, args.serving_slots,
