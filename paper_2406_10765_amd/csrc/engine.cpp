@@ -804,7 +804,7 @@ struct Engine {
     const rocblas_double_complex one(1.0, 0.0);
     h->tbegin();
     double* dS = h->at<double>(P.lay.ework);
-    double* piv_d = h->at<double>(P.lay.scal) + 3;  // [0, 2) belong to the Lanczos bound
+    double* piv_d = h->at<double>(P.lay.scal) + 3;  // [8, 8 + 2 kLanczosChunk) hold the Lanczos pairs
     if (min_pivot > 0.0) PW_HIP(launch_diag_copy(S, nb, nb, dS, h->stream));
     rocblas_status rs = rocsolver_zpotrf(h->blas, rocblas_fill_lower, nb, Sz, nb, info_d);
     if (rs != rocblas_status_success)
@@ -1100,7 +1100,7 @@ struct Engine {
     cplx<T>* V0 = h->at<cplx<T>>(P.lay.lanc);
     cplx<T>* V1 = V0 + P.ldw;
     cplx<T>* Wv = V1 + P.ldw;
-    double* sc = h->at<double>(P.lay.scal);
+    double* lab = h->at<double>(P.lay.scal) + 8;  // (alpha, beta) of each step of a chunk
     // seeded start vector (splitmix64 + Box-Muller), normalised on the host
     std::vector<cplx<T>> v(n);
     uint64_t x = seed ? seed : 0x9e3779b97f4a7c15ull;
@@ -1125,22 +1125,36 @@ struct Engine {
     for (int i = 0; i < n; ++i) v[i] = mk<T>((T)(tmp[2 * i] * nrm), (T)(tmp[2 * i + 1] * nrm));
     PW_HIP(hipMemcpyAsync(V1, v.data(), sizeof(cplx<T>) * n, hipMemcpyHostToDevice, h->stream));
     PW_HIP(launch_fill_zero<T>(V0, P.ldw, h->stream));
+    // The recurrence runs on the device, each step reading the previous beta there; the host reads
+    // the (alpha, beta) pairs once per chunk of kLanczosChunk steps.  A beta below 1e-12 ends the
+    // recurrence: the steps after it in its chunk are discarded.
     std::vector<double> al, be;
     double bprev = 0.0;
-    for (int it = 0; it < steps && it < n; ++it) {
-      pw_status s = apply_h(V1, Wv, 1, (int)P.ldw, P.nbb);
-      if (s != PW_OK) return s;
-      PW_HIP(launch_lanczos_step<T>(Wv, V1, V0, bprev, n, sc, h->stream));
-      double hs[2];
-      PW_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
+    const int total = std::min(steps, n);
+    bool ended = false;
+    for (int c0 = 0; c0 < total && !ended; c0 += kLanczosChunk) {
+      const int c1 = std::min(total, c0 + kLanczosChunk);
+      for (int it = c0; it < c1; ++it) {
+        pw_status s = apply_h(V1, Wv, 1, (int)P.ldw, P.nbb);
+        if (s != PW_OK) return s;
+        double* ab = lab + 2 * (it - c0);
+        PW_HIP(launch_lanczos_step<T>(Wv, V1, V0, bprev, it > c0 ? ab - 1 : nullptr, n, ab, h->stream));
+        // V0 <- V1, V1 <- W / beta
+        PW_HIP(launch_copy_cols<T>(V1, P.ldw, V0, P.ldw, n, 1, h->stream));
+        PW_HIP(launch_scale_copy_inv<T>(Wv, V1, ab + 1, n, h->stream));
+      }
+      std::vector<double> hs(2 * (size_t)(c1 - c0));
+      PW_HIP(hipMemcpyAsync(hs.data(), lab, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, h->stream));
       PW_HIP(hipStreamSynchronize(h->stream));
-      al.push_back(hs[0]);
-      be.push_back(hs[1]);
-      if (hs[1] < 1e-12) break;
-      // V0 <- V1, V1 <- W / beta
-      PW_HIP(launch_copy_cols<T>(V1, P.ldw, V0, P.ldw, n, 1, h->stream));
-      PW_HIP(launch_scale_copy<T>(Wv, V1, 1.0 / hs[1], n, h->stream));
-      bprev = hs[1];
+      for (int i = 0; i < c1 - c0; ++i) {
+        al.push_back(hs[2 * i]);
+        be.push_back(hs[2 * i + 1]);
+        if (hs[2 * i + 1] < 1e-12) {
+          ended = true;
+          break;
+        }
+      }
+      bprev = be.back();
     }
     // largest eigenvalue of the tridiagonal matrix by bisection (Sturm count)
     const int k = (int)al.size();

@@ -271,11 +271,13 @@ hipError_t launch_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, 
                         int cols, double* resid, hipStream_t s);
 
 // Lanczos: alpha = Re<v, w>; w <- w - alpha v - beta_prev v_prev; beta = ||w||.  sc[0..1] = alpha, beta.
+// beta_prev is read from beta_prev_dev when that is not null (the previous step's sc[1]).
 template <typename T>
-hipError_t launch_lanczos_step(cplx<T>* w, const cplx<T>* v, const cplx<T>* vp, double beta_prev, int n, double* sc,
-                               hipStream_t s);
+hipError_t launch_lanczos_step(cplx<T>* w, const cplx<T>* v, const cplx<T>* vp, double beta_prev,
+                               const double* beta_prev_dev, int n, double* sc, hipStream_t s);
+// out = in / *beta (zero when *beta < 1e-12, where the recurrence ends)
 template <typename T>
-hipError_t launch_scale_copy(const cplx<T>* in, cplx<T>* out, double scale, int n, hipStream_t s);
+hipError_t launch_scale_copy_inv(const cplx<T>* in, cplx<T>* out, const double* beta, int n, hipStream_t s);
 // Seeded random block (see pw_random_block) and per-column scaling by 1 / norm.
 template <typename T>
 hipError_t launch_random_block(cplx<T>* X, long ld, int npw, int nb, const T* kin, unsigned long long seed,

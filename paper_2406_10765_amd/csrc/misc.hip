@@ -267,10 +267,12 @@ __global__ __launch_bounds__(256) void k_resid(const cplx<T>* __restrict__ W, lo
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_lanczos(cplx<T>* __restrict__ w, const cplx<T>* __restrict__ v,
-                                                  const cplx<T>* __restrict__ vp, double bprev, int n,
+                                                  const cplx<T>* __restrict__ vp, double bprev_h,
+                                                  const double* __restrict__ bprev_d, int n,
                                                   double* __restrict__ sc) {
   __shared__ double red[16];
   __shared__ double alpha_s;
+  const double bprev = bprev_d ? *bprev_d : bprev_h;
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) s += (double)v[i].x * w[i].x + (double)v[i].y * w[i].y;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
@@ -303,21 +305,26 @@ __global__ __launch_bounds__(1024) void k_lanczos(cplx<T>* __restrict__ w, const
   }
 }
 
+// out = in / beta with beta read from the device.  A beta below 1e-12 ends the recurrence on the
+// host, which discards the later steps; the vector is then zeroed so that they stay finite.
 template <typename T>
-__global__ void k_scale_copy(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, double scale, int n) {
+__global__ void k_scale_copy_inv(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                 const double* __restrict__ beta, int n) {
+  const double b = *beta;
+  const double scale = b < 1e-12 ? 0.0 : 1.0 / b;
   PW_GRID_STRIDE(i, (long)n) out[i] = mk<T>((T)(in[i].x * scale), (T)(in[i].y * scale));
 }
 
 template <typename T>
-hipError_t launch_lanczos_step(cplx<T>* w, const cplx<T>* v, const cplx<T>* vp, double beta_prev, int n, double* sc,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_lanczos<T>, dim3(1), dim3(1024), 0, s, w, v, vp, beta_prev, n, sc);
+hipError_t launch_lanczos_step(cplx<T>* w, const cplx<T>* v, const cplx<T>* vp, double beta_prev,
+                               const double* beta_prev_dev, int n, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos<T>, dim3(1), dim3(1024), 0, s, w, v, vp, beta_prev, beta_prev_dev, n, sc);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_scale_copy(const cplx<T>* in, cplx<T>* out, double scale, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_copy<T>, dim3(stride_blocks(n)), dim3(256), 0, s, in, out, scale, n);
+hipError_t launch_scale_copy_inv(const cplx<T>* in, cplx<T>* out, const double* beta, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy_inv<T>, dim3(stride_blocks(n)), dim3(256), 0, s, in, out, beta, n);
   return hipGetLastError();
 }
 
@@ -563,9 +570,9 @@ hipError_t launch_resid(const cplx<T>* W, long ldw, const cplx<T>* X, long ldx, 
                                            cplx<T>*, long, hipStream_t);                                        \
   template hipError_t launch_convert_c64_to<T>(const double2*, long, cplx<T>*, long, int, int, hipStream_t);    \
   template hipError_t launch_copy_cols<T>(const cplx<T>*, long, cplx<T>*, long, int, int, hipStream_t);         \
-  template hipError_t launch_lanczos_step<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, double, int, double*, \
-                                             hipStream_t);                                                      \
-  template hipError_t launch_scale_copy<T>(const cplx<T>*, cplx<T>*, double, int, hipStream_t);                 \
+  template hipError_t launch_lanczos_step<T>(cplx<T>*, const cplx<T>*, const cplx<T>*, double, const double*, int, \
+                                             double*, hipStream_t);                                             \
+  template hipError_t launch_scale_copy_inv<T>(const cplx<T>*, cplx<T>*, const double*, int, hipStream_t);     \
   template hipError_t launch_random_block<T>(cplx<T>*, long, int, int, const T*, unsigned long long, hipStream_t); \
   template hipError_t launch_scale_cols_inv<T>(cplx<T>*, long, int, int, const double*, hipStream_t);          \
   template hipError_t launch_scale_cols_lam<T>(const double2*, long, cplx<T>*, long, int, const double*, double,  \

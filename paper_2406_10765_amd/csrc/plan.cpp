@@ -427,7 +427,7 @@ pw_status make_plan(const pw_cell_desc* d, size_t max_lds, Plan* p, std::string*
   L.ework = take(sizeof(double) * kb);
   L.resid = take(sizeof(double) * nb);
   L.info = take(sizeof(int) * 4);
-  L.scal = take(sizeof(double) * 8);
+  L.scal = take(sizeof(double) * (8 + 2 * kLanczosChunk));  // scalars, then the Lanczos (alpha, beta) pairs
   L.lanc = take(cb * P.ldw * 3);
   L.occ = take(sizeof(double) * nb);  // band weights of the charge density
   // LOBPCG basis Z = [X R P] and HZ = [HX HR HP] (3 nbands columns each)

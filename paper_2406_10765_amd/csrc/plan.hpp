@@ -12,6 +12,7 @@ namespace pw {
 
 constexpr size_t kArenaAlign = 256;
 constexpr size_t kDefaultMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kLanczosChunk = 64;  // Lanczos steps whose (alpha, beta) stay on the device between host reads
 
 struct ArenaLayout {
   size_t miller, sticks, colstart, kin, tw1, tw2, tw3, vr, frac, mmil, mamp, mpha, vg, dscale;

@@ -134,6 +134,20 @@ def test_step_parity_fp64_si8(si8_dense):
     assert bnd2[0] == e2[0] and bnd2[1] == e2[-1] and bnd2[2] == b
 
 
+@pytest.mark.parametrize("prec", [pw.PW_FP64, pw.PW_MIXED])
+def test_lanczos_bound_across_chunks(si8_dense, prec):
+    """The Lanczos recurrence keeps its coefficients on the device and the host reads them once per
+    chunk of 64 steps: runs that end inside, at and across chunk boundaries (up to the largest step
+    count the call accepts) bound the top of the dense spectrum and repeat exactly."""
+    cell, model, lam, V = si8_dense
+    h = pw.Handle(cell, prec)
+    for steps in (63, 64, 65, 130, 1000):
+        b = h.spectrum_bound(steps, 1)
+        say("lanczos steps", steps, "bound", b, "lam max", lam[-1])
+        assert b >= lam[-1]
+        assert h.spectrum_bound(steps, 1) == b
+
+
 @pytest.mark.parametrize("prec,tol,etol", [(pw.PW_FP64, 1e-7, 1e-8), (pw.PW_MIXED, 1e-4, 1e-5)])
 def test_solve_si8_matches_dense(si8_dense, prec, tol, etol):
     cell, model, lam, V = si8_dense
